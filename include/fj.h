@@ -1,0 +1,205 @@
+/*
+ * fj.h -- C-ABI of the MI355X Free Join executor (libfj.so).
+ *
+ * The library runs Free Join plans over COLT indexes on one gfx950 GPU.
+ * Its calls follow the paper's problem statement (Section 5 opening): a
+ * full conjunctive query over column-stored relations plus a left-deep
+ * binary plan, which is converted to a Free Join plan (Section 4.1), whose
+ * COLT indexes are built (Section 3.3 build phase, Section 4.2), and which
+ * is executed (Section 3.3 join phase, Section 4.3 vectorized batches,
+ * Section 4.4 dynamic covers).
+ *
+ * Conventions for every call:
+ *   - Device pointers are HIP device addresses on the context's device.
+ *     Host pointers are ordinary process memory.  Each argument says which.
+ *   - Relation columns and selection vectors are borrowed: the caller keeps
+ *     them alive and unchanged for the lifetime of every COLT built on them
+ *     (a COLT stores row offsets into the base relation, Section 4.2).
+ *   - Plans, COLTs and contexts are owned by the library; free them with
+ *     the matching *_free / *_destroy call.  Output buffers are the caller's.
+ *   - Calls return an fj_status and never abort.  On a non-OK status,
+ *     fj_last_error() returns a thread-local description.
+ *   - Work is ordered on the context's HIP stream.  Calls that return host
+ *     results synchronize that stream before returning.
+ *   - A context is not thread-safe; use one context per host thread.
+ */
+#ifndef FJ_H
+#define FJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FJ_OK = 0,
+    FJ_TRUNCATED = 1,               /* count exact, output rows capped at cap */
+    FJ_ERR_ARG = -1,                /* bad argument (null, size, range)      */
+    FJ_ERR_PLAN_INVALID = -2,       /* Section 3.2 validity (a)/(b) fails    */
+    FJ_ERR_PLAN_NO_PURE_COVER = -3, /* a node has no cover free of bound vars */
+    FJ_ERR_OOM = -4,                /* device or host allocation failed      */
+    FJ_ERR_HIP = -5,                /* a HIP runtime call failed             */
+    FJ_ERR_UNSUPPORTED = -6         /* outside the documented limits         */
+} fj_status;
+
+#define FJ_MAX_COLS 8     /* columns per relation / variables per subatom */
+#define FJ_MAX_ATOMS 16   /* atoms per query */
+#define FJ_MAX_VARS 32    /* variables per query */
+#define FJ_MAX_NODES 16   /* nodes per plan */
+
+/* A (possibly filtered) column-stored relation.  cols[j] is a device array
+   of nrows int32 values.  When sel is non-null it is a device array of nsel
+   row offsets (each < nrows): the atom ranges over those rows only, which is
+   how a pushed-down selection reaches the join (Section 2.1). */
+typedef struct {
+    int32_t ncols;
+    int64_t nrows;                       /* < 2^31 */
+    const int32_t *cols[FJ_MAX_COLS];    /* device, borrowed */
+    const uint32_t *sel;                 /* device, borrowed, nullable */
+    int64_t nsel;
+} fj_relation;
+
+/* One atom R_i(x_i) of Section 2.1, eq. "cq": vars[j] is the variable of
+   column j.  The variables of one atom are distinct (selections such as
+   R(x,x) are pushed down before the join, Section 2.1). */
+typedef struct {
+    int32_t arity;
+    int32_t vars[FJ_MAX_COLS];
+} fj_atom;
+
+/* A full conjunctive query.  head lists every variable once, in the column
+   order of materialized output rows.  Self-joins are separate atoms (the
+   paper renames them, Section 2.1); they may share one relation's buffers. */
+typedef struct {
+    int32_t natoms;
+    fj_atom atoms[FJ_MAX_ATOMS];
+    int32_t nvars;
+    int32_t nhead;
+    int32_t head[FJ_MAX_VARS];
+} fj_query;
+
+typedef struct fj_ctx fj_ctx;
+typedef struct fj_plan fj_plan;
+typedef struct fj_colt fj_colt;
+
+/* Execution options; zero fields take the defaults in brackets. */
+typedef struct {
+    int64_t tile;        /* max cover tuples per probe launch = frontier capacity [1<<24] */
+    int32_t block;       /* threads per workgroup for probe kernels, 64..1024 [256] */
+    int32_t timing;      /* nonzero: time kernel classes with hipEvents [0] */
+    int32_t tail;        /* 0: multiply trailing single-cover nodes (default);
+                            1: run every node through the probe kernel */
+    int32_t reserved[4];
+} fj_options;
+
+/* Per-execution counters (fj_execute fills them when stats is non-null).
+   Index k is plan node k.  Counting lookups costs a few percent. */
+typedef struct {
+    uint64_t cover[FJ_MAX_NODES];        /* cover tuples iterated */
+    uint64_t probe[FJ_MAX_NODES];        /* get() calls */
+    uint64_t hit[FJ_MAX_NODES];          /* successful get() calls */
+    uint64_t survivors[FJ_MAX_NODES];    /* tuples passing every lookup */
+    uint64_t forced[FJ_MAX_NODES];       /* tries forced while running node k */
+    uint64_t forced_offsets[FJ_MAX_NODES];
+    int32_t tail_from;                   /* first node handled as a product */
+    int32_t nnodes;
+    uint64_t tiles;                      /* probe launches */
+    uint64_t deferred;                   /* tuples re-run after a lazy force */
+} fj_stats;
+
+/* Kernel-class timings accumulated since the last fj_timings_reset. */
+typedef enum {
+    FJ_T_FILTER = 0, FJ_T_BUILD, FJ_T_COVER, FJ_T_PROBE, FJ_T_PROBE0,
+    FJ_T_FORCE, FJ_T_EMIT, FJ_T_SCAN, FJ_T_COUNT
+} fj_timer;
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device`.  `stream` is a hipStream_t (or
+   NULL for the default stream); the context does not own it.  opt may be
+   NULL.  Returns FJ_ERR_HIP if the device cannot be selected. */
+fj_status fj_ctx_create(int device, void *stream, const fj_options *opt, fj_ctx **out);
+void fj_ctx_destroy(fj_ctx *ctx);
+
+/* Thread-local message for the last non-OK status of this thread. */
+const char *fj_last_error(void);
+
+/* Accumulated milliseconds and launch counts per fj_timer class (host
+   arrays of FJ_T_COUNT entries); timing must be enabled in the options.
+   Synchronizes the stream. */
+fj_status fj_timings(fj_ctx *ctx, double *ms, uint64_t *launches);
+fj_status fj_timings_reset(fj_ctx *ctx);
+
+/* -------------------------------------------------------------------- plans */
+
+#define FJ_FACTOR 1u   /* apply conservative factoring (Section 4.1) */
+
+/* Convert the left-deep binary plan [R_order[0], ..., R_order[n-1]] (atom
+   indices, each atom once) into a Free Join plan (Section 4.1, figure
+   "bj2fj"), then factor it when flags has FJ_FACTOR (figure
+   "factorize-plan").  The result is validated (Section 3.2).  q and order
+   are host memory. */
+fj_status fj_plan_from_binary(const fj_query *q, const int32_t *order, int32_t n,
+                              uint32_t flags, fj_plan **out);
+
+/* Build a plan from explicit nodes (Section 3.2 definition): node k has
+   node_nsub[k] subatoms, listed flat in node order; subatom i belongs to
+   atom sub_atom[i] and has sub_nvars[i] variables sub_vars[i*FJ_MAX_COLS+j].
+   Returns FJ_ERR_PLAN_INVALID when the nodes do not partition every atom
+   or validity (a)/(b) fails, FJ_ERR_PLAN_NO_PURE_COVER when some node has
+   no cover whose variables are all new.  All arrays are host memory. */
+fj_status fj_plan_from_nodes(const fj_query *q, int32_t nnodes, const int32_t *node_nsub,
+                             const int32_t *sub_atom, const int32_t *sub_nvars,
+                             const int32_t *sub_vars, fj_plan **out);
+
+/* Read a plan back in the fj_plan_from_nodes layout (host arrays with room
+   for cap_sub subatoms; node_nsub needs FJ_MAX_NODES entries). */
+fj_status fj_plan_get(const fj_plan *p, int32_t *nnodes, int32_t *node_nsub, int32_t *sub_atom,
+                      int32_t *sub_nvars, int32_t *sub_vars, int32_t cap_sub);
+void fj_plan_free(fj_plan *p);
+
+/* ---------------------------------------------------------------- selection */
+
+/* Pushed-down selection sigma_{col < bound} (Section 2.1): writes the row
+   offsets r with col[r] < bound into out_sel (device, capacity nrows) in
+   unspecified order and their number to *out_n (host).  col is device. */
+fj_status fj_filter_lt(fj_ctx *ctx, const int32_t *col, int64_t nrows, int32_t bound,
+                       uint32_t *out_sel, int64_t *out_n);
+
+/* -------------------------------------------------------------------- COLTs */
+
+/* Build phase (Section 3.3) for atom `atom` of q under plan p: the COLT's
+   schema is the atom's subatom variable lists in plan order (Section 4.2).
+   Its root map is built now, on the GPU, unless the atom's first subatom is
+   both its only level and the only pure cover of its node; then the base
+   table (or rel->sel) is iterated directly (Section 4.2).  Deeper levels are
+   forced lazily during fj_execute.  rel describes the relation; its column
+   pointers are borrowed.  Device memory for the index is allocated here. */
+fj_status fj_build_colt(fj_ctx *ctx, const fj_query *q, const fj_plan *p, int32_t atom,
+                        const fj_relation *rel, fj_colt **out);
+
+/* Return a COLT to its just-built state (root rebuilt, inner levels
+   unforced) without reallocating; rel may change its row count only
+   downward and must keep its arity. */
+fj_status fj_colt_rebuild(fj_ctx *ctx, fj_colt *colt, const fj_relation *rel);
+void fj_colt_free(fj_colt *colt);
+
+/* --------------------------------------------------------------------- join */
+
+/* Join phase (Section 3.3, figure "fj-algo"; Section 4.3; Section 4.4).
+   colts: host array of q->natoms COLTs built for this q and p.  *count
+   (host) receives the exact number of result tuples under bag semantics.
+   If out (device, row-major cap x q->nhead int32) is non-null, min(count,
+   cap) result rows in head order are written to out[0 .. *written) in
+   unspecified order; FJ_TRUNCATED is returned when count > cap.  stats
+   (host) is optional. */
+fj_status fj_execute(fj_ctx *ctx, const fj_query *q, const fj_plan *p, fj_colt *const *colts,
+                     uint64_t *count, int32_t *out, uint64_t cap, uint64_t *written,
+                     fj_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FJ_H */

@@ -1,0 +1,934 @@
+// libfj: the C-ABI of include/fj.h.  Host orchestration of the Free Join
+// executor: contexts, COLT construction (Section 3.3 build phase, Section 4.2),
+// the depth-first, tiled execution of plan nodes with lazy forcing
+// (Section 3.3 join phase, Sections 4.3 and 4.4) and output emission.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstddef>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fj.h"
+#include "fj_dev.h"
+#include "fj_launch.h"
+#include "fj_plan.h"
+
+using fj::FrontierDev;
+using fj::LevelDev;
+using fj::NodeDev;
+using fj::StatusDev;
+using fj::SubDev;
+using fj::TailDev;
+typedef unsigned long long u64;
+
+namespace {
+
+thread_local std::string g_err;
+
+fj_status fail(fj_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+#define FJ_HIP(call)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(e_ == hipErrorOutOfMemory ? FJ_ERR_OOM : FJ_ERR_HIP,                 \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                  \
+    } while (0)
+
+#define FJ_TRY(expr)                         \
+    do {                                     \
+        fj_status s_ = (expr);               \
+        if (s_ != FJ_OK) return s_;          \
+    } while (0)
+
+template <typename T>
+fj_status dalloc(T **p, size_t n) {
+    *p = nullptr;
+    hipError_t e = hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(FJ_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    return FJ_OK;
+}
+
+// A device buffer that only grows.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    fj_status ensure(size_t want, hipStream_t s) {
+        if (want <= bytes) return FJ_OK;
+        if (p) {
+            hipStreamSynchronize(s);
+            hipFree(p);
+            p = nullptr;
+            bytes = 0;
+        }
+        size_t b = std::max<size_t>(want, 256);
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) { p = nullptr; return fail(FJ_ERR_OOM, "hipMalloc of scratch failed"); }
+        bytes = b;
+        return FJ_OK;
+    }
+    void release() {
+        if (p) hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T> T *as(size_t byte_off = 0) const { return (T *)((char *)p + byte_off); }
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ context
+
+struct fj_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    fj_options opt{};
+    StatusDev *status_d = nullptr;
+    StatusDev *status_h = nullptr;  // pinned
+    // per-node execution buffers
+    DevBuf front[FJ_MAX_NODES + 1];
+    DevBuf nodebuf[FJ_MAX_NODES];   // starts | cnt | cov
+    DevBuf defer;                   // two deferred lists
+    DevBuf force;                   // force scratch
+    DevBuf scanb;                   // block sums for scans
+    DevBuf desc;                    // node + emit descriptors
+    DevBuf emitbuf;                 // emit counts and starts
+    void *desc_h = nullptr;         // pinned staging for descriptors
+    size_t desc_h_bytes = 0;
+    // timing
+    struct Pending { int cls; hipEvent_t a, b; };
+    std::vector<hipEvent_t> pool;
+    std::vector<Pending> pending;
+    double ms[FJ_T_COUNT] = {0};
+    uint64_t launches[FJ_T_COUNT] = {0};
+};
+
+namespace {
+
+struct Timer {
+    fj_ctx *c;
+    int cls;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timer(fj_ctx *ctx, int k) : c(ctx), cls(k) {
+        if (!c->opt.timing) return;
+        a = get();
+        b = get();
+        hipEventRecord(a, c->stream);
+    }
+    ~Timer() {
+        if (!c->opt.timing) return;
+        hipEventRecord(b, c->stream);
+        c->pending.push_back({cls, a, b});
+    }
+    hipEvent_t get() {
+        if (!c->pool.empty()) {
+            hipEvent_t e = c->pool.back();
+            c->pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        hipEventCreate(&e);
+        return e;
+    }
+};
+
+fj_status sync_status(fj_ctx *c) {
+    FJ_HIP(hipMemcpyAsync(c->status_h, c->status_d, sizeof(StatusDev), hipMemcpyDeviceToHost, c->stream));
+    FJ_HIP(hipStreamSynchronize(c->stream));
+    if (c->status_h->err_count)
+        return fail(FJ_ERR_HIP, "device bounds check failed (fj_kernels.hip line " +
+                                    std::to_string(c->status_h->err_line) + ", " +
+                                    std::to_string(c->status_h->err_count) + " times)");
+    return FJ_OK;
+}
+
+fj_status zero_status_field(fj_ctx *c, size_t off, size_t bytes) {
+    FJ_HIP(hipMemsetAsync((char *)c->status_d + off, 0, bytes, c->stream));
+    return FJ_OK;
+}
+
+fj_status scan_u64(fj_ctx *c, const u64 *in, u64 *out, u64 n) {
+    size_t nb = (n + 1023) / 1024 + 1;
+    FJ_TRY(c->scanb.ensure(nb * sizeof(u64), c->stream));
+    Timer t(c, FJ_T_SCAN);
+    FJ_HIP(fj::launch_scan_u64(in, out, n, c->scanb.as<u64>(), &c->status_d->total, c->stream));
+    return FJ_OK;
+}
+
+fj_status scan_u32(fj_ctx *c, const uint32_t *in, uint32_t *out, u64 n) {
+    size_t nb = (n + 1023) / 1024 + 1;
+    FJ_TRY(c->scanb.ensure(nb * sizeof(uint32_t), c->stream));
+    Timer t(c, FJ_T_SCAN);
+    FJ_HIP(fj::launch_scan_u32(in, out, n, c->scanb.as<uint32_t>(), &c->status_d->total32, c->stream));
+    return FJ_OK;
+}
+
+}  // namespace
+
+// -------------------------------------------------------------------- COLTs
+
+struct fj_colt {
+    int device = 0;
+    int atom = -1;
+    int ncols = 0;
+    int nlev = 0;
+    const int32_t *cols[FJ_MAX_COLS] = {nullptr};
+    const uint32_t *sel = nullptr;
+    int64_t nrows = 0;
+    uint32_t nroot = 0;      // rows the root ranges over
+    uint32_t cap_rows = 0;   // rows the buffers were sized for
+    bool root_built = false;
+    int lev_nk[fj::kMaxLevels] = {0};
+    int lev_var[fj::kMaxLevels][FJ_MAX_COLS] = {{0}};
+    LevelDev lev[fj::kMaxLevels + 1];
+    u64 table_slots[fj::kMaxLevels] = {0};
+    std::vector<void *> allocs;
+};
+
+namespace {
+
+int key_mode(int level, int nk) {
+    if (nk == 0) return fj::KM_ZERO;
+    if (level == 0 && nk == 1) return fj::KM_K32;
+    if ((level == 0 && nk == 2) || (level > 0 && nk == 1)) return fj::KM_K64;
+    return fj::KM_REP;
+}
+
+size_t slot_bytes(int mode) {
+    return mode == fj::KM_K32 ? sizeof(fj::Slot32) : (mode == fj::KM_K64 ? sizeof(fj::Slot64) : sizeof(fj::SlotRep));
+}
+
+template <typename T>
+fj_status colt_alloc(fj_colt *t, T **p, size_t n) {
+    FJ_TRY(dalloc(p, n));
+    t->allocs.push_back((void *)*p);
+    return FJ_OK;
+}
+
+// Device buffers for every level; contents are initialised by colt_reset.
+fj_status colt_allocate(fj_colt *t) {
+    const size_t n = std::max<uint32_t>(t->cap_rows, 1);
+    for (int l = 0; l <= t->nlev; l++) {
+        LevelDev &L = t->lev[l];
+        memset(&L, 0, sizeof(L));
+        L.npos = (uint32_t)n;
+        L.nrows = (uint32_t)t->nrows;
+        bool leaf = (l == t->nlev);
+        if (l > 0) FJ_TRY(colt_alloc(t, &L.offs, n));
+        FJ_TRY(colt_alloc(t, &L.len, n));
+        if (leaf) continue;
+        FJ_TRY(colt_alloc(t, &L.st, n));
+        if (l == 0 && !t->root_built && t->nlev == 1) {
+            // a base table iterated directly is never forced: no map, no scratch
+            L.nk = t->lev_nk[l];
+            L.mode = fj::KM_ZERO;
+            continue;
+        }
+        FJ_TRY(colt_alloc(t, &L.kl, n));
+        FJ_TRY(colt_alloc(t, &L.rank_ctr, n));
+        FJ_TRY(colt_alloc(t, &L.cnt, n));
+        FJ_TRY(colt_alloc(t, &L.fq, n));
+        L.nk = t->lev_nk[l];
+        L.mode = key_mode(l, L.nk);
+        if (L.mode != fj::KM_ZERO) {
+            u64 cap = 16;
+            while (cap < 2 * (u64)n) cap <<= 1;
+            L.mask = cap - 1;
+            L.nslots = cap + 1;
+            t->table_slots[l] = cap + 1;
+            char *tb = nullptr;
+            FJ_TRY(colt_alloc(t, &tb, (cap + 1) * slot_bytes(L.mode)));
+            L.table = tb;
+        }
+    }
+    return FJ_OK;
+}
+
+void colt_free_all(fj_colt *t) {
+    for (void *p : t->allocs) hipFree(p);
+    t->allocs.clear();
+}
+
+}  // namespace
+
+// Force every handle queued on level l of colt t (the queue holds nh handle
+// starts; W is their total length when the caller knows it, else ~0).
+static fj_status force_queue(fj_ctx *c, fj_colt *t, int l, uint32_t nh, u64 W_known, int timer_cls,
+                             fj_stats *stats, int node) {
+    if (nh == 0) return FJ_OK;
+    LevelDev &L = t->lev[l];
+    LevelDev &C = t->lev[l + 1];
+    // scratch: lens (nh) | pre (nh + 1) | wslot | wrank | cntv | ex (W + 1)
+    size_t off_lens = 0;
+    size_t off_pre = align256(off_lens + sizeof(uint32_t) * nh);
+    size_t off_w = align256(off_pre + sizeof(uint32_t) * (nh + 1));
+    u64 Wmax = W_known != ~0ull ? W_known : t->nroot;
+    size_t wbytes = align256(sizeof(uint32_t) * (Wmax + 1));
+    FJ_TRY(c->force.ensure(off_w + 4 * wbytes, c->stream));
+    uint32_t *lens = c->force.as<uint32_t>(off_lens);
+    uint32_t *pre = c->force.as<uint32_t>(off_pre);
+    Timer tm(c, timer_cls);
+    FJ_HIP(fj::launch_fq_lens(L, L.fq, nh, lens, c->status_d, c->stream));
+    FJ_TRY(scan_u32(c, lens, pre, nh));
+    u64 W = W_known;
+    if (W == ~0ull) {
+        FJ_TRY(sync_status(c));
+        W = c->status_h->total32;
+    }
+    fj::ForceLaunch f;
+    f.L = L;
+    f.C = C;
+    for (int j = 0; j < FJ_MAX_COLS; j++) f.cols[j] = t->cols[j];
+    f.fq = L.fq;
+    f.nh = nh;
+    f.pre = pre;
+    f.W = (uint32_t)W;
+    f.wslot = c->force.as<uint32_t>(off_w);
+    f.wrank = c->force.as<uint32_t>(off_w + wbytes);
+    f.cntv = c->force.as<uint32_t>(off_w + 2 * wbytes);
+    f.ex = c->force.as<uint32_t>(off_w + 3 * wbytes);
+    f.wcap = (uint32_t)(Wmax + 1);
+    f.status = c->status_d;
+    if (W > Wmax) return fail(FJ_ERR_HIP, "forced offsets exceed the relation size");
+    FJ_HIP(fj::launch_force_phase(0, f, c->stream));
+    FJ_HIP(fj::launch_force_phase(1, f, c->stream));
+    FJ_HIP(fj::launch_force_phase(2, f, c->stream));
+    FJ_TRY(scan_u32(c, f.cntv, f.ex, W));
+    FJ_HIP(fj::launch_force_phase(3, f, c->stream));
+    FJ_HIP(fj::launch_force_phase(4, f, c->stream));
+    if (stats && node >= 0) {
+        stats->forced[node] += nh;
+        stats->forced_offsets[node] += W;
+    }
+    return FJ_OK;
+}
+
+static fj_status colt_reset(fj_ctx *c, fj_colt *t) {
+    hipStream_t s = c->stream;
+    for (int l = 0; l <= t->nlev; l++) t->lev[l].nrows = (uint32_t)t->nrows;
+    for (int l = 0; l < t->nlev; l++) {
+        LevelDev &L = t->lev[l];
+        size_t n = std::max<uint32_t>(t->cap_rows, 1);
+        FJ_HIP(hipMemsetAsync(L.st, 0, n * sizeof(uint32_t), s));
+        if (!L.cnt) continue;  // directly iterated base table
+        FJ_HIP(hipMemsetAsync(L.rank_ctr, 0, n * sizeof(uint32_t), s));
+        FJ_HIP(hipMemsetAsync(L.cnt, 0, n * sizeof(uint32_t), s));
+        if (L.table) FJ_HIP(fj::launch_table_init(L.table, t->table_slots[l], L.mode, s));
+    }
+    LevelDev &R = t->lev[0];
+    R.offs = const_cast<uint32_t *>(t->sel);
+    FJ_HIP(fj::launch_root_init(R, t->nroot, s));
+    if (t->root_built) {
+        if (t->nroot == 0) {
+            FJ_HIP(fj::launch_fill_u32(R.st, 1, 1u, s));  // forced, no keys
+        } else {
+            FJ_TRY(force_queue(c, t, 0, 1, t->nroot, FJ_T_BUILD, nullptr, -1));
+        }
+    }
+    return FJ_OK;
+}
+
+static fj_status check_relation(const fj_relation *r, int arity) {
+    if (!r) return fail(FJ_ERR_ARG, "null relation");
+    if (r->ncols != arity) return fail(FJ_ERR_ARG, "relation arity does not match the atom");
+    if (r->nrows < 0 || r->nrows >= (int64_t(1) << 31)) return fail(FJ_ERR_UNSUPPORTED, "nrows must be below 2^31");
+    for (int j = 0; j < arity; j++)
+        if (!r->cols[j] && r->nrows > 0) return fail(FJ_ERR_ARG, "null column");
+    if (r->sel && (r->nsel < 0 || r->nsel > r->nrows)) return fail(FJ_ERR_ARG, "nsel out of range");
+    return FJ_OK;
+}
+
+extern "C" {
+
+const char *fj_last_error(void) { return g_err.c_str(); }
+
+fj_status fj_ctx_create(int device, void *stream, const fj_options *opt, fj_ctx **out) {
+    if (!out) return fail(FJ_ERR_ARG, "null out");
+    *out = nullptr;
+    int ndev = 0;
+    FJ_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(FJ_ERR_ARG, "no such device");
+    FJ_HIP(hipSetDevice(device));
+    fj_ctx *c = new fj_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    if (opt) c->opt = *opt;
+    if (c->opt.tile <= 0) c->opt.tile = 1 << 24;
+    if (c->opt.tile > (int64_t(1) << 30)) c->opt.tile = int64_t(1) << 30;
+    if (c->opt.block <= 0) c->opt.block = 256;
+    if (c->opt.block % 64 || c->opt.block > 1024) { delete c; return fail(FJ_ERR_ARG, "block must be a multiple of 64, at most 1024"); }
+    hipError_t e = hipMalloc((void **)&c->status_d, sizeof(StatusDev));
+    if (e != hipSuccess) { delete c; return fail(FJ_ERR_OOM, "status block"); }
+    e = hipHostMalloc((void **)&c->status_h, sizeof(StatusDev), hipHostMallocDefault);
+    if (e != hipSuccess) { hipFree(c->status_d); delete c; return fail(FJ_ERR_OOM, "pinned status block"); }
+    memset(c->status_h, 0, sizeof(StatusDev));
+    *out = c;
+    return FJ_OK;
+}
+
+void fj_ctx_destroy(fj_ctx *c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    for (auto &b : c->front) b.release();
+    for (auto &b : c->nodebuf) b.release();
+    c->defer.release();
+    c->force.release();
+    c->scanb.release();
+    c->desc.release();
+    c->emitbuf.release();
+    if (c->desc_h) hipHostFree(c->desc_h);
+    for (auto &p : c->pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
+    for (auto e : c->pool) hipEventDestroy(e);
+    hipFree(c->status_d);
+    hipHostFree(c->status_h);
+    delete c;
+}
+
+fj_status fj_timings(fj_ctx *c, double *ms, uint64_t *launches) {
+    if (!c) return fail(FJ_ERR_ARG, "null ctx");
+    FJ_HIP(hipStreamSynchronize(c->stream));
+    for (auto &p : c->pending) {
+        float m = 0;
+        FJ_HIP(hipEventElapsedTime(&m, p.a, p.b));
+        c->ms[p.cls] += m;
+        c->launches[p.cls] += 1;
+        c->pool.push_back(p.a);
+        c->pool.push_back(p.b);
+    }
+    c->pending.clear();
+    for (int i = 0; i < FJ_T_COUNT; i++) {
+        if (ms) ms[i] = c->ms[i];
+        if (launches) launches[i] = c->launches[i];
+    }
+    return FJ_OK;
+}
+
+fj_status fj_timings_reset(fj_ctx *c) {
+    if (!c) return fail(FJ_ERR_ARG, "null ctx");
+    FJ_TRY(fj_timings(c, nullptr, nullptr));
+    for (int i = 0; i < FJ_T_COUNT; i++) { c->ms[i] = 0; c->launches[i] = 0; }
+    return FJ_OK;
+}
+
+// ------------------------------------------------------------------- plans
+
+fj_status fj_plan_from_binary(const fj_query *q, const int32_t *order, int32_t n, uint32_t flags,
+                              fj_plan **out) {
+    if (!q || !order || !out) return fail(FJ_ERR_ARG, "null argument");
+    *out = nullptr;
+    fj_plan *p = new fj_plan();
+    std::string err;
+    fj_status st = fj::plan_from_binary(*q, order, n, (flags & FJ_FACTOR) != 0, p, err);
+    if (st != FJ_OK) { delete p; return fail(st, err); }
+    *out = p;
+    return FJ_OK;
+}
+
+fj_status fj_plan_from_nodes(const fj_query *q, int32_t nnodes, const int32_t *node_nsub, const int32_t *sub_atom,
+                             const int32_t *sub_nvars, const int32_t *sub_vars, fj_plan **out) {
+    if (!q || !node_nsub || !sub_atom || !sub_nvars || !sub_vars || !out) return fail(FJ_ERR_ARG, "null argument");
+    *out = nullptr;
+    if (nnodes < 1 || nnodes > FJ_MAX_NODES) return fail(FJ_ERR_UNSUPPORTED, "nnodes out of range");
+    std::vector<std::vector<fj::Subatom>> nodes(nnodes);
+    int idx = 0;
+    for (int k = 0; k < nnodes; k++) {
+        if (node_nsub[k] < 1 || node_nsub[k] > FJ_MAX_ATOMS) return fail(FJ_ERR_PLAN_INVALID, "bad node size");
+        for (int s = 0; s < node_nsub[k]; s++, idx++) {
+            fj::Subatom sa;
+            sa.atom = sub_atom[idx];
+            sa.nv = sub_nvars[idx];
+            if (sa.nv < 0 || sa.nv > FJ_MAX_COLS) return fail(FJ_ERR_PLAN_INVALID, "bad subatom size");
+            for (int j = 0; j < sa.nv; j++) {
+                sa.vars[j] = sub_vars[idx * FJ_MAX_COLS + j];
+                if (sa.vars[j] < 0 || sa.vars[j] >= FJ_MAX_VARS) return fail(FJ_ERR_PLAN_INVALID, "bad variable");
+            }
+            nodes[k].push_back(sa);
+        }
+    }
+    fj_plan *p = new fj_plan();
+    std::string err;
+    fj_status st = fj::plan_from_nodes(*q, nodes, p, err);
+    if (st != FJ_OK) { delete p; return fail(st, err); }
+    *out = p;
+    return FJ_OK;
+}
+
+fj_status fj_plan_get(const fj_plan *p, int32_t *nnodes, int32_t *node_nsub, int32_t *sub_atom,
+                      int32_t *sub_nvars, int32_t *sub_vars, int32_t cap_sub) {
+    if (!p || !nnodes || !node_nsub || !sub_atom || !sub_nvars || !sub_vars) return fail(FJ_ERR_ARG, "null argument");
+    int idx = 0;
+    *nnodes = (int32_t)p->nodes.size();
+    for (size_t k = 0; k < p->nodes.size(); k++) {
+        node_nsub[k] = (int32_t)p->nodes[k].size();
+        for (const auto &s : p->nodes[k]) {
+            if (idx >= cap_sub) return fail(FJ_ERR_ARG, "cap_sub too small");
+            sub_atom[idx] = s.atom;
+            sub_nvars[idx] = s.nv;
+            for (int j = 0; j < FJ_MAX_COLS; j++) sub_vars[idx * FJ_MAX_COLS + j] = j < s.nv ? s.vars[j] : -1;
+            idx++;
+        }
+    }
+    return FJ_OK;
+}
+
+void fj_plan_free(fj_plan *p) { delete p; }
+
+// --------------------------------------------------------------- selection
+
+fj_status fj_filter_lt(fj_ctx *c, const int32_t *col, int64_t nrows, int32_t bound, uint32_t *out_sel,
+                       int64_t *out_n) {
+    if (!c || !out_n || nrows < 0 || (nrows > 0 && (!col || !out_sel))) return fail(FJ_ERR_ARG, "bad argument");
+    FJ_HIP(hipSetDevice(c->device));
+    FJ_TRY(zero_status_field(c, offsetof(StatusDev, total), sizeof(u64)));
+    {
+        Timer t(c, FJ_T_FILTER);
+        if (nrows > 0) FJ_HIP(fj::launch_filter_lt(col, (u64)nrows, bound, out_sel, &c->status_d->total, c->stream));
+    }
+    FJ_TRY(sync_status(c));
+    *out_n = (int64_t)c->status_h->total;
+    return FJ_OK;
+}
+
+// ------------------------------------------------------------------- COLTs
+
+fj_status fj_build_colt(fj_ctx *c, const fj_query *q, const fj_plan *p, int32_t atom, const fj_relation *rel,
+                        fj_colt **out) {
+    if (!c || !q || !p || !out) return fail(FJ_ERR_ARG, "null argument");
+    *out = nullptr;
+    if (atom < 0 || atom >= q->natoms || atom >= p->q.natoms) return fail(FJ_ERR_ARG, "atom out of range");
+    FJ_TRY(check_relation(rel, q->atoms[atom].arity));
+    FJ_HIP(hipSetDevice(c->device));
+    fj_colt *t = new fj_colt();
+    t->device = c->device;
+    t->atom = atom;
+    t->ncols = rel->ncols;
+    for (int j = 0; j < rel->ncols; j++) t->cols[j] = rel->cols[j];
+    t->sel = rel->sel;
+    t->nrows = rel->nrows;
+    t->nroot = (uint32_t)(rel->sel ? rel->nsel : rel->nrows);
+    t->cap_rows = t->nroot;
+    t->root_built = p->root_built[atom];
+    t->nlev = p->nlev[atom];
+    for (int l = 0; l < t->nlev; l++) {
+        const fj::Subatom &s = p->lev[atom][l];
+        t->lev_nk[l] = s.nv;
+        for (int j = 0; j < s.nv; j++) t->lev_var[l][j] = s.vars[j];
+    }
+    fj_status st = colt_allocate(t);
+    if (st == FJ_OK) {
+        // key columns of every level
+        for (int l = 0; l < t->nlev; l++)
+            for (int j = 0; j < t->lev_nk[l]; j++)
+                for (int cc = 0; cc < q->atoms[atom].arity; cc++)
+                    if (q->atoms[atom].vars[cc] == t->lev_var[l][j]) t->lev[l].kcol[j] = cc;
+        st = colt_reset(c, t);
+    }
+    if (st != FJ_OK) {
+        std::string keep = g_err;
+        hipStreamSynchronize(c->stream);
+        colt_free_all(t);
+        delete t;
+        g_err = keep;
+        return st;
+    }
+    *out = t;
+    return FJ_OK;
+}
+
+fj_status fj_colt_rebuild(fj_ctx *c, fj_colt *t, const fj_relation *rel) {
+    if (!c || !t || !rel) return fail(FJ_ERR_ARG, "null argument");
+    FJ_TRY(check_relation(rel, t->ncols));
+    uint32_t nroot = (uint32_t)(rel->sel ? rel->nsel : rel->nrows);
+    if (nroot > t->cap_rows) return fail(FJ_ERR_ARG, "relation grew beyond the COLT's capacity");
+    FJ_HIP(hipSetDevice(c->device));
+    for (int j = 0; j < rel->ncols; j++) t->cols[j] = rel->cols[j];
+    t->sel = rel->sel;
+    t->nrows = rel->nrows;
+    t->nroot = nroot;
+    return colt_reset(c, t);
+}
+
+void fj_colt_free(fj_colt *t) {
+    if (!t) return;
+    hipSetDevice(t->device);
+    hipDeviceSynchronize();
+    colt_free_all(t);
+    delete t;
+}
+
+}  // extern "C"
+
+// --------------------------------------------------------------------- join
+
+namespace {
+
+struct Exec {
+    fj_ctx *c;
+    const fj_plan *p;
+    fj_colt *const *colts;
+    int32_t *out;
+    u64 cap;
+    u64 written = 0;
+    fj_stats *stats;
+    int tail_from;
+    int nnodes;
+    u64 C;                              // tile / frontier capacity
+    FrontierDev F[FJ_MAX_NODES + 1];
+    NodeDev *nd_d = nullptr;            // device node descriptors
+    void *emit_d = nullptr;             // device emit descriptor
+    std::vector<TailDev> tails;
+    std::vector<int> head_src;
+    uint32_t *dA = nullptr, *dB = nullptr;
+    uint8_t *dA_j = nullptr, *dB_j = nullptr;
+};
+
+void fill_level_sub(SubDev &S, const fj_colt *t, int level) {
+    S.L = t->lev[level];
+    S.C = t->lev[level + 1];
+    for (int j = 0; j < FJ_MAX_COLS; j++) S.cols[j] = t->cols[j];
+    S.root_len = t->nroot;
+}
+
+fj_status force_pending_queues(Exec &x, int node, const std::vector<std::pair<int, int>> &queues) {
+    fj_ctx *c = x.c;
+    bool any = false;
+    for (auto &al : queues) {
+        int a = al.first, l = al.second;
+        uint32_t nh = c->status_h->fq_n[a * fj::kMaxLevels + l];
+        if (!nh) continue;
+        any = true;
+        FJ_TRY(force_queue(c, x.colts[a], l, nh, ~0ull, FJ_T_FORCE, x.stats, node));
+    }
+    if (any) FJ_TRY(zero_status_field(c, offsetof(StatusDev, fq_n), sizeof(c->status_h->fq_n)));
+    return FJ_OK;
+}
+
+fj_status emit_rows(Exec &x, uint32_t E) {
+    // materialize the result rows of E final bindings in frontier F[tail_from]
+    fj_ctx *c = x.c;
+    if (!x.out || E == 0 || x.written >= x.cap) return FJ_OK;
+    u64 *cnt = c->emitbuf.as<u64>();
+    u64 *starts = c->emitbuf.as<u64>(align256(sizeof(u64) * x.C));
+    {
+        Timer t(c, FJ_T_EMIT);
+        FJ_HIP(fj::launch_emit_count(x.emit_d, E, cnt, c->status_d, c->stream));
+    }
+    FJ_TRY(scan_u64(c, cnt, starts, E));
+    FJ_TRY(sync_status(c));
+    u64 total = c->status_h->total;
+    u64 rows = std::min<u64>(total, x.cap - x.written);
+    {
+        Timer t(c, FJ_T_EMIT);
+        FJ_HIP(fj::launch_emit_rows(x.emit_d, E, starts, rows, x.written, c->status_d, c->stream));
+    }
+    x.written += rows;
+    return FJ_OK;
+}
+
+fj_status exec_node(Exec &x, int k, uint32_t E) {
+    fj_ctx *c = x.c;
+    const NodeDev *nd = x.nd_d + k;
+    const fj_plan *p = x.p;
+    u64 *starts = c->nodebuf[k].as<u64>(0);
+    u64 *cnt = c->nodebuf[k].as<u64>(align256(sizeof(u64) * (x.C + 1)));
+    uint8_t *cov = c->nodebuf[k].as<uint8_t>(align256(sizeof(u64) * (x.C + 1)) + align256(sizeof(u64) * x.C));
+    // queues this node can fill: its subatoms' (atom, level)
+    std::vector<std::pair<int, int>> queues;
+    for (size_t i = 0; i < p->nodes[k].size(); i++) queues.push_back({p->nodes[k][i].atom, p->sub_level[k][i]});
+
+    FJ_TRY(zero_status_field(c, offsetof(StatusDev, pending), sizeof(uint32_t)));
+    {
+        Timer t(c, FJ_T_COVER);
+        FJ_HIP(fj::launch_cover_choose(nd, E, cov, cnt, c->status_d, c->stream));
+    }
+    FJ_TRY(scan_u64(c, cnt, starts, E));
+    FJ_TRY(sync_status(c));
+    if (c->status_h->pending) {
+        FJ_TRY(force_pending_queues(x, k, queues));
+        {
+            Timer t(c, FJ_T_COVER);
+            FJ_HIP(fj::launch_cover_fill(nd, E, cov, cnt, c->status_d, c->stream));
+        }
+        FJ_TRY(scan_u64(c, cnt, starts, E));
+        FJ_TRY(sync_status(c));
+    }
+    const u64 T = c->status_h->total;
+    if (x.stats) x.stats->cover[k] += T;
+    const bool emit = (k == x.tail_from - 1);
+    for (u64 t0 = 0; t0 < T; t0 += x.C) {
+        uint32_t n = (uint32_t)std::min<u64>(x.C, T - t0);
+        FJ_TRY(zero_status_field(c, offsetof(StatusDev, survivors), 2 * sizeof(u64)));
+        fj::ProbeLaunch pl;
+        pl.nd = nd;
+        pl.starts = starts;
+        pl.cov = cov;
+        pl.E = E;
+        pl.t0 = t0;
+        pl.n = n;
+        pl.din = nullptr;
+        pl.din_j = nullptr;
+        pl.dout = x.dA;
+        pl.dout_j = x.dA_j;
+        pl.status = c->status_d;
+        pl.count_stats = x.stats != nullptr;
+        pl.block = c->opt.block;
+        pl.dcap = (uint32_t)x.C;
+        {
+            Timer t(c, k == 0 ? FJ_T_PROBE0 : FJ_T_PROBE);
+            FJ_HIP(fj::launch_probe(pl, c->stream));
+        }
+        if (x.stats) x.stats->tiles++;
+        FJ_TRY(sync_status(c));
+        uint32_t *din = x.dA, *dout = x.dB;
+        uint8_t *din_j = x.dA_j, *dout_j = x.dB_j;
+        int rounds = 0;
+        while (c->status_h->deferred) {
+            // each round forces the tries the deferred tuples met, so a tuple
+            // advances by at least one lookup per round
+            if (++rounds > (int)p->nodes[k].size() + 1)
+                return fail(FJ_ERR_HIP, "lazy forcing made no progress");
+            uint32_t nd_n = (uint32_t)c->status_h->deferred;
+            if (x.stats) x.stats->deferred += nd_n;
+            FJ_TRY(force_pending_queues(x, k, queues));
+            FJ_TRY(zero_status_field(c, offsetof(StatusDev, deferred), sizeof(u64)));
+            pl.din = din;
+            pl.din_j = din_j;
+            pl.dout = dout;
+            pl.dout_j = dout_j;
+            pl.n = nd_n;
+            {
+                Timer t(c, FJ_T_PROBE);
+                FJ_HIP(fj::launch_probe(pl, c->stream));
+            }
+            FJ_TRY(sync_status(c));
+            std::swap(din, dout);
+            std::swap(din_j, dout_j);
+        }
+        const uint32_t surv = (uint32_t)c->status_h->survivors;
+        if (x.stats && !emit) x.stats->survivors[k] += surv;
+        if (emit) {
+            if (x.out) FJ_TRY(emit_rows(x, surv));
+        } else if (surv) {
+            FJ_TRY(exec_node(x, k + 1, surv));
+        }
+    }
+    return FJ_OK;
+}
+
+fj_status check_exec_args(const fj_query *q, const fj_plan *p, fj_colt *const *colts) {
+    if (q->natoms != p->q.natoms || q->nvars != p->q.nvars) return fail(FJ_ERR_ARG, "query does not match the plan");
+    for (int a = 0; a < q->natoms; a++) {
+        if (q->atoms[a].arity != p->q.atoms[a].arity ||
+            memcmp(q->atoms[a].vars, p->q.atoms[a].vars, sizeof(int32_t) * q->atoms[a].arity) != 0)
+            return fail(FJ_ERR_ARG, "query does not match the plan");
+        const fj_colt *t = colts[a];
+        if (!t) return fail(FJ_ERR_ARG, "null COLT");
+        if (t->atom != a || t->nlev != p->nlev[a]) return fail(FJ_ERR_ARG, "COLT was built for another atom or plan");
+        for (int l = 0; l < t->nlev; l++) {
+            if (t->lev_nk[l] != p->lev[a][l].nv) return fail(FJ_ERR_ARG, "COLT schema does not match the plan");
+            for (int j = 0; j < t->lev_nk[l]; j++)
+                if (t->lev_var[l][j] != p->lev[a][l].vars[j]) return fail(FJ_ERR_ARG, "COLT schema does not match the plan");
+        }
+        if (t->root_built != p->root_built[a]) return fail(FJ_ERR_ARG, "COLT root rule does not match the plan");
+    }
+    std::string err;
+    return fj::check_query(*q, err) == FJ_OK ? FJ_OK : fail(FJ_ERR_ARG, err);
+}
+
+}  // namespace
+
+extern "C" fj_status fj_execute(fj_ctx *c, const fj_query *q, const fj_plan *p, fj_colt *const *colts,
+                                uint64_t *count, int32_t *out, uint64_t cap, uint64_t *written, fj_stats *stats) {
+    if (!c || !q || !p || !colts || !count) return fail(FJ_ERR_ARG, "null argument");
+    FJ_TRY(check_exec_args(q, p, colts));
+    FJ_HIP(hipSetDevice(c->device));
+    if (stats) memset(stats, 0, sizeof(*stats));
+    Exec x;
+    x.c = c;
+    x.p = p;
+    x.colts = colts;
+    x.out = cap ? out : nullptr;
+    x.cap = out ? cap : 0;
+    x.stats = stats;
+    x.nnodes = (int)p->nodes.size();
+    x.tail_from = c->opt.tail == 1 ? x.nnodes : p->tail_from;
+    x.C = (u64)c->opt.tile;
+    if (stats) { stats->tail_from = x.tail_from; stats->nnodes = x.nnodes; }
+
+    // frontier buffers: F[0] is the single empty binding
+    for (int k = 0; k <= x.tail_from; k++) {
+        const auto &L = p->layout[k];
+        FrontierDev &F = x.F[k];
+        memset(&F, 0, sizeof(F));
+        F.nvals = (int)L.in_var.size();
+        F.nhdl = (int)L.in_hatom.size();
+        F.cap = k == 0 ? 1 : x.C;
+        if (k == 0) continue;
+        size_t bv = align256(sizeof(int32_t) * F.cap * F.nvals);
+        size_t bh = align256(sizeof(uint32_t) * F.cap * F.nhdl);
+        size_t bm = align256(sizeof(u64) * F.cap);
+        FJ_TRY(c->front[k].ensure(bv + bh + bm, c->stream));
+        F.vals = c->front[k].as<int32_t>(0);
+        F.hdl = c->front[k].as<uint32_t>(bv);
+        F.mult = c->front[k].as<u64>(bv + bh);
+    }
+    for (int k = 0; k < x.tail_from; k++) {
+        u64 E = k == 0 ? 1 : x.C;
+        size_t b = align256(sizeof(u64) * (E + 1)) + align256(sizeof(u64) * E) + align256(E);
+        b = std::max(b, align256(sizeof(u64) * (x.C + 1)) + align256(sizeof(u64) * x.C) + align256(x.C));
+        FJ_TRY(c->nodebuf[k].ensure(b, c->stream));
+    }
+    size_t dl = align256(sizeof(uint32_t) * x.C);
+    size_t dj = align256(x.C);
+    FJ_TRY(c->defer.ensure(2 * (dl + dj), c->stream));
+    x.dA = c->defer.as<uint32_t>(0);
+    x.dB = c->defer.as<uint32_t>(dl);
+    x.dA_j = c->defer.as<uint8_t>(2 * dl);
+    x.dB_j = c->defer.as<uint8_t>(2 * dl + dj);
+    if (x.out) FJ_TRY(c->emitbuf.ensure(align256(sizeof(u64) * x.C) + align256(sizeof(u64) * (x.C + 1)), c->stream));
+
+    // tail nodes and head mapping
+    const auto &LT = p->layout[x.tail_from];
+    for (int k = x.tail_from; k < x.nnodes; k++) {
+        const fj::Subatom &s = p->nodes[k][0];
+        int a = s.atom;
+        int l = p->sub_level[k][0];
+        TailDev T;
+        memset(&T, 0, sizeof(T));
+        T.atom = a;
+        T.level = l;
+        T.nk = s.nv;
+        for (int j = 0; j < s.nv; j++) {
+            T.kvar[j] = s.vars[j];
+            T.kcol[j] = colts[a]->lev[l].kcol[j];
+        }
+        for (int j = 0; j < FJ_MAX_COLS; j++) T.cols[j] = colts[a]->cols[j];
+        T.root_len = colts[a]->nroot;
+        T.L = colts[a]->lev[l];
+        x.tails.push_back(T);
+    }
+    for (int j = 0; j < q->nhead; j++) {
+        int v = q->head[j];
+        int src = 0;
+        bool found = false;
+        for (size_t i = 0; i < LT.in_var.size(); i++)
+            if (LT.in_var[i] == v) { src = (int)i; found = true; }
+        for (size_t t = 0; t < x.tails.size() && !found; t++)
+            for (int cc = 0; cc < x.tails[t].nk; cc++)
+                if (x.tails[t].kvar[cc] == v) { src = -((int)t * FJ_MAX_COLS + cc) - 1; found = true; }
+        if (!found) return fail(FJ_ERR_ARG, "head variable not bound by the plan");
+        x.head_src.push_back(src);
+    }
+
+    // node descriptors
+    size_t nd_bytes = align256(sizeof(NodeDev) * std::max(x.tail_from, 1));
+    size_t em_bytes = align256(fj::emit_dev_size());
+    FJ_TRY(c->desc.ensure(nd_bytes + em_bytes, c->stream));
+    if (c->desc_h_bytes < std::max(nd_bytes, em_bytes)) {
+        FJ_HIP(hipStreamSynchronize(c->stream));
+        if (c->desc_h) hipHostFree(c->desc_h);
+        c->desc_h = nullptr;
+        c->desc_h_bytes = 0;
+        FJ_HIP(hipHostMalloc(&c->desc_h, std::max(nd_bytes, em_bytes), hipHostMallocDefault));
+        c->desc_h_bytes = std::max(nd_bytes, em_bytes);
+    }
+    x.nd_d = c->desc.as<NodeDev>(0);
+    x.emit_d = c->desc.as<char>(nd_bytes);
+    FJ_HIP(hipStreamSynchronize(c->stream));  // desc_h may still feed an earlier copy
+    NodeDev *ndh = (NodeDev *)c->desc_h;
+    for (int k = 0; k < x.tail_from; k++) {
+        NodeDev &nd = ndh[k];
+        memset(&nd, 0, sizeof(nd));
+        const auto &L = p->layout[k];
+        const auto &LN = p->layout[k + 1];
+        nd.k = k;
+        nd.nsub = (int)p->nodes[k].size();
+        nd.npure = (int)L.pure.size();
+        for (int i = 0; i < nd.npure; i++) nd.pure[i] = L.pure[i];
+        int slot_of[FJ_MAX_VARS];
+        for (int v = 0; v < FJ_MAX_VARS; v++) slot_of[v] = -1;
+        nd.nin = (int)L.in_var.size();
+        for (int i = 0; i < nd.nin; i++) slot_of[L.in_var[i]] = i;
+        nd.nnew = (int)L.new_vars.size();
+        for (int i = 0; i < nd.nnew; i++) slot_of[L.new_vars[i]] = nd.nin + i;
+        for (int i = 0; i < nd.nsub; i++) {
+            const fj::Subatom &s = p->nodes[k][i];
+            SubDev &S = nd.sub[i];
+            int a = s.atom;
+            int l = p->sub_level[k][i];
+            S.atom = a;
+            S.level = l;
+            S.last = (l == p->nlev[a] - 1);
+            S.child_leaf = (l + 1 == p->nlev[a]);
+            S.nk = s.nv;
+            S.fq_slot = a * fj::kMaxLevels + l;
+            for (int j = 0; j < s.nv; j++) {
+                S.kslot[j] = slot_of[s.vars[j]];
+                S.kcol[j] = colts[a]->lev[l].kcol[j];
+            }
+            fill_level_sub(S, colts[a], l);
+        }
+        nd.nin_h = (int)L.in_hatom.size();
+        for (int i = 0; i < nd.nin_h; i++) nd.in_h_atom[i] = L.in_hatom[i];
+        nd.nout = (int)LN.in_var.size();
+        for (int i = 0; i < nd.nout; i++) nd.out_slot[i] = slot_of[LN.in_var[i]];
+        nd.nout_h = (int)LN.in_hatom.size();
+        for (int i = 0; i < nd.nout_h; i++) nd.out_h_atom[i] = LN.in_hatom[i];
+        nd.emit = (k == x.tail_from - 1);
+        nd.materialize = nd.emit && x.out != nullptr;
+        if (nd.emit) {
+            nd.ntail = (int)x.tails.size();
+            for (int i = 0; i < nd.ntail; i++) nd.tail[i] = x.tails[i];
+        }
+        nd.in = x.F[k];
+        nd.out = x.F[k + 1];
+    }
+    if (x.tail_from > 0)
+        FJ_HIP(hipMemcpyAsync(x.nd_d, ndh, sizeof(NodeDev) * x.tail_from, hipMemcpyHostToDevice, c->stream));
+    if (x.out) {
+        // the emit descriptor follows the node descriptors in the staging buffer
+        FJ_HIP(hipStreamSynchronize(c->stream));
+        fj::emit_dev_fill(c->desc_h, x.F[x.tail_from], p->layout[x.tail_from].in_var, p->layout[x.tail_from].in_hatom,
+                          x.tails.data(), (int)x.tails.size(), x.head_src.data(), (int)x.head_src.size(), x.out,
+                          x.cap);
+        FJ_HIP(hipMemcpyAsync(x.emit_d, c->desc_h, fj::emit_dev_size(), hipMemcpyHostToDevice, c->stream));
+        FJ_HIP(hipStreamSynchronize(c->stream));
+    }
+
+    FJ_HIP(hipMemsetAsync(c->status_d, 0, sizeof(StatusDev), c->stream));
+    fj_status st;
+    if (x.tail_from == 0) {
+        // every node is a product of base tables: one empty binding
+        FJ_HIP(hipStreamSynchronize(c->stream));
+        u64 total = 1;
+        for (const auto &T : x.tails) total *= T.root_len;
+        c->status_h->count = total;
+        FJ_HIP(hipMemcpyAsync(c->status_d, c->status_h, sizeof(u64), hipMemcpyHostToDevice, c->stream));
+        st = x.out ? emit_rows(x, 1) : FJ_OK;
+    } else {
+        st = exec_node(x, 0, 1);
+    }
+    if (st != FJ_OK) return st;
+    FJ_TRY(sync_status(c));
+    *count = c->status_h->count;
+    if (written) *written = x.written;
+    if (stats) {
+        for (int k = 0; k < x.tail_from; k++) {
+            stats->probe[k] = c->status_h->probe[k];
+            stats->hit[k] = c->status_h->hit[k];
+        }
+        if (x.tail_from > 0) stats->survivors[x.tail_from - 1] = 0;
+    }
+    return (x.out && *count > x.cap) ? FJ_TRUNCATED : FJ_OK;
+}

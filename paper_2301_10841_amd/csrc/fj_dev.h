@@ -1,0 +1,130 @@
+// Device-side data layout of COLT levels, plan nodes and frontiers, shared by
+// the HIP kernels and the host orchestration in libfj.  Internal header.
+//
+// Position space.  Every level of one atom's COLT uses the same positions
+// [0, nroot): the root handle owns [0, nroot); when a handle owning
+// [p, p + len) at level l is forced, its children at level l + 1 own disjoint
+// sub-ranges of [p, p + len) holding the same row offsets regrouped by key.
+// A handle is therefore identified by the start position of its range, and
+// per-handle metadata lives in position-indexed arrays of each level.
+#pragma once
+
+#include <cstdint>
+
+#include "fj.h"
+
+namespace fj {
+
+constexpr int kMaxLevels = FJ_MAX_NODES;   // schema levels per atom
+constexpr uint32_t kQueued = 0xFFFFFFFFu;  // state word: force requested
+constexpr uint32_t kEmpty32 = 0xFFFFFFFFu;
+constexpr unsigned long long kEmpty64 = ~0ull;
+
+// Hash-map layouts of one level, chosen by key width.
+enum KeyMode : int {
+    KM_K32 = 0,   // root level, one key column:  slot {u32 key, u32 val}
+    KM_K64 = 1,   // packed 64-bit key (root with two key columns, or
+                  // (handle, value) below the root): slot {u64 key, u32 val, pad}
+    KM_REP = 2,   // wider keys: slot {u32 handle, u32 representative row, u32 val, pad},
+                  // compared column by column against the representative row
+    KM_ZERO = 3   // a level with no variables: one key, no table
+};
+
+struct Slot32 { uint32_t key; uint32_t val; };
+struct alignas(16) Slot64 { unsigned long long key; uint32_t val; uint32_t pad; };
+struct alignas(16) SlotRep { unsigned long long hr; uint32_t val; uint32_t pad; };  // hr = row << 32 | handle
+
+// One level of one atom's COLT.  The leaf level (index nlev) only uses offs/len.
+struct LevelDev {
+    uint32_t *offs;      // row offsets by position (root: selection, or null = identity)
+    uint32_t *len;       // len[p] of the handle starting at p
+    uint32_t *st;        // 0 = unforced, kQueued, else (number of keys + 1)
+    uint32_t *kl;        // kl[p + r] = start of the child with rank r of handle p
+    void *table;         // hash slots, mask + 2 entries (the last is the reserved slot)
+    unsigned long long mask;
+    uint32_t *rank_ctr;  // per handle: distinct keys seen while forcing
+    uint32_t *cnt;       // per child rank position: offsets while forcing (returns to 0)
+    uint32_t *fq;        // force queue: handle starts
+    int mode;
+    int nk;
+    int kcol[FJ_MAX_COLS];
+    uint32_t npos;       // entries of every position-indexed array (>= 1)
+    uint32_t nrows;      // rows of the relation's columns
+    unsigned long long nslots;  // hash slots including the reserved one (0: no map)
+};
+
+struct SubDev {
+    int atom;
+    int level;
+    int last;        // level == nlev - 1
+    int child_leaf;  // level + 1 == nlev: a get reaches an offset vector (a multiplicity)
+    int nk;
+    int fq_slot;     // index of this (atom, level) in the status block's queue counters
+    int kslot[FJ_MAX_COLS];   // thread value slot of each key variable
+    int kcol[FJ_MAX_COLS];    // atom column of each key variable
+    const int32_t *cols[FJ_MAX_COLS];  // the atom's columns
+    uint32_t root_len;        // level 0: number of root offsets
+    LevelDev L;               // this level
+    LevelDev C;               // the child level
+};
+
+struct TailDev {
+    int atom;
+    int level;
+    int nk;
+    int kcol[FJ_MAX_COLS];
+    int kvar[FJ_MAX_COLS];
+    const int32_t *cols[FJ_MAX_COLS];
+    uint32_t root_len;
+    LevelDev L;
+};
+
+// A frontier: values of the bound variables and current handles of the
+// atoms part-way through their schemas, structure of arrays, `cap` rows.
+struct FrontierDev {
+    int32_t *vals;     // nvals columns of cap
+    uint32_t *hdl;     // nhdl columns of cap
+    unsigned long long *mult;
+    unsigned long long cap;
+    int nvals;
+    int nhdl;
+};
+
+struct NodeDev {
+    int k;
+    int nsub;
+    int npure;
+    int pure[FJ_MAX_ATOMS];
+    SubDev sub[FJ_MAX_ATOMS];
+    int nin;                       // input value columns -> slots [0, nin)
+    int nnew;                      // new variables -> slots [nin, nin + nnew)
+    int nin_h;
+    int in_h_atom[FJ_MAX_ATOMS];   // input handle column j -> atom
+    int nout;
+    int out_slot[FJ_MAX_VARS];     // output value column j <- slot
+    int nout_h;
+    int out_h_atom[FJ_MAX_ATOMS];  // output handle column j <- atom
+    int emit;                      // survivors are results (this is the last probed node)
+    int materialize;               // emit: also write survivors to the output frontier
+    int ntail;
+    TailDev tail[FJ_MAX_NODES];
+    FrontierDev in;
+    FrontierDev out;
+};
+
+// Host <-> device status block, one per context.
+struct StatusDev {
+    unsigned long long count;      // result tuples so far
+    unsigned long long survivors;  // rows written to the output frontier by the last launch
+    unsigned long long deferred;   // tuples waiting for a lazy force
+    unsigned long long total;      // scan totals
+    unsigned long long probe[FJ_MAX_NODES];
+    unsigned long long hit[FJ_MAX_NODES];
+    uint32_t fq_n[FJ_MAX_ATOMS * kMaxLevels];  // force-queue lengths per (atom, level)
+    uint32_t pending;              // entries whose cover had to be forced first
+    uint32_t total32;              // 32-bit scan totals
+    uint32_t err_line;             // first failed device bounds check (source line)
+    uint32_t err_count;            // failed device bounds checks
+};
+
+}  // namespace fj

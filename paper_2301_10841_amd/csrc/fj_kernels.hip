@@ -1,0 +1,910 @@
+// HIP kernels of the Free Join executor for gfx950 (wave64).
+//
+//  * selection push-down:   filter_lt                       (Section 2.1)
+//  * COLT force:            force_* pipeline, used both for the root build
+//                           and for lazy forcing of inner sub-tries
+//                           (Section 4.2, figure "colt-impl", force())
+//  * cover choice:          cover_choose / cover_fill        (Section 4.4)
+//  * probe / intersect:     probe                           (Section 3.3 figure
+//                           "fj-algo", vectorized as in Section 4.3)
+//  * output:                emit_count / emit_rows          (bag multiplicities)
+//  * scans:                 exclusive prefix sums used for load balancing
+//
+// No kernel here is a dense contraction, so nothing uses MFMA; every kernel is
+// bound by HBM or L2/MALL traffic and written for coalesced streams, wave64
+// ballots and one atomic per wave.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "fj_dev.h"
+#include "fj_launch.h"
+
+namespace fj {
+
+typedef unsigned long long u64;
+
+constexpr uint32_t kClaim = 0x80000000u;
+
+// ----------------------------------------------------------------- hashing
+// MurmurHash3 finalizers (Appleby): full avalanche for 32- and 64-bit keys.
+__device__ __forceinline__ uint32_t mix32(uint32_t h) {
+    h ^= h >> 16; h *= 0x85ebca6bu; h ^= h >> 13; h *= 0xc2b2ae35u; h ^= h >> 16;
+    return h;
+}
+__device__ __forceinline__ u64 mix64(u64 k) {
+    k ^= k >> 33; k *= 0xff51afd7ed558ccdull; k ^= k >> 33; k *= 0xc4ceb9fe1a85ec53ull; k ^= k >> 33;
+    return k;
+}
+
+struct Key {
+    uint32_t h;                  // handle (start position) of the probed trie
+    int32_t v[FJ_MAX_COLS];
+};
+
+__device__ __forceinline__ u64 pack64(const LevelDev &L, const Key &k) {
+    // root with two key columns: (v0, v1); below the root: (handle, v0)
+    return L.nk == 2 ? ((u64)(uint32_t)k.v[0] << 32) | (uint32_t)k.v[1]
+                     : ((u64)k.h << 32) | (uint32_t)k.v[0];
+}
+
+__device__ __forceinline__ u64 rep_hash(const Key &k, int nk) {
+    u64 x = mix64(((u64)k.h << 32) ^ 0x9E3779B97F4A7C15ull);
+    for (int j = 0; j < nk; j++) x = mix64(x ^ (u64)(uint32_t)k.v[j]);
+    return x;
+}
+
+__device__ __forceinline__ bool rep_equal(const LevelDev &L, const int32_t *const *cols, uint32_t row,
+                                          const Key &k) {
+    for (int j = 0; j < L.nk; j++)
+        if (cols[L.kcol[j]][row] != k.v[j]) return false;
+    return true;
+}
+
+// get(): the slot of key k in level L's map, or ~0 when absent.  Every hit
+// compares the full key.  Tables are immutable while probes run.
+__device__ __forceinline__ u64 table_find(const LevelDev &L, const int32_t *const *cols, const Key &k) {
+    const u64 mask = L.mask;
+    if (L.mode == KM_K32) {
+        const Slot32 *T = (const Slot32 *)L.table;
+        uint32_t key = (uint32_t)k.v[0];
+        if (key == kEmpty32) return T[mask + 1].key ? mask + 1 : ~0ull;
+        u64 i = mix32(key) & mask;
+        for (u64 n = 0; n <= mask; n++) {
+            uint32_t c = T[i].key;
+            if (c == key) return i;
+            if (c == kEmpty32) return ~0ull;
+            i = (i + 1) & mask;
+        }
+    } else if (L.mode == KM_K64) {
+        const Slot64 *T = (const Slot64 *)L.table;
+        u64 key = pack64(L, k);
+        if (key == kEmpty64) return T[mask + 1].key ? mask + 1 : ~0ull;
+        u64 i = mix64(key) & mask;
+        for (u64 n = 0; n <= mask; n++) {
+            u64 c = T[i].key;
+            if (c == key) return i;
+            if (c == kEmpty64) return ~0ull;
+            i = (i + 1) & mask;
+        }
+    } else {
+        const SlotRep *T = (const SlotRep *)L.table;
+        u64 i = rep_hash(k, L.nk) & mask;
+        for (u64 n = 0; n <= mask; n++) {
+            u64 c = T[i].hr;
+            if (c == kEmpty64) return ~0ull;
+            if ((uint32_t)c == k.h && (uint32_t)(c >> 32) < L.nrows &&
+                rep_equal(L, cols, (uint32_t)(c >> 32), k)) return i;
+            i = (i + 1) & mask;
+        }
+    }
+    return L.nslots;  // no empty slot: the map is corrupt (callers check the index)
+}
+
+__device__ __forceinline__ uint32_t slot_val(const LevelDev &L, u64 i) {
+    if (L.mode == KM_K32) return ((const Slot32 *)L.table)[i].val;
+    if (L.mode == KM_K64) return ((const Slot64 *)L.table)[i].val;
+    return ((const SlotRep *)L.table)[i].val;
+}
+
+__device__ __forceinline__ void set_slot_val(const LevelDev &L, u64 i, uint32_t v) {
+    if (L.mode == KM_K32) ((Slot32 *)L.table)[i].val = v;
+    else if (L.mode == KM_K64) ((Slot64 *)L.table)[i].val = v;
+    else ((SlotRep *)L.table)[i].val = v;
+}
+
+// Insert-or-find for force(); `row` is the representative row for KM_REP.
+__device__ __forceinline__ u64 table_insert(const LevelDev &L, const int32_t *const *cols, const Key &k,
+                                            uint32_t row, bool &claimed) {
+    const u64 mask = L.mask;
+    claimed = false;
+    if (L.mode == KM_K32) {
+        Slot32 *T = (Slot32 *)L.table;
+        uint32_t key = (uint32_t)k.v[0];
+        if (key == kEmpty32) {
+            claimed = atomicCAS(&T[mask + 1].key, 0u, 1u) == 0u;
+            return mask + 1;
+        }
+        u64 i = mix32(key) & mask;
+        for (u64 n = 0; n <= mask; n++) {
+            uint32_t c = __atomic_load_n(&T[i].key, __ATOMIC_RELAXED);
+            if (c == key) return i;
+            if (c == kEmpty32) {
+                uint32_t old = atomicCAS(&T[i].key, kEmpty32, key);
+                if (old == kEmpty32) { claimed = true; return i; }
+                if (old == key) return i;
+            }
+            i = (i + 1) & mask;
+        }
+    } else if (L.mode == KM_K64) {
+        Slot64 *T = (Slot64 *)L.table;
+        u64 key = pack64(L, k);
+        if (key == kEmpty64) {
+            claimed = atomicCAS(&T[mask + 1].key, 0ull, 1ull) == 0ull;
+            return mask + 1;
+        }
+        u64 i = mix64(key) & mask;
+        for (u64 n = 0; n <= mask; n++) {
+            u64 c = __atomic_load_n(&T[i].key, __ATOMIC_RELAXED);
+            if (c == key) return i;
+            if (c == kEmpty64) {
+                u64 old = atomicCAS(&T[i].key, kEmpty64, key);
+                if (old == kEmpty64) { claimed = true; return i; }
+                if (old == key) return i;
+            }
+            i = (i + 1) & mask;
+        }
+    } else {
+        SlotRep *T = (SlotRep *)L.table;
+        u64 mine = ((u64)row << 32) | k.h;
+        u64 i = rep_hash(k, L.nk) & mask;
+        for (u64 n = 0; n <= mask; n++) {
+            u64 c = __atomic_load_n(&T[i].hr, __ATOMIC_RELAXED);
+            if (c == kEmpty64) {
+                u64 old = atomicCAS(&T[i].hr, kEmpty64, mine);
+                if (old == kEmpty64) { claimed = true; return i; }
+                c = old;
+            }
+            if ((uint32_t)c == k.h && (uint32_t)(c >> 32) < L.nrows &&
+                rep_equal(L, cols, (uint32_t)(c >> 32), k)) return i;
+            i = (i + 1) & mask;
+        }
+    }
+    return L.nslots;  // the map is full: callers check the index
+}
+
+// ------------------------------------------------------------ wave helpers
+__device__ __forceinline__ u64 wave_sum_u64(u64 v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Wave-aggregated reservation: returns this lane's slot for `pred` lanes.
+__device__ __forceinline__ u64 wave_reserve(bool pred, u64 *counter) {
+    const u64 mask = __ballot(pred);
+    const int lane = __lane_id();
+    const int n = __popcll(mask);
+    u64 base = 0;
+    const int leader = n ? (__ffsll((long long)mask) - 1) : 0;
+    if (n && lane == leader) base = atomicAdd(counter, (u64)n);
+    base = __shfl(base, leader, 64);
+    return base + __popcll(mask & ((1ull << lane) - 1ull));
+}
+
+__device__ __forceinline__ uint32_t upper_entry(const u64 *starts, uint32_t lo, uint32_t hi, u64 g) {
+    // largest e in [lo, hi) with starts[e] <= g (starts non-decreasing, starts[lo] <= g)
+    while (hi - lo > 1) {
+        uint32_t mid = lo + ((hi - lo) >> 1);
+        if (starts[mid] <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t upper_entry32(const uint32_t *starts, uint32_t lo, uint32_t hi, uint32_t g) {
+    while (hi - lo > 1) {
+        uint32_t mid = lo + ((hi - lo) >> 1);
+        if (starts[mid] <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------------ fills
+template <typename T>
+__global__ void k_fill(T *p, u64 n, T v) {
+    u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    u64 stride = (u64)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_table_init(void *table, u64 nslots, int mode) {
+    // all slots empty; the reserved last slot starts at 0 (unclaimed)
+    u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    u64 stride = (u64)gridDim.x * blockDim.x;
+    for (; i < nslots; i += stride) {
+        bool last = (i + 1 == nslots);
+        if (mode == KM_K32) {
+            Slot32 s; s.key = last ? 0u : kEmpty32; s.val = 0; ((Slot32 *)table)[i] = s;
+        } else if (mode == KM_K64) {
+            Slot64 s; s.key = last ? 0ull : kEmpty64; s.val = 0; s.pad = 0; ((Slot64 *)table)[i] = s;
+        } else {
+            SlotRep s; s.hr = kEmpty64; s.val = 0; s.pad = 0; ((SlotRep *)table)[i] = s;
+        }
+    }
+}
+
+__global__ void k_root_init(LevelDev L, uint32_t nroot) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        L.len[0] = nroot;
+        L.st[0] = 0;
+        if (L.fq) L.fq[0] = 0;
+    }
+}
+
+// ------------------------------------------------------------------ scans
+// Exclusive scan of n values (u32 or u64) in three phases: per-block sums,
+// a single-block scan of the sums, and a per-block rescan with offsets.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T *lds, T &total) {
+    // v: per-thread value; returns exclusive prefix over the block
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    T x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        T y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) lds[wid] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T run = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); w++) { T t = lds[w]; lds[w] = run; run += t; }
+        lds[16] = run;
+    }
+    __syncthreads();
+    T r = lds[wid] + x - v;
+    total = lds[16];
+    __syncthreads();
+    return r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const T *in, u64 n, T *bsum) {
+    __shared__ T lds[17];
+    u64 base = (u64)blockIdx.x * kScanTile + (u64)threadIdx.x * kScanItems;
+    T s = 0;
+    for (int j = 0; j < kScanItems; j++) if (base + j < n) s += in[base + j];
+    T tot;
+    block_excl_scan<T>(s, lds, tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kScanThreads) k_scan_blocks(T *bsum, u64 nb, T *total_out) {
+    __shared__ T lds[17];
+    T carry = 0;
+    for (u64 c = 0; c < nb; c += kScanThreads) {
+        u64 i = c + threadIdx.x;
+        T v = i < nb ? bsum[i] : 0;
+        T tot;
+        T ex = block_excl_scan<T>(v, lds, tot);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply(const T *in, T *out, u64 n, const T *bsum) {
+    __shared__ T lds[17];
+    u64 base = (u64)blockIdx.x * kScanTile + (u64)threadIdx.x * kScanItems;
+    T v[kScanItems];
+    T s = 0;
+    for (int j = 0; j < kScanItems; j++) { v[j] = (base + j < n) ? in[base + j] : 0; s += v[j]; }
+    T tot;
+    T ex = block_excl_scan<T>(s, lds, tot) + bsum[blockIdx.x];
+    for (int j = 0; j < kScanItems; j++) {
+        if (base + j < n) out[base + j] = ex;
+        ex += v[j];
+    }
+}
+
+template <typename T>
+__global__ void k_scan_total(T *out, u64 n, const T *total) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) out[n] = *total;
+}
+
+// ----------------------------------------------------------------- filter
+// sigma_{col < bound}: row offsets of passing rows, wave-compacted.
+__global__ void __launch_bounds__(256) k_filter_lt(const int32_t *__restrict__ col, u64 n, int32_t bound,
+                                                   uint32_t *__restrict__ out, u64 *counter) {
+    u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    u64 stride = (u64)gridDim.x * blockDim.x;
+    u64 nround = (n + stride - 1) / stride * stride;
+    for (; i < nround; i += stride) {
+        bool pass = i < n && col[i] < bound;
+        u64 pos = wave_reserve(pass, counter);
+        if (pass) out[pos] = (uint32_t)i;
+    }
+}
+
+// ------------------------------------------------------------------ checks
+// Every indexed access of the join kernels is checked against the size of
+// the array it touches.  A failed check records the source line in the status
+// block and the access is skipped, so corrupt state becomes an error status on
+// the host instead of a memory fault.
+__device__ __noinline__ void fj_bad(StatusDev *st, int line) {
+    atomicCAS(&st->err_line, 0u, (uint32_t)line);
+    atomicAdd(&st->err_count, 1u);
+}
+#define CK(cond) ((cond) ? true : (fj_bad(status, __LINE__), false))
+
+// ------------------------------------------------------------------ force
+// force() of every handle in a queue (atom a, level l): regroup each
+// handle's offsets by the level's key into child segments of level l + 1
+// occupying the handle's own position range, and fill the level's map with
+// (handle, key) -> child start.
+
+struct ForceArgs {
+    LevelDev L;
+    LevelDev C;
+    const int32_t *cols[FJ_MAX_COLS];
+    const uint32_t *fq;     // queued handle starts
+    uint32_t nh;            // number of queued handles
+    const uint32_t *pre;    // exclusive scan of their lengths (nh + 1)
+    uint32_t W;             // total offsets
+    uint32_t wcap;          // capacity of the per-item scratch arrays
+    uint32_t *wslot;        // per item: slot index (low 32 bits)
+    uint32_t *wrank;        // per item: rank | kClaim
+    uint32_t *cntv;         // per item: cnt of child position
+    uint32_t *ex;           // per item: exclusive scan of cntv
+    StatusDev *status;
+};
+
+// Locate work item w: queue entry j, handle p, index i in it, base row.
+__device__ __forceinline__ bool force_item(const ForceArgs &a, uint32_t w, uint32_t &j, uint32_t &p,
+                                           uint32_t &i, uint32_t &row) {
+    StatusDev *status = a.status;
+    j = a.nh == 1 ? 0u : upper_entry32(a.pre, 0, a.nh, w);
+    if (!CK(j < a.nh)) return false;
+    p = a.fq[j];
+    i = w - a.pre[j];
+    if (!CK((u64)p + i < a.L.npos && w < a.wcap)) return false;
+    row = a.L.offs ? a.L.offs[p + i] : p + i;
+    return CK(row < a.L.nrows);
+}
+
+__global__ void __launch_bounds__(256) k_fq_lens(LevelDev L, const uint32_t *fq, uint32_t nh, uint32_t *lens,
+                                                 StatusDev *status) {
+    uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nh) return;
+    uint32_t p = fq[j];
+    lens[j] = CK(p < L.npos) ? L.len[p] : 0u;
+}
+
+__global__ void __launch_bounds__(256) k_force_insert(ForceArgs a) {
+    StatusDev *status = a.status;
+    uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= a.W) return;
+    uint32_t j, p, i, row;
+    if (!force_item(a, w, j, p, i, row)) return;
+    if (a.L.mode == KM_ZERO) {
+        if (i == 0) a.L.rank_ctr[p] = 1;
+        a.wrank[w] = i == 0 ? (0u | kClaim) : 0u;
+        return;
+    }
+    Key k;
+    k.h = p;
+    for (int c = 0; c < a.L.nk; c++) k.v[c] = a.cols[a.L.kcol[c]][row];
+    bool claimed;
+    u64 sl = table_insert(a.L, a.cols, k, row, claimed);
+    if (!CK(sl < a.L.nslots)) return;
+    a.wslot[w] = (uint32_t)sl;
+    if (claimed) {
+        uint32_t r = atomicAdd(&a.L.rank_ctr[p], 1u);
+        set_slot_val(a.L, sl, r);
+        a.wrank[w] = r | kClaim;
+    } else {
+        a.wrank[w] = 0;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_force_count(ForceArgs a) {
+    StatusDev *status = a.status;
+    uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= a.W) return;
+    uint32_t j, p, i, row;
+    if (!force_item(a, w, j, p, i, row)) return;
+    uint32_t r = a.wrank[w];
+    if (!(r & kClaim)) {
+        if (a.L.mode == KM_ZERO) r = 0u;
+        else if (CK(a.wslot[w] < a.L.nslots)) r = slot_val(a.L, a.wslot[w]);
+        else return;
+        a.wrank[w] = r;
+    } else {
+        r &= ~kClaim;
+    }
+    if (!CK((u64)p + r < a.L.npos)) return;
+    atomicAdd(&a.L.cnt[p + r], 1u);
+}
+
+__global__ void __launch_bounds__(256) k_force_cntv(ForceArgs a) {
+    uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= a.W) return;
+    uint32_t j, p, i, row;
+    if (!force_item(a, w, j, p, i, row)) return;
+    a.cntv[w] = a.L.cnt[p + i];
+}
+
+__global__ void __launch_bounds__(256) k_force_children(ForceArgs a) {
+    StatusDev *status = a.status;
+    uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= a.W) return;
+    uint32_t j, p, i, row;
+    if (!force_item(a, w, j, p, i, row)) return;
+    uint32_t nkeys = a.L.rank_ctr[p];
+    if (i < nkeys) {
+        uint32_t s = p + (a.ex[w] - a.pre[j]);
+        if (!CK(s < a.C.npos)) return;
+        a.L.kl[p + i] = s;
+        a.C.len[s] = a.L.cnt[p + i];
+    }
+    if (i == 0) a.L.st[p] = nkeys + 1;
+}
+
+__global__ void __launch_bounds__(256) k_force_scatter(ForceArgs a) {
+    StatusDev *status = a.status;
+    uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= a.W) return;
+    uint32_t j, p, i, row;
+    if (!force_item(a, w, j, p, i, row)) return;
+    uint32_t rw = a.wrank[w];
+    uint32_t r = rw & ~kClaim;
+    if (!CK((u64)p + r < a.L.npos)) return;
+    uint32_t s = a.L.kl[p + r];
+    uint32_t pos = s + atomicSub(&a.L.cnt[p + r], 1u) - 1u;
+    if (!CK(pos < a.C.npos && pos >= p && pos < p + a.L.len[p])) return;
+    a.C.offs[pos] = row;
+    if ((rw & kClaim) && a.L.mode != KM_ZERO) set_slot_val(a.L, a.wslot[w], s);
+}
+
+// ----------------------------------------------------------- cover choice
+// Per input binding: among the node's pure covers pick the one whose current
+// trie has the fewest keys (a forced map's key count, an unforced vector's
+// length), first on ties (Section 4.4).  A last-level unforced vector is
+// iterated by offset; anything else is iterated by key, forcing it first.
+
+__device__ __forceinline__ uint32_t handle_of(const SubDev &S, const FrontierDev &F, const NodeDev &nd,
+                                              uint32_t e) {
+    if (S.level == 0) return 0u;
+    for (int j = 0; j < nd.nin_h; j++)
+        if (nd.in_h_atom[j] == S.atom) return F.hdl[(u64)j * F.cap + e];
+    return 0xFFFFFFFFu;
+}
+
+__device__ __forceinline__ uint32_t trie_len(const SubDev &S, uint32_t p) {
+    return S.level == 0 ? S.root_len : S.L.len[p];
+}
+
+__global__ void __launch_bounds__(256) k_cover_choose(const NodeDev *__restrict__ ndp, uint32_t E, uint8_t *cov,
+                                                      u64 *cnt, StatusDev *status) {
+    const NodeDev &nd = *ndp;
+    uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    cov[e] = 0;
+    cnt[e] = 0;
+    if (!CK(e < nd.in.cap)) return;
+    int best = -1;
+    uint32_t best_est = 0, best_p = 0, best_st = 0;
+    for (int q = 0; q < nd.npure; q++) {
+        const SubDev &S = nd.sub[nd.pure[q]];
+        uint32_t p = handle_of(S, nd.in, nd, e);
+        if (!CK(p < S.L.npos)) return;
+        uint32_t st = S.L.st[p];
+        uint32_t est = (st != 0 && st != kQueued) ? st - 1 : trie_len(S, p);
+        if (best < 0 || est < best_est) { best = q; best_est = est; best_p = p; best_st = st; }
+    }
+    const SubDev &S = nd.sub[nd.pure[best]];
+    bool forced = best_st != 0 && best_st != kQueued;
+    uint8_t keys_mode = 0;
+    u64 n;
+    if (forced) { keys_mode = 1; n = best_st - 1; }
+    else if (S.last) { keys_mode = 0; n = trie_len(S, best_p); }
+    else {
+        // iter() on a vector that is not the last level: force it first
+        keys_mode = 1; n = 0;
+        if (!CK(S.level > 0)) return;
+        if (atomicCAS(&S.L.st[best_p], 0u, kQueued) == 0u) {
+            uint32_t pos = atomicAdd(&status->fq_n[S.fq_slot], 1u);
+            if (CK(pos < S.L.npos)) S.L.fq[pos] = best_p;
+        }
+        atomicAdd(&status->pending, 1u);
+    }
+    cov[e] = (uint8_t)(nd.pure[best] | (keys_mode << 7));
+    cnt[e] = n;
+}
+
+__global__ void __launch_bounds__(256) k_cover_fill(const NodeDev *__restrict__ ndp, uint32_t E, const uint8_t *cov,
+                                                    u64 *cnt, StatusDev *status) {
+    const NodeDev &nd = *ndp;
+    uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    uint8_t c = cov[e];
+    if (!(c & 0x80)) return;
+    const SubDev &S = nd.sub[c & 0x7F];
+    uint32_t p = handle_of(S, nd.in, nd, e);
+    if (!CK(p < S.L.npos)) { cnt[e] = 0; return; }
+    uint32_t st = S.L.st[p];
+    if (!CK(st != 0 && st != kQueued)) { cnt[e] = 0; return; }
+    cnt[e] = st - 1;
+}
+
+// ------------------------------------------------------------------ probe
+// One thread per cover tuple of the tile.  The tuple's binding is located by
+// binary search over the scanned cover counts, its cover tuple is bound, and
+// the node's other subatoms are probed in node order with early exit.  A
+// probe that meets an unforced trie queues that trie for forcing (once, by
+// state CAS) and defers the tuple; the host forces the queue and re-runs the
+// deferred tuples from that lookup on.
+
+struct ProbeArgs {
+    const NodeDev *nd;
+    const u64 *starts;        // E + 1 scanned cover counts
+    const uint8_t *cov;
+    uint32_t E;
+    u64 t0;                   // first tuple of the tile
+    uint32_t n;               // threads' work items
+    const uint32_t *din;      // deferred mode: tuple (tile-local) and resume lookup
+    const uint8_t *din_j;
+    uint32_t *dout;           // deferrals of this launch
+    uint8_t *dout_j;
+    uint32_t dcap;            // capacity of the deferral lists
+    StatusDev *status;
+    int count_stats;
+};
+
+__global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
+    const NodeDev &nd = *a.nd;
+    StatusDev *status = a.status;
+    const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+    bool survive = false, defer = false;
+    uint32_t t = 0;
+    int resume = 0, defer_j = 0;
+    u64 mult = 1, emitv = 0;
+    uint32_t nprobe = 0, nhit = 0;
+    int32_t v[FJ_MAX_VARS];
+    uint32_t h[FJ_MAX_ATOMS];
+    uint32_t e = 0;
+    bool ok = idx < a.n;
+    if (ok) {
+        if (a.din) { t = a.din[idx]; resume = a.din_j[idx]; } else { t = idx; }
+        const u64 g = a.t0 + t;
+        e = a.E == 1 ? 0u : upper_entry(a.starts, 0, a.E, g);
+        ok = CK(e < a.E && e < nd.in.cap && g >= a.starts[e] && g < a.starts[e + 1]);
+    }
+    if (ok) {
+        const u64 i = a.t0 + t - a.starts[e];
+        const FrontierDev &F = nd.in;
+        for (int j = 0; j < nd.nin; j++) v[j] = F.vals[(u64)j * F.cap + e];
+        for (int j = 0; j < nd.nin_h; j++) h[nd.in_h_atom[j]] = F.hdl[(u64)j * F.cap + e];
+        mult = F.mult ? F.mult[e] : 1ull;
+        // bind the cover tuple
+        const uint8_t cb = a.cov[e];
+        const int ci = cb & 0x7F;
+        const SubDev &S = nd.sub[ci];
+        const uint32_t p = S.level == 0 ? 0u : h[S.atom];
+        if (cb & 0x80) {
+            ok = CK(p + i < S.L.npos);
+            const uint32_t s = ok ? S.L.kl[p + (uint32_t)i] : 0u;
+            ok = ok && CK(s < S.C.npos);
+            const uint32_t row = ok ? S.C.offs[s] : 0u;
+            ok = ok && CK(row < S.L.nrows);
+            if (ok) {
+                for (int c = 0; c < S.nk; c++) v[S.kslot[c]] = S.cols[S.kcol[c]][row];
+                if (S.child_leaf) mult *= S.C.len[s];
+                else h[S.atom] = s;
+            }
+        } else {
+            const u64 pos = p + i;
+            ok = CK(p < S.L.npos) && CK(pos < S.L.npos && i < trie_len(S, p));
+            const uint32_t row = ok ? (S.L.offs ? S.L.offs[pos] : (uint32_t)pos) : 0u;
+            ok = ok && CK(row < S.L.nrows);
+            if (ok)
+                for (int c = 0; c < S.nk; c++) v[S.kslot[c]] = S.cols[S.kcol[c]][row];
+        }
+        // lookups in node order
+        survive = ok;
+        for (int j = 0; j < nd.nsub && survive; j++) {
+            if (j == ci) continue;
+            const SubDev &P = nd.sub[j];
+            const uint32_t ph = P.level == 0 ? 0u : h[P.atom];
+            if (!CK(ph < P.L.npos)) { survive = false; break; }
+            const uint32_t st = P.L.st[ph];
+            if (st == 0 || st == kQueued) {
+                if (!CK(P.level > 0)) { survive = false; break; }
+                if (st == 0 && atomicCAS(&P.L.st[ph], 0u, kQueued) == 0u) {
+                    uint32_t pos = atomicAdd(&status->fq_n[P.fq_slot], 1u);
+                    if (CK(pos < P.L.npos)) P.L.fq[pos] = ph;
+                }
+                defer = true; defer_j = j; survive = false;
+                break;
+            }
+            uint32_t s;
+            if (j >= resume) nprobe++;
+            if (P.L.mode == KM_ZERO) {
+                // a map with no variables has one key, or none when empty
+                if (st - 1 == 0) { survive = false; break; }
+                s = P.L.kl[ph];
+            } else {
+                Key k;
+                k.h = ph;
+                for (int c = 0; c < P.nk; c++) k.v[c] = v[P.kslot[c]];
+                const u64 slot = table_find(P.L, P.cols, k);
+                if (slot == ~0ull) { survive = false; break; }
+                if (!CK(slot < P.L.nslots)) { survive = false; break; }
+                s = slot_val(P.L, slot);
+            }
+            if (!CK(s < P.C.npos)) { survive = false; break; }
+            if (j >= resume) nhit++;
+            if (P.child_leaf) mult *= P.C.len[s];
+            else h[P.atom] = s;
+        }
+        if (survive && nd.emit) {
+            emitv = mult;
+            for (int q = 0; q < nd.ntail; q++) {
+                const TailDev &T = nd.tail[q];
+                if (T.level == 0) { emitv *= (u64)T.root_len; continue; }
+                const uint32_t th = h[T.atom];
+                if (!CK(th < T.L.npos)) { survive = false; emitv = 0; break; }
+                emitv *= (u64)T.L.len[th];
+            }
+        }
+    }
+    if (a.count_stats) {
+        u64 np = wave_sum_u64(nprobe), nh = wave_sum_u64(nhit);
+        if (__lane_id() == 0 && (np | nh)) {
+            atomicAdd(&a.status->probe[nd.k], np);
+            atomicAdd(&a.status->hit[nd.k], nh);
+        }
+    }
+    if (nd.emit) {
+        u64 c = wave_sum_u64(emitv);
+        if (__lane_id() == 0 && c) atomicAdd(&a.status->count, c);
+    }
+    // deferred tuples
+    {
+        u64 pos = wave_reserve(defer, &a.status->deferred);
+        if (defer && CK(pos < a.dcap)) { a.dout[pos] = t; a.dout_j[pos] = (uint8_t)defer_j; }
+    }
+    // survivors to the output frontier
+    const bool write = survive && (!nd.emit || nd.materialize);
+    u64 pos = wave_reserve(write, &a.status->survivors);
+    if (write && CK(pos < nd.out.cap)) {
+        const FrontierDev &O = nd.out;
+        for (int j = 0; j < nd.nout; j++) O.vals[(u64)j * O.cap + pos] = v[nd.out_slot[j]];
+        for (int j = 0; j < nd.nout_h; j++) O.hdl[(u64)j * O.cap + pos] = h[nd.out_h_atom[j]];
+        if (O.mult) O.mult[pos] = mult;
+    }
+}
+
+// ------------------------------------------------------------------- emit
+// Materialization: every final binding stands for mult * prod(tail lengths)
+// result tuples; rows are laid out by a scan of those counts.
+
+struct EmitDev {
+    FrontierDev F;
+    int nin;
+    int in_var[FJ_MAX_VARS];
+    int nin_h;
+    int in_h_atom[FJ_MAX_ATOMS];
+    int ntail;
+    TailDev tail[FJ_MAX_NODES];
+    int nhead;
+    int head_src[FJ_MAX_VARS];    // >= 0: frontier value column; < 0: -(tail * FJ_MAX_COLS + c) - 1
+    int32_t *out;
+    u64 out_rows;                 // capacity of out in rows
+};
+
+__device__ __forceinline__ uint32_t emit_handle(const EmitDev &d, int atom, uint32_t e) {
+    for (int j = 0; j < d.nin_h; j++)
+        if (d.in_h_atom[j] == atom) return d.F.hdl[(u64)j * d.F.cap + e];
+    return 0xFFFFFFFFu;
+}
+
+__device__ __forceinline__ uint32_t tail_len(const EmitDev &d, const TailDev &T, uint32_t e, uint32_t &p,
+                                             StatusDev *status) {
+    if (T.level == 0) { p = 0; return T.root_len; }
+    p = emit_handle(d, T.atom, e);
+    if (!CK(p < T.L.npos)) { p = 0; return 0u; }
+    return T.L.len[p];
+}
+
+__global__ void __launch_bounds__(256) k_emit_count(const EmitDev *__restrict__ dp, uint32_t E, u64 *cnt,
+                                                    StatusDev *status) {
+    const EmitDev &d = *dp;
+    uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    if (!CK(e < d.F.cap)) { cnt[e] = 0; return; }
+    u64 v = d.F.mult ? d.F.mult[e] : 1ull;
+    for (int q = 0; q < d.ntail; q++) {
+        uint32_t p;
+        v *= tail_len(d, d.tail[q], e, p, status);
+    }
+    cnt[e] = v;
+}
+
+__global__ void __launch_bounds__(256) k_emit_rows(const EmitDev *__restrict__ dp, uint32_t E, const u64 *starts,
+                                                   u64 nrows, u64 base, StatusDev *status) {
+    const EmitDev &d = *dp;
+    u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    uint32_t e = E == 1 ? 0u : upper_entry(starts, 0, E, r);
+    if (!CK(e < E && e < d.F.cap && r >= starts[e] && r < starts[e + 1] && base + r < d.out_rows)) return;
+    u64 idx = r - starts[e];
+    uint32_t rows[FJ_MAX_NODES];
+    for (int q = d.ntail - 1; q >= 0; q--) {
+        const TailDev &T = d.tail[q];
+        uint32_t p;
+        uint32_t len = tail_len(d, T, e, p, status);
+        if (!CK(len > 0)) return;
+        uint32_t i = (uint32_t)(idx % len);
+        idx /= len;
+        uint32_t pos = p + i;
+        if (!CK(pos < T.L.npos || (T.level == 0 && pos < T.root_len))) return;
+        rows[q] = T.L.offs ? T.L.offs[pos] : pos;
+        if (!CK(rows[q] < T.L.nrows)) return;
+    }
+    int32_t *o = d.out + (base + r) * (u64)d.nhead;
+    for (int j = 0; j < d.nhead; j++) {
+        int s = d.head_src[j];
+        if (s >= 0) {
+            o[j] = d.F.vals[(u64)s * d.F.cap + e];
+        } else {
+            int z = -s - 1;
+            int q = z / FJ_MAX_COLS, c = z % FJ_MAX_COLS;
+            const TailDev &T = d.tail[q];
+            o[j] = T.cols[T.kcol[c]][rows[q]];
+        }
+    }
+}
+
+// ------------------------------------------------------------- launchers
+
+static inline unsigned blocks_for(u64 n, unsigned t) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t launch_fill_u32(uint32_t *p, u64 n, uint32_t v, hipStream_t s) {
+    if (!n) return hipSuccess;
+    unsigned b = (unsigned)std::min<u64>(blocks_for(n, 256), 65535);
+    hipLaunchKernelGGL(k_fill<uint32_t>, dim3(b), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_init(void *table, u64 nslots, int mode, hipStream_t s) {
+    unsigned b = (unsigned)std::min<u64>(blocks_for(nslots, 256), 65535);
+    hipLaunchKernelGGL(k_table_init, dim3(b), dim3(256), 0, s, table, nslots, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_root_init(const LevelDev &L, uint32_t nroot, hipStream_t s) {
+    hipLaunchKernelGGL(k_root_init, dim3(1), dim3(64), 0, s, L, nroot);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t scan_impl(const T *in, T *out, u64 n, T *bsum, T *total, hipStream_t s) {
+    // out has n + 1 entries; out[n] = total; bsum needs ceil(n / kScanTile) + 1 entries
+    u64 nb = (n + kScanTile - 1) / kScanTile;
+    if (nb == 0) {
+        hipLaunchKernelGGL(k_fill<T>, dim3(1), dim3(64), 0, s, out, (u64)1, (T)0);
+        hipLaunchKernelGGL(k_fill<T>, dim3(1), dim3(64), 0, s, total, (u64)1, (T)0);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, bsum);
+    hipLaunchKernelGGL(k_scan_blocks<T>, dim3(1), dim3(kScanThreads), 0, s, bsum, nb, total);
+    hipLaunchKernelGGL(k_scan_apply<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n,
+                       (const T *)bsum);
+    hipLaunchKernelGGL(k_scan_total<T>, dim3(1), dim3(64), 0, s, out, n, (const T *)total);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_u64(const u64 *in, u64 *out, u64 n, u64 *bsum, u64 *total, hipStream_t s) {
+    return scan_impl<u64>(in, out, n, bsum, total, s);
+}
+hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, u64 n, uint32_t *bsum, uint32_t *total,
+                           hipStream_t s) {
+    return scan_impl<uint32_t>(in, out, n, bsum, total, s);
+}
+
+hipError_t launch_filter_lt(const int32_t *col, u64 n, int32_t bound, uint32_t *out, u64 *counter, hipStream_t s) {
+    unsigned b = (unsigned)std::min<u64>(std::max<u64>(blocks_for(n, 256), 1), 8192);
+    hipLaunchKernelGGL(k_filter_lt, dim3(b), dim3(256), 0, s, col, n, bound, out, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_fq_lens(const LevelDev &L, const uint32_t *fq, uint32_t nh, uint32_t *lens, StatusDev *st,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_fq_lens, dim3(blocks_for(nh, 256)), dim3(256), 0, s, L, fq, nh, lens, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_force_phase(int phase, const ForceLaunch &f, hipStream_t s) {
+    ForceArgs a;
+    a.L = f.L; a.C = f.C;
+    for (int c = 0; c < FJ_MAX_COLS; c++) a.cols[c] = f.cols[c];
+    a.fq = f.fq; a.nh = f.nh; a.pre = f.pre; a.W = f.W;
+    a.wslot = f.wslot; a.wrank = f.wrank; a.cntv = f.cntv; a.ex = f.ex;
+    a.wcap = f.wcap; a.status = f.status;
+    dim3 g(blocks_for(f.W, 256)), b(256);
+    if (f.W == 0) return hipSuccess;
+    switch (phase) {
+        case 0: hipLaunchKernelGGL(k_force_insert, g, b, 0, s, a); break;
+        case 1: hipLaunchKernelGGL(k_force_count, g, b, 0, s, a); break;
+        case 2: hipLaunchKernelGGL(k_force_cntv, g, b, 0, s, a); break;
+        case 3: hipLaunchKernelGGL(k_force_children, g, b, 0, s, a); break;
+        case 4: hipLaunchKernelGGL(k_force_scatter, g, b, 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cover_choose(const NodeDev *nd, uint32_t E, uint8_t *cov, u64 *cnt, StatusDev *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_cover_choose, dim3(blocks_for(E, 256)), dim3(256), 0, s, nd, E, cov, cnt, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_cover_fill(const NodeDev *nd, uint32_t E, const uint8_t *cov, u64 *cnt, StatusDev *st,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_cover_fill, dim3(blocks_for(E, 256)), dim3(256), 0, s, nd, E, cov, cnt, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe(const ProbeLaunch &p, hipStream_t s) {
+    ProbeArgs a;
+    a.nd = p.nd; a.starts = p.starts; a.cov = p.cov; a.E = p.E; a.t0 = p.t0; a.n = p.n;
+    a.din = p.din; a.din_j = p.din_j; a.dout = p.dout; a.dout_j = p.dout_j;
+    a.status = p.status; a.count_stats = p.count_stats; a.dcap = p.dcap;
+    if (p.n == 0) return hipSuccess;
+    int bs = p.block > 0 ? p.block : 256;
+    hipLaunchKernelGGL(k_probe, dim3(blocks_for(p.n, bs)), dim3(bs), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit_count(const void *emit_dev, uint32_t E, u64 *cnt, StatusDev *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_emit_count, dim3(blocks_for(E, 256)), dim3(256), 0, s, (const EmitDev *)emit_dev, E, cnt,
+                       st);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit_rows(const void *emit_dev, uint32_t E, const u64 *starts, u64 nrows, u64 base,
+                            StatusDev *st, hipStream_t s) {
+    if (!nrows) return hipSuccess;
+    hipLaunchKernelGGL(k_emit_rows, dim3(blocks_for(nrows, 256)), dim3(256), 0, s, (const EmitDev *)emit_dev, E,
+                       starts, nrows, base, st);
+    return hipGetLastError();
+}
+
+size_t emit_dev_size() { return sizeof(EmitDev); }
+
+void emit_dev_fill(void *host_buf, const FrontierDev &F, const std::vector<int> &in_var,
+                   const std::vector<int> &in_h_atom, const TailDev *tails, int ntail, const int *head_src,
+                   int nhead, int32_t *out, u64 out_rows) {
+    EmitDev *d = (EmitDev *)host_buf;
+    memset(d, 0, sizeof(EmitDev));
+    d->F = F;
+    d->nin = (int)in_var.size();
+    for (int j = 0; j < d->nin; j++) d->in_var[j] = in_var[j];
+    d->nin_h = (int)in_h_atom.size();
+    for (int j = 0; j < d->nin_h; j++) d->in_h_atom[j] = in_h_atom[j];
+    d->ntail = ntail;
+    for (int q = 0; q < ntail; q++) d->tail[q] = tails[q];
+    d->nhead = nhead;
+    for (int j = 0; j < nhead; j++) d->head_src[j] = head_src[j];
+    d->out = out;
+    d->out_rows = out_rows;
+}
+
+}  // namespace fj

@@ -1,0 +1,69 @@
+// Kernel launchers of libfj (host-callable, stream-ordered).  Internal header.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "fj_dev.h"
+
+namespace fj {
+
+struct ForceLaunch {
+    LevelDev L;            // level being forced
+    LevelDev C;            // its child level
+    const int32_t *cols[FJ_MAX_COLS];
+    const uint32_t *fq;    // queued handle starts (device)
+    uint32_t nh;
+    const uint32_t *pre;   // exclusive scan of their lengths (device, nh + 1)
+    uint32_t W;            // total offsets of the queued handles
+    uint32_t *wslot, *wrank, *cntv, *ex;  // scratch, W (+1) entries each
+    uint32_t wcap;         // entries of each scratch array
+    StatusDev *status;
+};
+
+struct ProbeLaunch {
+    const NodeDev *nd;
+    const unsigned long long *starts;
+    const uint8_t *cov;
+    uint32_t E;
+    unsigned long long t0;
+    uint32_t n;
+    const uint32_t *din;
+    const uint8_t *din_j;
+    uint32_t *dout;
+    uint8_t *dout_j;
+    StatusDev *status;
+    int count_stats;
+    int block;
+    uint32_t dcap;         // capacity of the deferral lists
+};
+
+hipError_t launch_fill_u32(uint32_t *p, unsigned long long n, uint32_t v, hipStream_t s);
+hipError_t launch_table_init(void *table, unsigned long long nslots, int mode, hipStream_t s);
+hipError_t launch_root_init(const LevelDev &L, uint32_t nroot, hipStream_t s);
+hipError_t launch_scan_u64(const unsigned long long *in, unsigned long long *out, unsigned long long n,
+                           unsigned long long *bsum, unsigned long long *total, hipStream_t s);
+hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, unsigned long long n, uint32_t *bsum,
+                           uint32_t *total, hipStream_t s);
+hipError_t launch_filter_lt(const int32_t *col, unsigned long long n, int32_t bound, uint32_t *out,
+                            unsigned long long *counter, hipStream_t s);
+hipError_t launch_fq_lens(const LevelDev &L, const uint32_t *fq, uint32_t nh, uint32_t *lens, StatusDev *st,
+                          hipStream_t s);
+hipError_t launch_force_phase(int phase, const ForceLaunch &f, hipStream_t s);
+hipError_t launch_cover_choose(const NodeDev *nd, uint32_t E, uint8_t *cov, unsigned long long *cnt,
+                               StatusDev *st, hipStream_t s);
+hipError_t launch_cover_fill(const NodeDev *nd, uint32_t E, const uint8_t *cov, unsigned long long *cnt,
+                             StatusDev *st, hipStream_t s);
+hipError_t launch_probe(const ProbeLaunch &p, hipStream_t s);
+hipError_t launch_emit_count(const void *emit_dev, uint32_t E, unsigned long long *cnt, StatusDev *st,
+                             hipStream_t s);
+hipError_t launch_emit_rows(const void *emit_dev, uint32_t E, const unsigned long long *starts,
+                            unsigned long long nrows, unsigned long long base, StatusDev *st, hipStream_t s);
+size_t emit_dev_size();
+void emit_dev_fill(void *host_buf, const FrontierDev &F, const std::vector<int> &in_var,
+                   const std::vector<int> &in_h_atom, const TailDev *tails, int ntail, const int *head_src,
+                   int nhead, int32_t *out, unsigned long long out_rows);
+
+}  // namespace fj

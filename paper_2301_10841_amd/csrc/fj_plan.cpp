@@ -1,0 +1,229 @@
+// Free Join plan pipeline on the host: binary-plan conversion and
+// conservative factoring (Section 4.1), validity and covers (Section 3.2),
+// COLT schemas (Section 3.3 build phase) and the executor's per-node layout.
+#include "fj_plan.h"
+
+#include <algorithm>
+#include <cstring>
+
+namespace fj {
+
+namespace {
+
+using VarSet = uint64_t;  // FJ_MAX_VARS <= 64
+
+VarSet vset(const Subatom &s) {
+    VarSet m = 0;
+    for (int j = 0; j < s.nv; j++) m |= VarSet(1) << s.vars[j];
+    return m;
+}
+
+VarSet node_vset(const std::vector<Subatom> &node) {
+    VarSet m = 0;
+    for (const auto &s : node) m |= vset(s);
+    return m;
+}
+
+Subatom make_sub(const fj_query &q, int atom, VarSet keep) {
+    // the atom's variables that are in `keep`, in column order
+    Subatom s;
+    s.atom = atom;
+    const fj_atom &a = q.atoms[atom];
+    for (int j = 0; j < a.arity; j++)
+        if (keep & (VarSet(1) << a.vars[j])) s.vars[s.nv++] = a.vars[j];
+    return s;
+}
+
+VarSet atom_vset(const fj_query &q, int a) {
+    VarSet m = 0;
+    for (int j = 0; j < q.atoms[a].arity; j++) m |= VarSet(1) << q.atoms[a].vars[j];
+    return m;
+}
+
+}  // namespace
+
+fj_status check_query(const fj_query &q, std::string &err) {
+    if (q.natoms < 1 || q.natoms > FJ_MAX_ATOMS) { err = "natoms out of range"; return FJ_ERR_ARG; }
+    if (q.nvars < 1 || q.nvars > FJ_MAX_VARS) { err = "nvars out of range"; return FJ_ERR_ARG; }
+    VarSet all = 0;
+    for (int a = 0; a < q.natoms; a++) {
+        const fj_atom &at = q.atoms[a];
+        if (at.arity < 0 || at.arity > FJ_MAX_COLS) { err = "atom arity out of range"; return FJ_ERR_ARG; }
+        VarSet m = 0;
+        for (int j = 0; j < at.arity; j++) {
+            int v = at.vars[j];
+            if (v < 0 || v >= q.nvars) { err = "atom variable out of range"; return FJ_ERR_ARG; }
+            if (m & (VarSet(1) << v)) { err = "variables of one atom must be distinct"; return FJ_ERR_ARG; }
+            m |= VarSet(1) << v;
+        }
+        all |= m;
+    }
+    if (all != ((q.nvars == 64) ? ~VarSet(0) : ((VarSet(1) << q.nvars) - 1))) {
+        err = "every variable must occur in some atom";
+        return FJ_ERR_ARG;
+    }
+    if (q.nhead != q.nvars) { err = "the query is full: the head lists every variable once"; return FJ_ERR_ARG; }
+    VarSet h = 0;
+    for (int j = 0; j < q.nhead; j++) {
+        int v = q.head[j];
+        if (v < 0 || v >= q.nvars || (h & (VarSet(1) << v))) { err = "bad head"; return FJ_ERR_ARG; }
+        h |= VarSet(1) << v;
+    }
+    return FJ_OK;
+}
+
+// Section 4.1, figure "bj2fj": iterate the left relation; each next relation
+// is probed with the variables already available (those of the emitted nodes
+// and of the current one) and its remaining variables start the next node.
+static std::vector<std::vector<Subatom>> binary_to_fj(const fj_query &q, const int32_t *order, int n) {
+    std::vector<std::vector<Subatom>> plan;
+    int r = order[0];
+    std::vector<Subatom> cur{make_sub(q, r, atom_vset(q, r))};
+    VarSet avail = atom_vset(q, r);
+    for (int i = 1; i < n; i++) {
+        int s = order[i];
+        VarSet sv = atom_vset(q, s);
+        cur.push_back(make_sub(q, s, sv & avail));
+        plan.push_back(cur);
+        cur.assign(1, make_sub(q, s, sv & ~avail));
+        avail |= sv;
+    }
+    plan.push_back(cur);
+    return plan;
+}
+
+// Section 4.1, figure "factorize-plan": walk nodes from the last to the
+// second; move the node's lookups (subatoms after the first, in order) to the
+// previous node while their variables are bound before this node and the
+// previous node holds no subatom of the same atom; stop at the first that
+// cannot move, so the optimizer's lookup order is kept.
+static void factor_plan(std::vector<std::vector<Subatom>> &plan) {
+    int n = (int)plan.size();
+    for (int i = n - 1; i >= 1; i--) {
+        VarSet before = 0;
+        for (int j = 0; j < i; j++) before |= node_vset(plan[j]);
+        auto &phi = plan[i];
+        auto &prev = plan[i - 1];
+        while (phi.size() > 1) {
+            const Subatom cand = phi[1];
+            bool avail = (vset(cand) & ~before) == 0;
+            bool clash = false;
+            for (const auto &p : prev) clash |= (p.atom == cand.atom);
+            if (!avail || clash) break;
+            prev.push_back(cand);
+            phi.erase(phi.begin() + 1);
+        }
+    }
+}
+
+static fj_status finish_plan(const fj_query &q, const std::vector<std::vector<Subatom>> &nodes,
+                             fj_plan *out, std::string &err) {
+    int nn = (int)nodes.size();
+    if (nn < 1 || nn > FJ_MAX_NODES) { err = "plan must have 1..FJ_MAX_NODES nodes"; return FJ_ERR_UNSUPPORTED; }
+    *out = fj_plan{};
+    out->q = q;
+    out->nodes = nodes;
+    // partition check and schemas
+    VarSet seen[FJ_MAX_ATOMS] = {0};
+    out->sub_level.assign(nn, {});
+    for (int k = 0; k < nn; k++) {
+        if (nodes[k].empty()) { err = "empty plan node"; return FJ_ERR_PLAN_INVALID; }
+        uint32_t atoms_here = 0;
+        for (const auto &s : nodes[k]) {
+            if (s.atom < 0 || s.atom >= q.natoms) { err = "subatom names an unknown atom"; return FJ_ERR_PLAN_INVALID; }
+            if (atoms_here & (1u << s.atom)) { err = "validity (a): an atom occurs twice in a node"; return FJ_ERR_PLAN_INVALID; }
+            atoms_here |= 1u << s.atom;
+            VarSet sv = vset(s);
+            if (s.nv < 0 || s.nv > FJ_MAX_COLS || (sv & ~atom_vset(q, s.atom))) {
+                err = "subatom variables are not the atom's"; return FJ_ERR_PLAN_INVALID;
+            }
+            if (__builtin_popcountll(sv) != s.nv) { err = "repeated variable in a subatom"; return FJ_ERR_PLAN_INVALID; }
+            if (seen[s.atom] & sv) { err = "the nodes do not partition an atom"; return FJ_ERR_PLAN_INVALID; }
+            seen[s.atom] |= sv;
+            int l = out->nlev[s.atom]++;
+            out->lev[s.atom][l] = s;
+            out->sub_level[k].push_back(l);
+        }
+    }
+    for (int a = 0; a < q.natoms; a++) {
+        if (seen[a] != atom_vset(q, a) || out->nlev[a] == 0) { err = "the nodes do not partition an atom"; return FJ_ERR_PLAN_INVALID; }
+    }
+    // covers (validity (b)) and pure covers; per-node frontier layout
+    out->layout.assign(nn + 1, {});
+    VarSet bound = 0;
+    int lev_at[FJ_MAX_ATOMS] = {0};  // current level of each atom before node k
+    for (int k = 0; k <= nn; k++) {
+        fj::NodeLayout &L = out->layout[k];
+        for (int v = 0; v < q.nvars; v++)
+            if (bound & (VarSet(1) << v)) L.in_var.push_back(v);
+        for (int a = 0; a < q.natoms; a++)
+            if (lev_at[a] > 0 && lev_at[a] < out->nlev[a]) L.in_hatom.push_back(a);
+        if (k == nn) break;
+        VarSet nv = node_vset(nodes[k]) & ~bound;
+        bool any_cover = false;
+        for (int i = 0; i < (int)nodes[k].size(); i++) {
+            VarSet sv = vset(nodes[k][i]);
+            if ((nv & ~sv) == 0) {
+                any_cover = true;
+                if ((sv & bound) == 0) L.pure.push_back(i);
+            }
+        }
+        if (!any_cover) { err = "validity (b): a node has no cover"; return FJ_ERR_PLAN_INVALID; }
+        if (L.pure.empty()) { err = "no cover of a node is free of bound variables"; return FJ_ERR_PLAN_NO_PURE_COVER; }
+        for (int v = 0; v < q.nvars; v++)
+            if (nv & (VarSet(1) << v)) L.new_vars.push_back(v);
+        for (const auto &s : nodes[k]) lev_at[s.atom]++;
+        bound |= nv;
+    }
+    // build-phase rule for roots: iterate the base table directly only when
+    // the atom's first subatom is its single level and the only pure cover.
+    for (int a = 0; a < q.natoms; a++) {
+        out->root_built[a] = true;
+        for (int k = 0; k < nn; k++) {
+            for (int i = 0; i < (int)nodes[k].size(); i++) {
+                if (nodes[k][i].atom == a && out->sub_level[k][i] == 0) {
+                    const auto &pc = out->layout[k].pure;
+                    if (out->nlev[a] == 1 && pc.size() == 1 && pc[0] == i) out->root_built[a] = false;
+                }
+            }
+        }
+    }
+    // trailing nodes whose only subatom is the last level of its atom need
+    // no probing: each input binding contributes the product of their sizes.
+    int t = nn;
+    while (t > 0) {
+        const auto &node = nodes[t - 1];
+        if (node.size() != 1) break;
+        int a = node[0].atom;
+        if (out->sub_level[t - 1][0] != out->nlev[a] - 1) break;
+        t--;
+    }
+    out->tail_from = t;
+    return FJ_OK;
+}
+
+fj_status plan_from_binary(const fj_query &q, const int32_t *order, int n, bool do_factor,
+                           fj_plan *out, std::string &err) {
+    fj_status st = check_query(q, err);
+    if (st != FJ_OK) return st;
+    if (!order || n != q.natoms) { err = "the left-deep order must list every atom once"; return FJ_ERR_ARG; }
+    uint32_t used = 0;
+    for (int i = 0; i < n; i++) {
+        if (order[i] < 0 || order[i] >= q.natoms || (used & (1u << order[i]))) {
+            err = "the left-deep order must list every atom once"; return FJ_ERR_ARG;
+        }
+        used |= 1u << order[i];
+    }
+    auto plan = binary_to_fj(q, order, n);
+    if (do_factor) factor_plan(plan);
+    return finish_plan(q, plan, out, err);
+}
+
+fj_status plan_from_nodes(const fj_query &q, const std::vector<std::vector<Subatom>> &nodes,
+                          fj_plan *out, std::string &err) {
+    fj_status st = check_query(q, err);
+    if (st != FJ_OK) return st;
+    return finish_plan(q, nodes, out, err);
+}
+
+}  // namespace fj

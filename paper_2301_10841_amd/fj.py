@@ -1,0 +1,281 @@
+"""Python binding of libfj (include/fj.h): argument marshalling only.
+
+Every step of the join runs in the library's HIP kernels; PyTorch provides the
+device memory and the stream.  Importing this module fails loudly when
+libfj.so has not been built: there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfj.so")
+
+MAX_COLS = 8
+MAX_ATOMS = 16
+MAX_VARS = 32
+MAX_NODES = 16
+FACTOR = 1
+
+STATUS = {0: "FJ_OK", 1: "FJ_TRUNCATED", -1: "FJ_ERR_ARG", -2: "FJ_ERR_PLAN_INVALID",
+          -3: "FJ_ERR_PLAN_NO_PURE_COVER", -4: "FJ_ERR_OOM", -5: "FJ_ERR_HIP", -6: "FJ_ERR_UNSUPPORTED"}
+TIMERS = ("filter", "build", "cover", "probe", "probe0", "force", "emit", "scan")
+
+
+class FJError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Relation(C.Structure):
+    _fields_ = [("ncols", C.c_int32), ("nrows", C.c_int64),
+                ("cols", C.c_void_p * MAX_COLS), ("sel", C.c_void_p), ("nsel", C.c_int64)]
+
+
+class Atom(C.Structure):
+    _fields_ = [("arity", C.c_int32), ("vars", C.c_int32 * MAX_COLS)]
+
+
+class QueryS(C.Structure):
+    _fields_ = [("natoms", C.c_int32), ("atoms", Atom * MAX_ATOMS), ("nvars", C.c_int32),
+                ("nhead", C.c_int32), ("head", C.c_int32 * MAX_VARS)]
+
+
+class Options(C.Structure):
+    _fields_ = [("tile", C.c_int64), ("block", C.c_int32), ("timing", C.c_int32),
+                ("tail", C.c_int32), ("reserved", C.c_int32 * 4)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("cover", C.c_uint64 * MAX_NODES), ("probe", C.c_uint64 * MAX_NODES),
+                ("hit", C.c_uint64 * MAX_NODES), ("survivors", C.c_uint64 * MAX_NODES),
+                ("forced", C.c_uint64 * MAX_NODES), ("forced_offsets", C.c_uint64 * MAX_NODES),
+                ("tail_from", C.c_int32), ("nnodes", C.c_int32), ("tiles", C.c_uint64),
+                ("deferred", C.c_uint64)]
+
+    def per_node(self):
+        n = self.nnodes
+        keys = ("cover", "probe", "hit", "survivors", "forced", "forced_offsets")
+        return [{k: int(getattr(self, k)[i]) for k in keys} for i in range(n)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2301_10841_amd/build.py "
+                              "(there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        vp = C.c_void_p
+        L.fj_last_error.restype = C.c_char_p
+        L.fj_ctx_create.argtypes = [C.c_int, vp, P(Options), P(vp)]
+        L.fj_ctx_destroy.argtypes = [vp]
+        L.fj_ctx_destroy.restype = None
+        L.fj_timings.argtypes = [vp, vp, vp]
+        L.fj_timings_reset.argtypes = [vp]
+        L.fj_plan_from_binary.argtypes = [P(QueryS), vp, C.c_int32, C.c_uint32, P(vp)]
+        L.fj_plan_from_nodes.argtypes = [P(QueryS), C.c_int32, vp, vp, vp, vp, P(vp)]
+        L.fj_plan_get.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int32]
+        L.fj_plan_free.argtypes = [vp]
+        L.fj_plan_free.restype = None
+        L.fj_filter_lt.argtypes = [vp, vp, C.c_int64, C.c_int32, vp, P(C.c_int64)]
+        L.fj_build_colt.argtypes = [vp, P(QueryS), vp, C.c_int32, P(Relation), P(vp)]
+        L.fj_colt_rebuild.argtypes = [vp, vp, P(Relation)]
+        L.fj_colt_free.argtypes = [vp]
+        L.fj_colt_free.restype = None
+        L.fj_execute.argtypes = [vp, P(QueryS), vp, vp, P(C.c_uint64), vp, C.c_uint64,
+                                 P(C.c_uint64), P(Stats)]
+        for name in ("fj_ctx_create", "fj_timings", "fj_timings_reset", "fj_plan_from_binary",
+                     "fj_plan_from_nodes", "fj_plan_get", "fj_filter_lt", "fj_build_colt",
+                     "fj_colt_rebuild", "fj_execute"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st: int, ok=(0,)):
+    if st not in ok:
+        raise FJError(st, lib().fj_last_error().decode(errors="replace"))
+    return st
+
+
+# ------------------------------------------------------------------ queries
+
+def make_query(atoms: Sequence[Sequence[int]], nvars: int, head: Optional[Sequence[int]] = None) -> QueryS:
+    """atoms[i] = the variable of each column of atom i."""
+    q = QueryS()
+    if len(atoms) > MAX_ATOMS:
+        raise ValueError("too many atoms")
+    q.natoms = len(atoms)
+    for i, vs in enumerate(atoms):
+        q.atoms[i].arity = len(vs)
+        for j, v in enumerate(vs):
+            q.atoms[i].vars[j] = int(v)
+    q.nvars = nvars
+    head = list(range(nvars)) if head is None else list(head)
+    q.nhead = len(head)
+    for j, v in enumerate(head):
+        q.head[j] = int(v)
+    return q
+
+
+class Plan:
+    def __init__(self, handle: int, query: QueryS):
+        self.h = handle
+        self.query = query
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.fj_plan_free(self.h)
+            self.h = None
+
+    def nodes(self) -> List[List[Tuple[int, Tuple[int, ...]]]]:
+        cap = MAX_NODES * MAX_ATOMS
+        nn = C.c_int32(0)
+        nsub = (C.c_int32 * MAX_NODES)()
+        sa = (C.c_int32 * cap)()
+        snv = (C.c_int32 * cap)()
+        sv = (C.c_int32 * (cap * MAX_COLS))()
+        _check(lib().fj_plan_get(self.h, C.byref(nn), nsub, sa, snv, sv, cap))
+        out, idx = [], 0
+        for k in range(nn.value):
+            node = []
+            for _ in range(nsub[k]):
+                node.append((sa[idx], tuple(sv[idx * MAX_COLS + j] for j in range(snv[idx]))))
+                idx += 1
+            out.append(node)
+        return out
+
+
+def plan_from_binary(q: QueryS, order: Sequence[int], factor: bool = True) -> Plan:
+    arr = (C.c_int32 * len(order))(*order)
+    h = C.c_void_p()
+    _check(lib().fj_plan_from_binary(C.byref(q), arr, len(order), FACTOR if factor else 0, C.byref(h)))
+    return Plan(h.value, q)
+
+
+def plan_from_nodes(q: QueryS, nodes: Sequence[Sequence[Tuple[int, Sequence[int]]]]) -> Plan:
+    subs = [s for n in nodes for s in n]
+    nsub = (C.c_int32 * max(1, len(nodes)))(*[len(n) for n in nodes])
+    sa = (C.c_int32 * max(1, len(subs)))(*[a for a, _ in subs])
+    snv = (C.c_int32 * max(1, len(subs)))(*[len(vs) for _, vs in subs])
+    sv = (C.c_int32 * (max(1, len(subs)) * MAX_COLS))()
+    for i, (_, vs) in enumerate(subs):
+        for j, v in enumerate(vs):
+            sv[i * MAX_COLS + j] = v
+    h = C.c_void_p()
+    _check(lib().fj_plan_from_nodes(C.byref(q), len(nodes), nsub, sa, snv, sv, C.byref(h)))
+    return Plan(h.value, q)
+
+
+# ------------------------------------------------------------------ context
+
+class Context:
+    """A libfj context bound to a device and a torch stream."""
+
+    def __init__(self, device: int = 0, stream=None, tile: int = 0, block: int = 0,
+                 timing: bool = False, tail: int = 0):
+        import torch
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        opt = Options()
+        opt.tile = tile
+        opt.block = block
+        opt.timing = 1 if timing else 0
+        opt.tail = tail
+        h = C.c_void_p()
+        _check(lib().fj_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(opt), C.byref(h)))
+        self.h = h.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fj_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def timings(self):
+        ms = (C.c_double * len(TIMERS))()
+        n = (C.c_uint64 * len(TIMERS))()
+        _check(lib().fj_timings(self.h, ms, n))
+        return {k: (ms[i], int(n[i])) for i, k in enumerate(TIMERS)}
+
+    def timings_reset(self):
+        _check(lib().fj_timings_reset(self.h))
+
+    # ---- selection
+    def filter_lt(self, col, bound: int, out_sel=None):
+        """Row offsets r with col[r] < bound (device uint32 tensor, unspecified order)."""
+        import torch
+        n = int(col.shape[0])
+        if out_sel is None:
+            out_sel = torch.empty(max(n, 1), dtype=torch.int32, device=col.device)
+        cnt = C.c_int64(0)
+        _check(lib().fj_filter_lt(self.h, C.c_void_p(col.data_ptr()), n, int(bound),
+                                  C.c_void_p(out_sel.data_ptr()), C.byref(cnt)))
+        return out_sel, int(cnt.value)
+
+    # ---- COLTs
+    def build_colt(self, q: QueryS, plan: Plan, atom: int, cols, sel=None, nsel: int = 0) -> "Colt":
+        rel = _relation(cols, sel, nsel)
+        h = C.c_void_p()
+        _check(lib().fj_build_colt(self.h, C.byref(q), plan.h, atom, C.byref(rel), C.byref(h)))
+        return Colt(h.value, cols, sel)
+
+    def rebuild_colt(self, colt: "Colt", cols, sel=None, nsel: int = 0):
+        rel = _relation(cols, sel, nsel)
+        _check(lib().fj_colt_rebuild(self.h, colt.h, C.byref(rel)))
+        colt.keep = (cols, sel)
+
+    # ---- join
+    def execute(self, q: QueryS, plan: Plan, colts: Sequence["Colt"], out=None, stats: bool = False):
+        """Returns (count, written, Stats or None).  out: device int32 [cap, nhead] or None."""
+        arr = (C.c_void_p * len(colts))(*[c.h for c in colts])
+        cnt = C.c_uint64(0)
+        wr = C.c_uint64(0)
+        st = Stats() if stats else None
+        cap = int(out.shape[0]) if out is not None else 0
+        rc = lib().fj_execute(self.h, C.byref(q), plan.h, arr, C.byref(cnt),
+                              C.c_void_p(out.data_ptr()) if out is not None else None, cap,
+                              C.byref(wr), C.byref(st) if st is not None else None)
+        _check(rc, ok=(0, 1))
+        return int(cnt.value), int(wr.value), st
+
+
+class Colt:
+    def __init__(self, handle: int, cols, sel):
+        self.h = handle
+        self.keep = (cols, sel)  # the library borrows these buffers
+
+    def free(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.fj_colt_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.free()
+
+
+def _relation(cols, sel, nsel) -> Relation:
+    r = Relation()
+    r.ncols = len(cols)
+    r.nrows = int(cols[0].shape[0]) if cols else 0
+    for j, c in enumerate(cols):
+        r.cols[j] = c.data_ptr()
+    r.sel = sel.data_ptr() if sel is not None else None
+    r.nsel = int(nsel) if sel is not None else 0
+    return r

@@ -1,0 +1,86 @@
+"""Run a conjunctive query end to end through libfj.
+
+Uploads column-stored relations with torch, applies pushed-down selections
+with the library's filter kernel, builds the plan and the COLTs, and runs the
+join.  Only argument marshalling happens here; all join work is in libfj.
+"""
+
+from __future__ import annotations
+
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import fj
+
+
+class DeviceQuery:
+    """Relations of a ``datagen`` query resident on one GPU."""
+
+    def __init__(self, ctx: fj.Context, dq, device: Optional[str] = None):
+        import torch
+        self.ctx = ctx
+        self.dq = dq
+        dev = device or f"cuda:{ctx.device}"
+        self.rel_cols = [[torch.from_numpy(np.ascontiguousarray(c, dtype=np.int32)).to(dev) for c in r.cols]
+                         for r in dq.relations]
+        self.q = fj.make_query([vs for _, vs in dq.atoms], dq.nvars, dq.head)
+        self.sel: List = [None] * len(dq.atoms)
+        self.nsel: List[int] = [0] * len(dq.atoms)
+        self.apply_filters()
+
+    def apply_filters(self):
+        for a, f in enumerate(self.dq.filters):
+            if f is None:
+                continue
+            col = self.rel_cols[self.dq.atoms[a][0]][f[0]]
+            s, n = self.ctx.filter_lt(col, f[1], self.sel[a])
+            self.sel[a], self.nsel[a] = s, n
+
+    def atom_cols(self, a: int):
+        return self.rel_cols[self.dq.atoms[a][0]]
+
+    def plan_binary(self, order: Sequence[int], factor: bool = True) -> fj.Plan:
+        return fj.plan_from_binary(self.q, list(order), factor)
+
+    def plan_nodes(self, nodes) -> fj.Plan:
+        return fj.plan_from_nodes(self.q, nodes)
+
+    def build(self, plan: fj.Plan):
+        return [self.ctx.build_colt(self.q, plan, a, self.atom_cols(a), self.sel[a], self.nsel[a])
+                for a in range(len(self.dq.atoms))]
+
+    def rebuild(self, colts):
+        for a, c in enumerate(colts):
+            self.ctx.rebuild_colt(c, self.atom_cols(a), self.sel[a], self.nsel[a])
+
+    def run(self, plan: fj.Plan, materialize: bool = True, cap: Optional[int] = None,
+            stats: bool = False, colts=None):
+        """Returns dict(count, rows (sorted numpy or None), written, stats)."""
+        import torch
+        if colts is None:
+            colts = self.build(plan)
+        out = None
+        if materialize:
+            if cap is None:
+                cnt, _, _ = self.ctx.execute(self.q, plan, colts)
+                cap = cnt
+                self.rebuild(colts)
+            out = torch.empty((max(int(cap), 1), self.q.nhead), dtype=torch.int32,
+                              device=f"cuda:{self.ctx.device}")
+            if cap == 0:
+                out = out[:0]
+        cnt, written, st = self.ctx.execute(self.q, plan, colts, out=out if materialize and cap else None,
+                                            stats=stats)
+        rows = None
+        if materialize:
+            rows = out[:written].cpu().numpy() if written else np.zeros((0, self.q.nhead), np.int32)
+            rows = sort_rows(rows)
+        return {"count": cnt, "rows": rows, "written": written, "stats": st, "colts": colts}
+
+
+def sort_rows(rows: np.ndarray) -> np.ndarray:
+    if rows.shape[0] == 0:
+        return rows
+    keys = [rows[:, j] for j in range(rows.shape[1] - 1, -1, -1)]
+    return rows[np.lexsort(keys)]

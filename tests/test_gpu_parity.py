@@ -1,0 +1,297 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle, the
+closed forms and the paper's worked examples.  Counts and sorted tuples must
+match bit for bit."""
+
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+import datagen
+from oracle import closed
+from tests.gpu_util import assert_same_rows, gj_nodes, oracle_plan_binary, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def fjm(torch_mod):
+    from paper_2301_10841_amd import fj, runner
+    fj.lib()
+    return fj, runner
+
+
+@pytest.fixture(scope="module")
+def ctx_small(fjm):
+    fj, _ = fjm
+    c = fj.Context(0, tile=7)          # tiny frontiers: many tiles, deep recursion
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ctx(fjm):
+    fj, _ = fjm
+    c = fj.Context(0, tile=1 << 20)
+    yield c
+    c.close()
+
+
+def gpu_run(fjm, ctx, dq, order=None, factor=True, nodes=None, materialize=True, stats=False, cap=None):
+    _, runner = fjm
+    d = runner.DeviceQuery(ctx, dq)
+    plan = d.plan_nodes(nodes) if nodes is not None else d.plan_binary(order, factor)
+    r = d.run(plan, materialize=materialize, stats=stats, cap=cap)
+    r["plan_nodes"] = plan.nodes()
+    for c in r["colts"]:
+        c.free()
+    return r
+
+
+# --------------------------------------------------------------- worked examples
+
+@pytest.mark.parametrize("n", [1, 3, 6])
+def test_clover_instance(fjm, ctx_small, n):
+    dq = datagen.clover_instance(n)
+    _say("clover", n)
+    for order in itertools.permutations(range(3)):
+        for factor in (False, True):
+            r = gpu_run(fjm, ctx_small, dq, order, factor, stats=True)
+            assert r["count"] == 1
+            assert r["rows"].tolist() == [[0, 0, 0, 0]]
+    # Section 4.1 probe counts: naive plan probes T n^2+1 times, factored n+1
+    naive = gpu_run(fjm, ctx_small, dq, [0, 1, 2], False, stats=True)["stats"].per_node()
+    assert naive[0]["probe"] == 2 * n + 1
+    assert naive[1]["probe"] == n * n + 1
+    fac = gpu_run(fjm, ctx_small, dq, [0, 1, 2], True, stats=True)["stats"].per_node()
+    assert fac[0]["probe"] == (2 * n + 1) + (n + 1)
+    gj = gpu_run(fjm, ctx_small, dq, nodes=gj_nodes(dq, [0, 1, 2, 3]))
+    assert gj["count"] == 1
+
+
+def test_clover_u_laziness(fjm, ctx_small):
+    # Section 4.2 example: [[R(x,a),S(x),T(x)],[U(b),S(b)],[T(c)]]: only the
+    # sub-tries reached from x0 are ever forced
+    dq = datagen.random_tiny_query(4, "clover_u", max_rows=12, domain=4)
+    nodes = [[(0, (0, 1)), (1, (0,)), (2, (0,))], [(3, (2,)), (1, (2,))], [(2, (3,))]]
+    want = oracle_run(dq, nodes)
+    got = gpu_run(fjm, ctx_small, dq, nodes=nodes, stats=True)
+    assert got["count"] == want["count"]
+    assert_same_rows(got["rows"], want["rows"])
+
+
+# ----------------------------------------------------------- random tiny bags
+
+SHAPES = ["triangle", "clover", "chain3", "chain4", "star3", "cycle4", "clover_u", "pair", "single"]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_tiny_vs_oracle(fjm, ctx_small, ctx, shape):
+    for seed in range(4):
+        dq = datagen.random_tiny_query(seed * 13 + 5, shape, max_rows=10, domain=3)
+        _say("tiny", shape, seed)
+        orders = list(itertools.permutations(range(len(dq.atoms))))[:6]
+        plans = []
+        for o in orders:
+            plans.append(("bin", o, False))
+            plans.append(("bin", o, True))
+        for vo in list(itertools.permutations(range(dq.nvars)))[:4]:
+            plans.append(("gj", vo, None))
+        for i, (kind, arg, factor) in enumerate(plans):
+            if kind == "bin":
+                onodes = oracle_plan_binary(dq, arg, factor)
+                want = oracle_run(dq, onodes, batch=(1, 2, 1000)[i % 3])
+                got = gpu_run(fjm, ctx_small if i % 2 else ctx, dq, arg, factor)
+            else:
+                nodes = gj_nodes(dq, arg)
+                want = oracle_run(dq, nodes, batch=2)
+                got = gpu_run(fjm, ctx_small if i % 2 else ctx, dq, nodes=nodes)
+            assert got["count"] == want["count"], (shape, seed, kind, arg)
+            assert_same_rows(got["rows"], want["rows"])
+
+
+def test_tail_products_match_full_execution(fjm):
+    fj, _ = fjm
+    c_full = fj.Context(0, tile=5, tail=1)
+    try:
+        for shape in ("clover", "star3", "chain4", "triangle"):
+            dq = datagen.random_tiny_query(21, shape, max_rows=10, domain=3)
+            order = list(range(len(dq.atoms)))
+            want = oracle_run(dq, oracle_plan_binary(dq, order, True))
+            got = gpu_run(fjm, c_full, dq, order, True)
+            assert got["count"] == want["count"]
+            assert_same_rows(got["rows"], want["rows"])
+    finally:
+        c_full.close()
+
+
+def test_static_cover_counters_match_oracle(fjm, ctx):
+    # nodes with one pure cover: the set of get() calls is fixed by the plan
+    for shape in ("clover", "chain4", "star3"):
+        dq = datagen.random_tiny_query(8, shape, max_rows=12, domain=3)
+        for factor in (False, True):
+            order = list(range(len(dq.atoms)))
+            want = oracle_run(dq, oracle_plan_binary(dq, order, factor))
+            got = gpu_run(fjm, ctx, dq, order, factor, stats=True)
+            gs = got["stats"].per_node()
+            for k in range(got["stats"].tail_from):
+                assert gs[k]["probe"] == want["counters"][k]["probe"], (shape, factor, k)
+                assert gs[k]["hit"] == want["counters"][k]["hit"], (shape, factor, k)
+
+
+# -------------------------------------------------------------- workloads
+
+@pytest.mark.parametrize("rep", [0, 1, 2])
+def test_triangle_10k_edges(fjm, ctx, rep):
+    e = datagen.triangle_edges(datagen.seed_for(1, rep))
+    dq = datagen.synth.triangle_query(e)
+    trace = closed.cycle_count(e[0], e[1], 3)
+    _say("triangle", rep, trace)
+    conv = oracle_plan_binary(dq, [0, 1, 2], True)
+    want = oracle_run(dq, conv)
+    assert want["count"] == trace
+    got = gpu_run(fjm, ctx, dq, [0, 1, 2], True)
+    assert got["count"] == trace
+    assert_same_rows(got["rows"], want["rows"])
+    gj = gpu_run(fjm, ctx, dq, nodes=gj_nodes(dq, [0, 1, 2]), stats=True)
+    assert gj["count"] == trace
+    assert_same_rows(gj["rows"], want["rows"])
+
+
+def test_triangle_small_tiles(fjm, ctx_small):
+    e = datagen.triangle_edges(77, n_edges=600, n_vertices=60)
+    dq = datagen.synth.triangle_query(e)
+    want = oracle_run(dq, gj_nodes(dq, [0, 1, 2]))
+    got = gpu_run(fjm, ctx_small, dq, nodes=gj_nodes(dq, [0, 1, 2]))
+    assert got["count"] == want["count"] == closed.cycle_count(e[0], e[1], 3)
+    assert_same_rows(got["rows"], want["rows"])
+
+
+def test_star_medium_vs_oracle(fjm, ctx):
+    dq = datagen.star_schema(datagen.seed_for(2, 9), n_fact=300_000, n_dim=30_000)
+    want = oracle_run(dq, oracle_plan_binary(dq, [0, 1, 2, 3, 4], True))
+    got = gpu_run(fjm, ctx, dq, [0, 1, 2, 3, 4], True)
+    assert got["count"] == want["count"]
+    assert_same_rows(got["rows"], want["rows"])
+
+
+def test_star_one_filter_large_output(fjm, ctx):
+    # filter on D1 only: about 10% of the fact rows survive, all materialized
+    dq = datagen.star_schema(datagen.seed_for(2, 3), n_fact=2_000_000, n_dim=200_000, filter_dims=[0])
+    dims = [tuple(dq.relations[i + 1].cols) for i in range(4)]
+    want = closed.star_rows(dq.relations[0].cols, dims, [10, None, None, None])
+    got = gpu_run(fjm, ctx, dq, [0, 1, 2, 3, 4], True)
+    assert got["count"] == want.shape[0]
+    assert_same_rows(got["rows"], want)
+
+
+def test_star_full_size(fjm):
+    # 10M fact rows x 4 Zipf(1.1) keys, 4 x 1M dimension rows, attr < 10 on each
+    fj, _ = fjm
+    c = fj.Context(0)
+    try:
+        dq = datagen.star_schema(datagen.seed_for(2, 0))
+        dims = [tuple(dq.relations[i + 1].cols) for i in range(4)]
+        want = closed.star_rows(dq.relations[0].cols, dims, [10] * 4)
+        got = gpu_run(fjm, c, dq, [0, 1, 2, 3, 4], True, stats=True)
+        _say("star full", got["count"], want.shape[0])
+        assert got["count"] == want.shape[0]
+        assert_same_rows(got["rows"], want)
+    finally:
+        c.close()
+
+
+@pytest.mark.parametrize("scale,edges", [(10, 8_000), (13, 60_000)])
+def test_rmat_cycles(fjm, ctx, scale, edges):
+    e = datagen.rmat_edges(datagen.seed_for(3, scale), scale, edges)
+    tq = datagen.synth.triangle_query(e)
+    t3 = closed.cycle_count(e[0], e[1], 3)
+    for nodes in (None, gj_nodes(tq, [0, 1, 2]), gj_nodes(tq, [2, 0, 1])):
+        r = gpu_run(fjm, ctx, tq, [0, 1, 2], True, nodes=nodes, materialize=False)
+        assert r["count"] == t3
+    cq = datagen.synth.four_cycle_query(e)
+    t4 = closed.cycle_count(e[0], e[1], 4)
+    for nodes in (None, gj_nodes(cq, [0, 1, 2, 3]), gj_nodes(cq, [0, 2, 1, 3])):
+        r = gpu_run(fjm, ctx, cq, [0, 1, 2, 3], True, nodes=nodes, materialize=False)
+        assert r["count"] == t4
+
+
+def test_batch_mix_queries(fjm, ctx):
+    qs, _ = datagen.batch_mix(11, n_queries=10, max_rows=30_000)
+    for dq in qs:
+        order = list(range(len(dq.atoms)))
+        want = oracle_run(dq, oracle_plan_binary(dq, order, True))
+        got = gpu_run(fjm, ctx, dq, order, True)
+        assert got["count"] == want["count"], dq.kind
+        assert_same_rows(got["rows"], want["rows"])
+
+
+# -------------------------------------------------------------- edge cases
+
+def test_truncation_keeps_exact_count(fjm, ctx):
+    dq = datagen.random_tiny_query(3, "chain3", max_rows=10, domain=2)
+    want = oracle_run(dq, oracle_plan_binary(dq, [0, 1, 2], True))
+    assert want["count"] > 5
+    got = gpu_run(fjm, ctx, dq, [0, 1, 2], True, cap=5)
+    assert got["count"] == want["count"]
+    assert got["written"] == 5
+    # the written rows are a sub-multiset of the result
+    from collections import Counter
+    w = Counter(map(tuple, want["rows"].tolist()))
+    g = Counter(map(tuple, got["rows"].tolist()))
+    assert all(g[k] <= w[k] for k in g)
+
+
+def test_empty_inputs(fjm, ctx):
+    e = (np.zeros(0, np.int32), np.zeros(0, np.int32))
+    dq = datagen.synth.triangle_query(e)
+    assert gpu_run(fjm, ctx, dq, [0, 1, 2], True)["count"] == 0
+    assert gpu_run(fjm, ctx, dq, nodes=gj_nodes(dq, [0, 1, 2]))["count"] == 0
+    st = datagen.star_schema(5, n_fact=1000, n_dim=100, attr_lt=0)   # empty selections
+    assert gpu_run(fjm, ctx, st, [0, 1, 2, 3, 4], True)["count"] == 0
+
+
+def test_negative_and_sentinel_keys(fjm, ctx):
+    # -1 is the empty marker of the 32-bit maps and (-1, -1) of the 64-bit ones
+    r = np.array([-1, -1, 5, 0, -1], np.int32)
+    s = np.array([-1, 3, 5, -1, 7], np.int32)
+    dq = datagen.synth.make_query(
+        ["x", "y", "z"],
+        [datagen.Relation("R", [r, s]), datagen.Relation("S", [s, r]), datagen.Relation("T", [r, r])],
+        [(0, (0, 1)), (1, (1, 2)), (2, (2, 0))])
+    for order in itertools.permutations(range(3)):
+        want = oracle_run(dq, oracle_plan_binary(dq, order, True))
+        got = gpu_run(fjm, ctx, dq, order, True)
+        assert got["count"] == want["count"]
+        assert_same_rows(got["rows"], want["rows"])
+
+
+def test_repeat_and_rebuild(fjm, ctx):
+    _, runner = fjm
+    e = datagen.triangle_edges(5, n_edges=2000, n_vertices=200)
+    dq = datagen.synth.triangle_query(e)
+    d = runner.DeviceQuery(ctx, dq)
+    plan = d.plan_nodes(gj_nodes(dq, [0, 1, 2]))
+    colts = d.build(plan)
+    want = closed.cycle_count(e[0], e[1], 3)
+    c1, _, _ = ctx.execute(d.q, plan, colts)
+    c2, _, _ = ctx.execute(d.q, plan, colts)     # inner levels already forced
+    d.rebuild(colts)
+    c3, _, _ = ctx.execute(d.q, plan, colts)
+    assert c1 == c2 == c3 == want
+    for c in colts:
+        c.free()
