@@ -90,7 +90,8 @@ typedef struct {
     int32_t timing;      /* nonzero: time kernel classes with hipEvents [0] */
     int32_t tail;        /* 0: multiply trailing single-cover nodes (default);
                             1: run every node through the probe kernel */
-    int32_t reserved[4];
+    int32_t generic;     /* 1: never use the specialised first-node scan kernel [0] */
+    int32_t reserved[3];
 } fj_options;
 
 /* Per-execution counters (fj_execute fills them when stats is non-null).

@@ -17,23 +17,23 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, defines=(), lib: str = LIB, bdir: str = None) -> str:
     objs = []
     inc = ["-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
-    bdir = os.path.join(HERE, "_build")
+    bdir = bdir or os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     for s in SOURCES:
         o = os.path.join(bdir, s + ".o")
         lang = ["-x", "hip"] if s.endswith(".hip") else []
-        cmd = [HIPCC] + FLAGS + inc + lang + ["-c", os.path.join(CSRC, s), "-o", o]
+        cmd = [HIPCC] + FLAGS + ["-D" + d for d in defines] + inc + lang + ["-c", os.path.join(CSRC, s), "-o", o]
         if verbose:
             print(" ".join(cmd))
         subprocess.check_call(cmd)
         objs.append(o)
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

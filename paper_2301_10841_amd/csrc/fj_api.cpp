@@ -145,10 +145,15 @@ struct Timer {
 fj_status sync_status(fj_ctx *c) {
     FJ_HIP(hipMemcpyAsync(c->status_h, c->status_d, sizeof(StatusDev), hipMemcpyDeviceToHost, c->stream));
     FJ_HIP(hipStreamSynchronize(c->stream));
-    if (c->status_h->err_count)
-        return fail(FJ_ERR_HIP, "device bounds check failed (fj_kernels.hip line " +
-                                    std::to_string(c->status_h->err_line) + ", " +
-                                    std::to_string(c->status_h->err_count) + " times)");
+    if (c->status_h->err_count) {
+        std::string msg = "device bounds check failed (fj_kernels.hip line " +
+                          std::to_string(c->status_h->err_line) + ", " +
+                          std::to_string(c->status_h->err_count) + " times)";
+        // report once, then let the context continue
+        hipMemsetAsync(&c->status_d->err_line, 0, 2 * sizeof(uint32_t), c->stream);
+        hipStreamSynchronize(c->stream);
+        return fail(FJ_ERR_HIP, msg);
+    }
     return FJ_OK;
 }
 
@@ -372,6 +377,9 @@ fj_status fj_ctx_create(int device, void *stream, const fj_options *opt, fj_ctx 
     e = hipHostMalloc((void **)&c->status_h, sizeof(StatusDev), hipHostMallocDefault);
     if (e != hipSuccess) { hipFree(c->status_d); delete c; return fail(FJ_ERR_OOM, "pinned status block"); }
     memset(c->status_h, 0, sizeof(StatusDev));
+    e = hipMemset(c->status_d, 0, sizeof(StatusDev));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) { fj_ctx_destroy(c); return fail(FJ_ERR_HIP, "status block initialisation failed"); }
     *out = c;
     return FJ_OK;
 }
@@ -390,8 +398,8 @@ void fj_ctx_destroy(fj_ctx *c) {
     if (c->desc_h) hipHostFree(c->desc_h);
     for (auto &p : c->pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
     for (auto e : c->pool) hipEventDestroy(e);
-    hipFree(c->status_d);
-    hipHostFree(c->status_h);
+    if (c->status_d) hipFree(c->status_d);
+    if (c->status_h) hipHostFree(c->status_h);
     delete c;
 }
 
@@ -533,6 +541,7 @@ fj_status fj_build_colt(fj_ctx *c, const fj_query *q, const fj_plan *p, int32_t 
                 for (int cc = 0; cc < q->atoms[atom].arity; cc++)
                     if (q->atoms[atom].vars[cc] == t->lev_var[l][j]) t->lev[l].kcol[j] = cc;
         st = colt_reset(c, t);
+        if (st == FJ_OK) st = sync_status(c);
     }
     if (st != FJ_OK) {
         std::string keep = g_err;
@@ -636,8 +645,42 @@ fj_status emit_rows(Exec &x, uint32_t E) {
     return FJ_OK;
 }
 
+// The first node can use the specialised scan-probe kernel when its only
+// pure cover is a base table iterated directly and every other subatom
+// probes a root map keyed by one or two cover columns.
+bool scan_eligible(const Exec &x, int &cover_sub) {
+    const fj_plan *p = x.p;
+    if (x.tail_from < 1) return false;
+    const auto &L = p->layout[0];
+    if (L.pure.size() != 1) return false;
+    cover_sub = L.pure[0];
+    const auto &node = p->nodes[0];
+    int ca = node[cover_sub].atom;
+    if (p->root_built[ca] || p->nlev[ca] != 1) return false;
+    int nl = 0;
+    for (size_t i = 0; i < node.size(); i++) {
+        if ((int)i == cover_sub) continue;
+        const fj_colt *t = x.colts[node[i].atom];
+        const LevelDev &R = t->lev[0];
+        if (p->sub_level[0][i] != 0 || !p->root_built[node[i].atom]) return false;
+        if (!(R.mode == fj::KM_K32 || (R.mode == fj::KM_K64 && R.nk == 2))) return false;
+        nl++;
+    }
+    if (nl > fj::scan_max_lookups()) return false;
+    for (int q = 0; q < (int)x.tails.size(); q++)
+        if (x.tails[q].level > 1) return false;
+    return true;
+}
+
+fj_status exec_scan_node(Exec &x, int cover_sub, u64 T, uint32_t r0_limit);
+
 fj_status exec_node(Exec &x, int k, uint32_t E) {
     fj_ctx *c = x.c;
+    int cover_sub = -1;
+    if (k == 0 && !c->opt.generic && scan_eligible(x, cover_sub)) {
+        const fj_colt *ct = x.colts[x.p->nodes[0][cover_sub].atom];
+        return exec_scan_node(x, cover_sub, ct->nroot, 0);
+    }
     const NodeDev *nd = x.nd_d + k;
     const fj_plan *p = x.p;
     u64 *starts = c->nodebuf[k].as<u64>(0);
@@ -721,6 +764,90 @@ fj_status exec_node(Exec &x, int k, uint32_t E) {
             if (x.out) FJ_TRY(emit_rows(x, surv));
         } else if (surv) {
             FJ_TRY(exec_node(x, k + 1, surv));
+        }
+    }
+    return FJ_OK;
+}
+
+fj_status exec_scan_node(Exec &x, int cover_sub, u64 T, uint32_t) {
+    fj_ctx *c = x.c;
+    const fj_plan *p = x.p;
+    const auto &node = p->nodes[0];
+    const fj_colt *ct = x.colts[node[cover_sub].atom];
+    const fj::Subatom &cs = node[cover_sub];
+    fj::ScanLaunch sl;
+    memset(&sl, 0, sizeof(sl));
+    for (int j = 0; j < FJ_MAX_COLS; j++) sl.cols[j] = ct->cols[j];
+    sl.ncols = ct->ncols;
+    sl.sel = ct->sel;
+    sl.nrows = (uint32_t)ct->nrows;
+    auto cover_col = [&](int var) {
+        for (int j = 0; j < cs.nv; j++)
+            if (cs.vars[j] == var) return ct->lev[0].kcol[j];
+        return -1;
+    };
+    const auto &LN = p->layout[1];
+    for (size_t i = 0; i < node.size(); i++) {
+        if ((int)i == cover_sub) continue;
+        const int a = node[i].atom;
+        const fj_colt *t = x.colts[a];
+        fj::ScanLookup &L = sl.lk[sl.nl++];
+        L.table = t->lev[0].table;
+        L.mask = t->lev[0].mask;
+        L.mode = t->lev[0].mode;
+        for (int j = 0; j < node[i].nv; j++) L.kc[j] = cover_col(node[i].vars[j]);
+        L.child_leaf = p->nlev[a] == 1;
+        L.clen = t->lev[1].len;
+        L.cnpos = t->lev[1].npos;
+        L.hcol = -1;
+        for (size_t h = 0; h < LN.in_hatom.size(); h++)
+            if (LN.in_hatom[h] == a) L.hcol = (int)h;
+    }
+    sl.nout = (int)LN.in_var.size();
+    for (int j = 0; j < sl.nout; j++) sl.out_col[j] = cover_col(LN.in_var[j]);
+    sl.out = x.F[1];
+    sl.emit = x.tail_from == 1;
+    sl.materialize = sl.emit && x.out != nullptr;
+    if (sl.emit) {
+        sl.ntail = (int)x.tails.size();
+        for (int q = 0; q < sl.ntail; q++) {
+            const TailDev &Td = x.tails[q];
+            sl.tail_lk[q] = -1;
+            sl.tail_root_len[q] = Td.root_len;
+            sl.tail_len[q] = Td.L.len;
+            sl.tail_npos[q] = Td.L.npos;
+            if (Td.level == 1) {
+                int j = 0;
+                for (size_t i = 0; i < node.size(); i++) {
+                    if ((int)i == cover_sub) continue;
+                    if (node[i].atom == Td.atom) sl.tail_lk[q] = j;
+                    j++;
+                }
+                if (sl.tail_lk[q] < 0) return fail(FJ_ERR_HIP, "tail trie not reached by the first node");
+            }
+        }
+    }
+    sl.status = c->status_d;
+    sl.count_stats = x.stats != nullptr;
+    sl.node = 0;
+    if (x.stats) x.stats->cover[0] += T;
+    for (u64 t0 = 0; t0 < T; t0 += x.C) {
+        uint32_t n = (uint32_t)std::min<u64>(x.C, T - t0);
+        FJ_TRY(zero_status_field(c, offsetof(StatusDev, survivors), 2 * sizeof(u64)));
+        sl.r0 = (uint32_t)t0;
+        sl.n = n;
+        {
+            Timer t(c, FJ_T_PROBE0);
+            FJ_HIP(fj::launch_scan_probe(sl, c->stream));
+        }
+        if (x.stats) x.stats->tiles++;
+        FJ_TRY(sync_status(c));
+        const uint32_t surv = (uint32_t)c->status_h->survivors;
+        if (sl.emit) {
+            if (x.out) FJ_TRY(emit_rows(x, surv));
+        } else {
+            if (x.stats) x.stats->survivors[0] += surv;
+            if (surv) FJ_TRY(exec_node(x, 1, surv));
         }
     }
     return FJ_OK;
@@ -906,7 +1033,8 @@ extern "C" fj_status fj_execute(fj_ctx *c, const fj_query *q, const fj_plan *p, 
         FJ_HIP(hipStreamSynchronize(c->stream));
     }
 
-    FJ_HIP(hipMemsetAsync(c->status_d, 0, sizeof(StatusDev), c->stream));
+    // clear the counters but keep any error a build left for the next check
+    FJ_HIP(hipMemsetAsync(c->status_d, 0, offsetof(StatusDev, err_line), c->stream));
     fj_status st;
     if (x.tail_from == 0) {
         // every node is a product of base tables: one empty binding

@@ -112,6 +112,18 @@ struct NodeDev {
     FrontierDev out;
 };
 
+// A root-map probe of the specialised first-node kernel.
+struct ScanLookup {
+    const void *table;
+    unsigned long long mask;
+    int mode;              // KM_K32 or KM_K64 (root keys of one or two columns)
+    int kc[2];             // cover columns of the key variables
+    int child_leaf;
+    const uint32_t *clen;  // child level lengths
+    uint32_t cnpos;        // child level positions
+    int hcol;              // output handle column of this atom, or -1
+};
+
 // Host <-> device status block, one per context.
 struct StatusDev {
     unsigned long long count;      // result tuples so far

@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "fj_dev.h"
@@ -43,6 +44,17 @@ struct Key {
     uint32_t h;                  // handle (start position) of the probed trie
     int32_t v[FJ_MAX_COLS];
 };
+
+// Probing walks forward from the start of a 32-byte bucket (4 slots of 8 B,
+// or 2 of 16 B), so that one pair of 16-byte loads usually settles a lookup.
+// Insert and find use the same sequence.
+#ifndef FJ_BUCKET_BYTES
+#define FJ_BUCKET_BYTES 32
+#endif
+constexpr int kBucketBytes = FJ_BUCKET_BYTES;
+template <typename SlotT> __device__ __forceinline__ u64 bucket_start(u64 h, u64 mask) {
+    return (h & mask) & ~(u64)(kBucketBytes / sizeof(SlotT) - 1);
+}
 
 __device__ __forceinline__ u64 pack64(const LevelDev &L, const Key &k) {
     // root with two key columns: (v0, v1); below the root: (handle, v0)
@@ -71,7 +83,7 @@ __device__ __forceinline__ u64 table_find(const LevelDev &L, const int32_t *cons
         const Slot32 *T = (const Slot32 *)L.table;
         uint32_t key = (uint32_t)k.v[0];
         if (key == kEmpty32) return T[mask + 1].key ? mask + 1 : ~0ull;
-        u64 i = mix32(key) & mask;
+        u64 i = bucket_start<Slot32>(mix32(key), mask);
         for (u64 n = 0; n <= mask; n++) {
             uint32_t c = T[i].key;
             if (c == key) return i;
@@ -82,7 +94,7 @@ __device__ __forceinline__ u64 table_find(const LevelDev &L, const int32_t *cons
         const Slot64 *T = (const Slot64 *)L.table;
         u64 key = pack64(L, k);
         if (key == kEmpty64) return T[mask + 1].key ? mask + 1 : ~0ull;
-        u64 i = mix64(key) & mask;
+        u64 i = bucket_start<Slot64>(mix64(key), mask);
         for (u64 n = 0; n <= mask; n++) {
             u64 c = T[i].key;
             if (c == key) return i;
@@ -91,7 +103,7 @@ __device__ __forceinline__ u64 table_find(const LevelDev &L, const int32_t *cons
         }
     } else {
         const SlotRep *T = (const SlotRep *)L.table;
-        u64 i = rep_hash(k, L.nk) & mask;
+        u64 i = bucket_start<SlotRep>(rep_hash(k, L.nk), mask);
         for (u64 n = 0; n <= mask; n++) {
             u64 c = T[i].hr;
             if (c == kEmpty64) return ~0ull;
@@ -127,7 +139,7 @@ __device__ __forceinline__ u64 table_insert(const LevelDev &L, const int32_t *co
             claimed = atomicCAS(&T[mask + 1].key, 0u, 1u) == 0u;
             return mask + 1;
         }
-        u64 i = mix32(key) & mask;
+        u64 i = bucket_start<Slot32>(mix32(key), mask);
         for (u64 n = 0; n <= mask; n++) {
             uint32_t c = __atomic_load_n(&T[i].key, __ATOMIC_RELAXED);
             if (c == key) return i;
@@ -145,7 +157,7 @@ __device__ __forceinline__ u64 table_insert(const LevelDev &L, const int32_t *co
             claimed = atomicCAS(&T[mask + 1].key, 0ull, 1ull) == 0ull;
             return mask + 1;
         }
-        u64 i = mix64(key) & mask;
+        u64 i = bucket_start<Slot64>(mix64(key), mask);
         for (u64 n = 0; n <= mask; n++) {
             u64 c = __atomic_load_n(&T[i].key, __ATOMIC_RELAXED);
             if (c == key) return i;
@@ -159,7 +171,7 @@ __device__ __forceinline__ u64 table_insert(const LevelDev &L, const int32_t *co
     } else {
         SlotRep *T = (SlotRep *)L.table;
         u64 mine = ((u64)row << 32) | k.h;
-        u64 i = rep_hash(k, L.nk) & mask;
+        u64 i = bucket_start<SlotRep>(rep_hash(k, L.nk), mask);
         for (u64 n = 0; n <= mask; n++) {
             u64 c = __atomic_load_n(&T[i].hr, __ATOMIC_RELAXED);
             if (c == kEmpty64) {
@@ -319,16 +331,31 @@ __global__ void k_scan_total(T *out, u64 n, const T *total) {
 }
 
 // ----------------------------------------------------------------- filter
-// sigma_{col < bound}: row offsets of passing rows, wave-compacted.
+// sigma_{col < bound}: row offsets of passing rows.  Each workgroup scans a
+// contiguous chunk, counts its passing rows, reserves their output range
+// with one atomic and writes them; rows keep their order within a thread.
+constexpr int kFilterItems = 16;
+
 __global__ void __launch_bounds__(256) k_filter_lt(const int32_t *__restrict__ col, u64 n, int32_t bound,
                                                    uint32_t *__restrict__ out, u64 *counter) {
-    u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    u64 stride = (u64)gridDim.x * blockDim.x;
-    u64 nround = (n + stride - 1) / stride * stride;
-    for (; i < nround; i += stride) {
-        bool pass = i < n && col[i] < bound;
-        u64 pos = wave_reserve(pass, counter);
-        if (pass) out[pos] = (uint32_t)i;
+    __shared__ uint32_t lds[17];
+    __shared__ u64 block_base;
+    const u64 chunk = (u64)blockDim.x * kFilterItems;
+    const u64 start = (u64)blockIdx.x * chunk;
+    uint32_t bits = 0, cnt = 0;
+    for (int k = 0; k < kFilterItems; k++) {
+        u64 i = start + (u64)k * blockDim.x + threadIdx.x;
+        bool pass = i < n && __builtin_nontemporal_load(col + i) < bound;
+        bits |= (uint32_t)pass << k;
+        cnt += pass;
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan<uint32_t>(cnt, lds, tot);
+    if (threadIdx.x == 0) block_base = tot ? atomicAdd(counter, (u64)tot) : 0ull;
+    __syncthreads();
+    u64 pos = block_base + ex;
+    for (int k = 0; k < kFilterItems; k++) {
+        if (bits & (1u << k)) out[pos++] = (uint32_t)(start + (u64)k * blockDim.x + threadIdx.x);
     }
 }
 
@@ -402,15 +429,27 @@ __global__ void __launch_bounds__(256) k_force_insert(ForceArgs a) {
     for (int c = 0; c < a.L.nk; c++) k.v[c] = a.cols[a.L.kcol[c]][row];
     bool claimed;
     u64 sl = table_insert(a.L, a.cols, k, row, claimed);
-    if (!CK(sl < a.L.nslots)) return;
-    a.wslot[w] = (uint32_t)sl;
-    if (claimed) {
-        uint32_t r = atomicAdd(&a.L.rank_ctr[p], 1u);
-        set_slot_val(a.L, sl, r);
-        a.wrank[w] = r | kClaim;
-    } else {
-        a.wrank[w] = 0;
+    const bool good = CK(sl < a.L.nslots);
+    if (good) a.wslot[w] = (uint32_t)sl;
+    // new keys take consecutive ranks of their handle; lanes of a wave that
+    // claim keys of the same handle share one atomic
+    const bool want = good && claimed;
+    u64 pending = __ballot(want);
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const uint32_t pl = __shfl(p, leader, 64);
+        const u64 grp = __ballot(want && p == pl);
+        uint32_t base = 0;
+        if (__lane_id() == leader) base = atomicAdd(&a.L.rank_ctr[pl], (uint32_t)__popcll(grp));
+        base = __shfl(base, leader, 64);
+        if (want && p == pl) {
+            const uint32_t r = base + (uint32_t)__popcll(grp & ((1ull << __lane_id()) - 1ull));
+            set_slot_val(a.L, sl, r);
+            a.wrank[w] = r | kClaim;
+        }
+        pending &= ~grp;
     }
+    if (good && !claimed) a.wrank[w] = 0;
 }
 
 __global__ void __launch_bounds__(256) k_force_count(ForceArgs a) {
@@ -691,6 +730,277 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
     }
 }
 
+// ------------------------------------------------------------ scan probe
+// Specialised first node: the cover is a base table (or its selection)
+// iterated directly and every other subatom is a probe of a root map keyed
+// by cover columns.  Each thread takes kScanRows rows of a contiguous tile
+// (coalesced, non-temporal column loads) and probes trie by trie across its
+// rows, so the rows' independent probes are in flight together: the
+// vectorized execution of Section 4.3 mapped onto one thread's registers.
+
+#ifndef FJ_SCAN_ROWS
+#define FJ_SCAN_ROWS 1
+#endif
+#ifndef FJ_SCAN_PRELOAD
+#define FJ_SCAN_PRELOAD 0
+#endif
+constexpr int kScanRows = FJ_SCAN_ROWS;
+constexpr int kScanMaxLookups = 8;
+
+// Streaming loads of cover columns (read once).
+__device__ __forceinline__ int32_t stream_load(const int32_t *p) {
+#ifdef FJ_NT_LOADS
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+
+struct ScanArgs {
+    const int32_t *cols[FJ_MAX_COLS];
+    int ncols;
+    int vec;                  // cover columns are 16-byte aligned: load 4 rows at once
+    int keycol[FJ_MAX_COLS];  // nonzero for columns some lookup keys on
+    const uint32_t *sel;      // selection of the cover relation, or null
+    uint32_t nrows;           // rows of the cover relation's columns
+    uint32_t r0;              // first cover position of this launch
+    uint32_t n;               // cover positions in this launch
+    int nl;
+    ScanLookup lk[kScanMaxLookups];
+    int nout;
+    int out_col[FJ_MAX_VARS]; // output value column j <- cover column
+    FrontierDev out;
+    int emit, materialize;
+    int ntail;
+    int tail_lk[FJ_MAX_NODES];          // lookup whose child is the tail's trie, -1: a root
+    const uint32_t *tail_len[FJ_MAX_NODES];
+    uint32_t tail_npos[FJ_MAX_NODES];
+    uint32_t tail_root_len[FJ_MAX_NODES];
+    StatusDev *status;
+    int count_stats;
+    int node;
+};
+
+// Bucket of a root map, held as 16-byte vector registers.
+constexpr int kBucketVec = kBucketBytes / 16;
+struct Bucket { uint4 q[kBucketVec]; };
+
+__device__ __forceinline__ void load_bucket(const void *T, u64 byte_off, Bucket &out) {
+    const uint4 *src = (const uint4 *)((const char *)T + byte_off);
+#pragma unroll
+    for (int q = 0; q < kBucketVec; q++) out.q[q] = src[q];
+}
+
+// Scan a loaded bucket in slot order: 1 = hit, 2 = miss (empty slot), 0 = go
+// on.  Branch-free: walking the slots backwards, the earliest slot that holds
+// the key or is empty decides.
+__device__ __forceinline__ int scan_bucket32(const Bucket &bk, uint32_t key, uint32_t &val) {
+    int st = 0;
+    uint32_t v = 0;
+#pragma unroll
+    for (int q = kBucketVec - 1; q >= 0; q--) {
+        const uint32_t kz = bk.q[q].z, kx = bk.q[q].x;
+        st = kz == key ? 1 : (kz == kEmpty32 ? 2 : st);
+        v = kz == key ? bk.q[q].w : v;
+        st = kx == key ? 1 : (kx == kEmpty32 ? 2 : st);
+        v = kx == key ? bk.q[q].y : v;
+    }
+    val = v;
+    return st;
+}
+
+__device__ __forceinline__ int scan_bucket64(const Bucket &bk, u64 key, uint32_t &val) {
+    int st = 0;
+    uint32_t v = 0;
+#pragma unroll
+    for (int q = kBucketVec - 1; q >= 0; q--) {
+        const u64 k = ((u64)bk.q[q].y << 32) | bk.q[q].x;
+        st = k == key ? 1 : (k == kEmpty64 ? 2 : st);
+        v = k == key ? bk.q[q].z : v;
+    }
+    val = v;
+    return st;
+}
+
+// One round of root-map probes for kScanRows rows: every row's bucket load
+// is issued before any is examined.  Keys equal to the empty marker live in
+// the reserved slot (mask + 1), whose key word is 1 once claimed.
+template <int MODE>
+__device__ __forceinline__ void scan_round(const ScanArgs &a, const ScanLookup &L, const uint32_t *row,
+                                           bool *alive, bool vec, uint32_t *val,
+                                           const int32_t (*pre)[FJ_MAX_COLS]) {
+    typedef typename std::conditional<MODE == KM_K32, Slot32, Slot64>::type SlotT;
+    typedef typename std::conditional<MODE == KM_K32, uint32_t, u64>::type KeyT;
+    constexpr u64 B = kBucketBytes / sizeof(SlotT);
+    const SlotT *T = (const SlotT *)L.table;
+    const KeyT empty = MODE == KM_K32 ? (KeyT)kEmpty32 : (KeyT)kEmpty64;
+    const int32_t *c0 = a.cols[L.kc[0]];
+    const int32_t *c1 = a.cols[MODE == KM_K32 ? L.kc[0] : L.kc[1]];
+    int32_t k0[kScanRows], k1[kScanRows];
+#if FJ_SCAN_PRELOAD
+    // keys come from the columns preloaded at kernel start
+#pragma unroll
+    for (int r = 0; r < kScanRows; r++) {
+        k0[r] = 0; k1[r] = 0;
+#pragma unroll
+        for (int c = 0; c < FJ_MAX_COLS; c++) {
+            k0[r] = c == L.kc[0] ? pre[r][c] : k0[r];
+            k1[r] = c == L.kc[1] ? pre[r][c] : k1[r];
+        }
+    }
+    bool all = false;
+#else
+    // keys: one 16-byte load per column when the thread's rows are
+    // consecutive and all alive, else one load per live row
+    bool all = vec;
+#pragma unroll
+    for (int r = 0; r < kScanRows; r++) all = all && alive[r];
+    if constexpr (kScanRows == 4) {
+        if (all) {
+            const int4 x = *(const int4 *)(c0 + row[0]);
+            k0[0] = x.x; k0[1] = x.y; k0[2] = x.z; k0[3] = x.w;
+            if (MODE != KM_K32) {
+                const int4 y = *(const int4 *)(c1 + row[0]);
+                k1[0] = y.x; k1[1] = y.y; k1[2] = y.z; k1[3] = y.w;
+            }
+        }
+    }
+    if (!all || kScanRows != 4) {
+#pragma unroll
+        for (int r = 0; r < kScanRows; r++) {
+            k0[r] = alive[r] ? c0[row[r]] : 0;
+            if (MODE != KM_K32) k1[r] = alive[r] ? c1[row[r]] : 0;
+        }
+    }
+#endif
+    KeyT key[kScanRows];
+    u64 idx[kScanRows];
+    Bucket bk[kScanRows];
+#pragma unroll
+    for (int r = 0; r < kScanRows; r++) {
+#pragma unroll
+        for (int q = 0; q < kBucketVec; q++) bk[r].q[q] = make_uint4(0, 0, 0, 0);
+        key[r] = MODE == KM_K32 ? (KeyT)(uint32_t)k0[r]
+                                : (KeyT)((((u64)(uint32_t)k0[r]) << 32) | (uint32_t)k1[r]);
+        const u64 h = MODE == KM_K32 ? (u64)mix32((uint32_t)key[r]) : mix64((u64)key[r]);
+        idx[r] = bucket_start<SlotT>(h, L.mask);
+        if (alive[r] && key[r] != empty) load_bucket(T, idx[r] * sizeof(SlotT), bk[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < kScanRows; r++) {
+        if (!alive[r]) continue;
+        if (key[r] == empty) {
+            const SlotT rs = T[L.mask + 1];
+            alive[r] = rs.key != 0;
+            val[r] = rs.val;
+            continue;
+        }
+        int st = MODE == KM_K32 ? scan_bucket32(bk[r], (uint32_t)key[r], val[r])
+                                : scan_bucket64(bk[r], (u64)key[r], val[r]);
+        for (u64 n = B; st == 0 && n <= L.mask; n += B) {   // a full bucket: go on (rare)
+            idx[r] = (idx[r] + B) & L.mask;
+            load_bucket(T, idx[r] * sizeof(SlotT), bk[r]);
+            st = MODE == KM_K32 ? scan_bucket32(bk[r], (uint32_t)key[r], val[r])
+                                : scan_bucket64(bk[r], (u64)key[r], val[r]);
+        }
+        alive[r] = st == 1;
+    }
+}
+
+template <bool STATS>
+__global__ void __launch_bounds__(256) k_scan_probe(ScanArgs a) {
+    StatusDev *status = a.status;
+    // child handles of the thread's live rows, per lookup
+    __shared__ uint32_t hs[kScanMaxLookups][256 * kScanRows];
+    const uint32_t first = (blockIdx.x * 256u + threadIdx.x) * kScanRows;
+    uint32_t row[kScanRows];
+    bool alive[kScanRows];
+    u64 mult[kScanRows];
+    uint32_t nprobe = 0, nhit = 0;
+#pragma unroll
+    for (int r = 0; r < kScanRows; r++) {
+        alive[r] = first + r < a.n;
+        mult[r] = 1;
+        row[r] = alive[r] ? a.r0 + first + r : 0u;
+    }
+    bool vec = a.vec;
+    if (a.sel) {
+#pragma unroll
+        for (int r = 0; r < kScanRows; r++) row[r] = alive[r] ? a.sel[row[r]] : 0u;
+        vec = false;
+    }
+#pragma unroll
+    for (int r = 0; r < kScanRows; r++) alive[r] = alive[r] && CK(row[r] < a.nrows);
+    int32_t pre[kScanRows][FJ_MAX_COLS];
+#if FJ_SCAN_PRELOAD
+    // every key column of the thread's rows in one batch of loads
+#pragma unroll
+    for (int r = 0; r < kScanRows; r++)
+#pragma unroll
+        for (int c = 0; c < FJ_MAX_COLS; c++)
+            pre[r][c] = (c < a.ncols && a.keycol[c] && alive[r]) ? a.cols[c][row[r]] : 0;
+#endif
+    // trie by trie over this thread's rows (Section 4.3's vectorized order)
+    for (int j = 0; j < a.nl; j++) {
+        const ScanLookup &L = a.lk[j];
+        uint32_t val[kScanRows];
+        if (STATS) {
+#pragma unroll
+            for (int r = 0; r < kScanRows; r++) nprobe += alive[r];
+        }
+        if (L.mode == KM_K32) scan_round<KM_K32>(a, L, row, alive, vec, val, pre);
+        else scan_round<KM_K64>(a, L, row, alive, vec, val, pre);
+#pragma unroll
+        for (int r = 0; r < kScanRows; r++) {
+            if (!alive[r]) continue;
+            if (!CK(val[r] < L.cnpos)) { alive[r] = false; continue; }
+            if (STATS) nhit++;
+            hs[j][threadIdx.x * kScanRows + r] = val[r];
+            if (L.child_leaf) mult[r] *= L.clen[val[r]];
+        }
+    }
+    if (STATS) {
+        u64 np = wave_sum_u64(nprobe), nh = wave_sum_u64(nhit);
+        if (__lane_id() == 0 && (np | nh)) {
+            atomicAdd(&a.status->probe[a.node], np);
+            atomicAdd(&a.status->hit[a.node], nh);
+        }
+    }
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < kScanRows; r++) any |= alive[r];
+    if (!__any(any)) return;   // the common case: no survivor in the whole wave
+    if (a.emit) {
+        u64 tot = 0;
+#pragma unroll
+        for (int r = 0; r < kScanRows; r++) {
+            if (!alive[r]) continue;
+            u64 e = mult[r];
+            for (int q = 0; q < a.ntail; q++) {
+                if (a.tail_lk[q] < 0) { e *= a.tail_root_len[q]; continue; }
+                const uint32_t th = hs[a.tail_lk[q]][threadIdx.x * kScanRows + r];
+                if (!CK(th < a.tail_npos[q])) { e = 0; break; }
+                e *= a.tail_len[q][th];
+            }
+            tot += e;
+        }
+        tot = wave_sum_u64(tot);
+        if (__lane_id() == 0 && tot) atomicAdd(&a.status->count, tot);
+    }
+    if (!a.emit || a.materialize) {
+#pragma unroll
+        for (int r = 0; r < kScanRows; r++) {
+            const u64 pos = wave_reserve(alive[r], &a.status->survivors);
+            if (!alive[r] || !CK(pos < a.out.cap)) continue;
+            const FrontierDev &O = a.out;
+            for (int j = 0; j < a.nout; j++) O.vals[(u64)j * O.cap + pos] = a.cols[a.out_col[j]][row[r]];
+            for (int j = 0; j < a.nl; j++)
+                if (a.lk[j].hcol >= 0) O.hdl[(u64)a.lk[j].hcol * O.cap + pos] = hs[j][threadIdx.x * kScanRows + r];
+            if (O.mult) O.mult[pos] = mult[r];
+        }
+    }
+}
+
 // ------------------------------------------------------------------- emit
 // Materialization: every final binding stands for mult * prod(tail lengths)
 // result tuples; rows are laid out by a scan of those counts.
@@ -820,7 +1130,7 @@ hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, u64 n, uint32_t *b
 }
 
 hipError_t launch_filter_lt(const int32_t *col, u64 n, int32_t bound, uint32_t *out, u64 *counter, hipStream_t s) {
-    unsigned b = (unsigned)std::min<u64>(std::max<u64>(blocks_for(n, 256), 1), 8192);
+    unsigned b = (unsigned)std::max<u64>(blocks_for(n, 256 * kFilterItems), 1);
     hipLaunchKernelGGL(k_filter_lt, dim3(b), dim3(256), 0, s, col, n, bound, out, counter);
     return hipGetLastError();
 }
@@ -886,6 +1196,40 @@ hipError_t launch_emit_rows(const void *emit_dev, uint32_t E, const u64 *starts,
                        starts, nrows, base, st);
     return hipGetLastError();
 }
+
+hipError_t launch_scan_probe(const ScanLaunch &l, hipStream_t s) {
+    if (l.nl > kScanMaxLookups) return hipErrorInvalidValue;
+    if (l.n == 0) return hipSuccess;
+    ScanArgs a;
+    memset(&a, 0, sizeof(a));
+    for (int c = 0; c < FJ_MAX_COLS; c++) a.cols[c] = l.cols[c];
+    a.ncols = l.ncols; a.sel = l.sel; a.nrows = l.nrows; a.r0 = l.r0; a.n = l.n;
+    // 4-row vector loads need 16-byte aligned columns and a 4-aligned start
+    a.vec = kScanRows == 4 && (l.r0 % 4) == 0;
+    for (int c = 0; c < l.ncols; c++) a.vec = a.vec && ((uintptr_t)l.cols[c] % 16) == 0;
+    a.nl = l.nl;
+    for (int j = 0; j < l.nl; j++) {
+        a.lk[j] = l.lk[j];
+        a.keycol[l.lk[j].kc[0]] = 1;
+        if (l.lk[j].mode == KM_K64) a.keycol[l.lk[j].kc[1]] = 1;
+    }
+    a.nout = l.nout;
+    for (int j = 0; j < l.nout; j++) a.out_col[j] = l.out_col[j];
+    a.out = l.out; a.emit = l.emit; a.materialize = l.materialize;
+    a.ntail = l.ntail;
+    for (int q = 0; q < l.ntail; q++) {
+        a.tail_lk[q] = l.tail_lk[q]; a.tail_len[q] = l.tail_len[q];
+        a.tail_npos[q] = l.tail_npos[q]; a.tail_root_len[q] = l.tail_root_len[q];
+    }
+    a.status = l.status; a.count_stats = l.count_stats; a.node = l.node;
+    if (l.count_stats)
+            hipLaunchKernelGGL(k_scan_probe<true>, dim3(blocks_for(l.n, 256 * kScanRows)), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_scan_probe<false>, dim3(blocks_for(l.n, 256 * kScanRows)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+int scan_max_lookups() { return kScanMaxLookups; }
 
 size_t emit_dev_size() { return sizeof(EmitDev); }
 

@@ -40,6 +40,31 @@ struct ProbeLaunch {
     uint32_t dcap;         // capacity of the deferral lists
 };
 
+struct ScanLaunch {
+    const int32_t *cols[FJ_MAX_COLS];
+    int ncols;
+    const uint32_t *sel;
+    uint32_t nrows;
+    uint32_t r0;
+    uint32_t n;
+    int nl;
+    ScanLookup lk[FJ_MAX_ATOMS];
+    int nout;
+    int out_col[FJ_MAX_VARS];
+    FrontierDev out;
+    int emit, materialize;
+    int ntail;
+    int tail_lk[FJ_MAX_NODES];
+    const uint32_t *tail_len[FJ_MAX_NODES];
+    uint32_t tail_npos[FJ_MAX_NODES];
+    uint32_t tail_root_len[FJ_MAX_NODES];
+    StatusDev *status;
+    int count_stats;
+    int node;
+};
+
+hipError_t launch_scan_probe(const ScanLaunch &l, hipStream_t s);
+int scan_max_lookups();
 hipError_t launch_fill_u32(uint32_t *p, unsigned long long n, uint32_t v, hipStream_t s);
 hipError_t launch_table_init(void *table, unsigned long long nslots, int mode, hipStream_t s);
 hipError_t launch_root_init(const LevelDev &L, uint32_t nroot, hipStream_t s);

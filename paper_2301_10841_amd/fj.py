@@ -47,7 +47,7 @@ class QueryS(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("tile", C.c_int64), ("block", C.c_int32), ("timing", C.c_int32),
-                ("tail", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("tail", C.c_int32), ("generic", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class Stats(C.Structure):
@@ -182,7 +182,7 @@ class Context:
     """A libfj context bound to a device and a torch stream."""
 
     def __init__(self, device: int = 0, stream=None, tile: int = 0, block: int = 0,
-                 timing: bool = False, tail: int = 0):
+                 timing: bool = False, tail: int = 0, generic: bool = False):
         import torch
         self.device = device
         if stream is None:
@@ -193,6 +193,7 @@ class Context:
         opt.block = block
         opt.timing = 1 if timing else 0
         opt.tail = tail
+        opt.generic = 1 if generic else 0
         h = C.c_void_p()
         _check(lib().fj_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(opt), C.byref(h)))
         self.h = h.value

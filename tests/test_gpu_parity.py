@@ -295,3 +295,24 @@ def test_repeat_and_rebuild(fjm, ctx):
     assert c1 == c2 == c3 == want
     for c in colts:
         c.free()
+
+
+def test_scan_path_matches_generic_kernel(fjm, ctx):
+    # the specialised first-node kernel and the generic one give the same
+    # results and the same lookup counts
+    fj, _ = fjm
+    gen = fj.Context(0, tile=1 << 20, generic=True)
+    try:
+        cases = [datagen.star_schema(7, n_fact=50_000, n_dim=5_000),
+                 datagen.synth.triangle_query(datagen.triangle_edges(3, n_edges=3000, n_vertices=400))]
+        cases += [q for q in datagen.batch_mix(5, n_queries=6, max_rows=20_000)[0]]
+        for dq in cases:
+            order = list(range(len(dq.atoms)))
+            a = gpu_run(fjm, ctx, dq, order, True, stats=True)
+            b = gpu_run(fjm, gen, dq, order, True, stats=True)
+            assert a["count"] == b["count"], dq.kind
+            assert_same_rows(a["rows"], b["rows"])
+            assert a["stats"].per_node()[0]["probe"] == b["stats"].per_node()[0]["probe"]
+            assert a["stats"].per_node()[0]["hit"] == b["stats"].per_node()[0]["hit"]
+    finally:
+        gen.close()
