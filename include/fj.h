@@ -164,9 +164,16 @@ void fj_plan_free(fj_plan *p);
 
 /* Pushed-down selection sigma_{col < bound} (Section 2.1): writes the row
    offsets r with col[r] < bound into out_sel (device, capacity nrows) in
-   unspecified order and their number to *out_n (host).  col is device. */
+   row order and their number to *out_n (host).  col is device. */
 fj_status fj_filter_lt(fj_ctx *ctx, const int32_t *col, int64_t nrows, int32_t bound,
                        uint32_t *out_sel, int64_t *out_n);
+
+/* Several selections with one synchronization: selection i keeps the rows
+   r < nrows[i] of device column cols[i] with cols[i][r] < bounds[i], writing
+   their offsets to outs[i] (device, capacity nrows[i]) in row order and
+   their number to counts[i] (host).  n <= FJ_MAX_ATOMS. */
+fj_status fj_filter_lt_batch(fj_ctx *ctx, int32_t n, const int32_t *const *cols, const int64_t *nrows,
+                             const int32_t *bounds, uint32_t *const *outs, int64_t *counts);
 
 /* -------------------------------------------------------------------- COLTs */
 

@@ -91,6 +91,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct fj_ctx {
     int device = 0;
+    int num_cus = 256;
     hipStream_t stream = nullptr;
     fj_options opt{};
     StatusDev *status_d = nullptr;
@@ -197,6 +198,8 @@ struct fj_colt {
     int lev_var[fj::kMaxLevels][FJ_MAX_COLS] = {{0}};
     LevelDev lev[fj::kMaxLevels + 1];
     u64 table_slots[fj::kMaxLevels] = {0};
+    fj::FillList *fill_dev = nullptr;   // regions the (re)build initialises
+    u64 fill_words = 0;
     std::vector<void *> allocs;
 };
 
@@ -266,30 +269,44 @@ void colt_free_all(fj_colt *t) {
 
 }  // namespace
 
+// Scratch layout of one force: lens (nh) | pre (nh + 1) | wslot (W) |
+// cntv (W, 64-bit) | ex (W + 1, 64-bit).
+struct ForceScratch {
+    size_t off_pre, off_w, off_c, off_e;
+    ForceScratch(uint32_t nh, u64 wmax) {
+        off_pre = align256(sizeof(uint32_t) * nh);
+        off_w = align256(off_pre + sizeof(uint32_t) * (nh + 1));
+        off_c = align256(off_w + sizeof(uint32_t) * (wmax + 1));
+        off_e = align256(off_c + sizeof(u64) * (wmax + 1));
+    }
+    size_t bytes(u64 wmax) const { return off_e + align256(sizeof(u64) * (wmax + 2)); }
+};
+
 // Force every handle queued on level l of colt t (the queue holds nh handle
 // starts; W is their total length when the caller knows it, else ~0).
+// pre_ready: the prefix of the handle lengths is already in scratch (the
+// single root handle, written by the COLT init kernel).
 static fj_status force_queue(fj_ctx *c, fj_colt *t, int l, uint32_t nh, u64 W_known, int timer_cls,
-                             fj_stats *stats, int node) {
+                             fj_stats *stats, int node, bool pre_ready = false) {
     if (nh == 0) return FJ_OK;
     LevelDev &L = t->lev[l];
     LevelDev &C = t->lev[l + 1];
-    // scratch: lens (nh) | pre (nh + 1) | wslot | wrank | cntv | ex (W + 1)
-    size_t off_lens = 0;
-    size_t off_pre = align256(off_lens + sizeof(uint32_t) * nh);
-    size_t off_w = align256(off_pre + sizeof(uint32_t) * (nh + 1));
     u64 Wmax = W_known != ~0ull ? W_known : t->nroot;
-    size_t wbytes = align256(sizeof(uint32_t) * (Wmax + 1));
-    FJ_TRY(c->force.ensure(off_w + 4 * wbytes, c->stream));
-    uint32_t *lens = c->force.as<uint32_t>(off_lens);
-    uint32_t *pre = c->force.as<uint32_t>(off_pre);
+    ForceScratch fs(nh, Wmax);
+    FJ_TRY(c->force.ensure(fs.bytes(Wmax), c->stream));
+    uint32_t *lens = c->force.as<uint32_t>(0);
+    uint32_t *pre = c->force.as<uint32_t>(fs.off_pre);
     Timer tm(c, timer_cls);
-    FJ_HIP(fj::launch_fq_lens(L, L.fq, nh, lens, c->status_d, c->stream));
-    FJ_TRY(scan_u32(c, lens, pre, nh));
+    if (!pre_ready) {
+        FJ_HIP(fj::launch_fq_lens(L, L.fq, nh, lens, c->status_d, c->stream));
+        FJ_TRY(scan_u32(c, lens, pre, nh));
+    }
     u64 W = W_known;
     if (W == ~0ull) {
         FJ_TRY(sync_status(c));
         W = c->status_h->total32;
     }
+    if (W > Wmax) return fail(FJ_ERR_HIP, "forced offsets exceed the relation size");
     fj::ForceLaunch f;
     f.L = L;
     f.C = C;
@@ -298,19 +315,16 @@ static fj_status force_queue(fj_ctx *c, fj_colt *t, int l, uint32_t nh, u64 W_kn
     f.nh = nh;
     f.pre = pre;
     f.W = (uint32_t)W;
-    f.wslot = c->force.as<uint32_t>(off_w);
-    f.wrank = c->force.as<uint32_t>(off_w + wbytes);
-    f.cntv = c->force.as<uint32_t>(off_w + 2 * wbytes);
-    f.ex = c->force.as<uint32_t>(off_w + 3 * wbytes);
+    f.wslot = c->force.as<uint32_t>(fs.off_w);
+    f.cntv = c->force.as<u64>(fs.off_c);
+    f.ex = c->force.as<u64>(fs.off_e);
     f.wcap = (uint32_t)(Wmax + 1);
     f.status = c->status_d;
-    if (W > Wmax) return fail(FJ_ERR_HIP, "forced offsets exceed the relation size");
-    FJ_HIP(fj::launch_force_phase(0, f, c->stream));
-    FJ_HIP(fj::launch_force_phase(1, f, c->stream));
-    FJ_HIP(fj::launch_force_phase(2, f, c->stream));
-    FJ_TRY(scan_u32(c, f.cntv, f.ex, W));
-    FJ_HIP(fj::launch_force_phase(3, f, c->stream));
-    FJ_HIP(fj::launch_force_phase(4, f, c->stream));
+    FJ_HIP(fj::launch_force_phase(0, f, c->stream));   // insert and count
+    FJ_HIP(fj::launch_force_phase(1, f, c->stream));   // (1, count) per new key
+    FJ_TRY(scan_u64(c, f.cntv, f.ex, W));               // ranks and child starts
+    FJ_HIP(fj::launch_force_phase(2, f, c->stream));   // publish children
+    FJ_HIP(fj::launch_force_phase(3, f, c->stream));   // scatter offsets
     if (stats && node >= 0) {
         stats->forced[node] += nh;
         stats->forced_offsets[node] += W;
@@ -318,26 +332,72 @@ static fj_status force_queue(fj_ctx *c, fj_colt *t, int l, uint32_t nh, u64 W_kn
     return FJ_OK;
 }
 
-static fj_status colt_reset(fj_ctx *c, fj_colt *t) {
-    hipStream_t s = c->stream;
-    for (int l = 0; l <= t->nlev; l++) t->lev[l].nrows = (uint32_t)t->nrows;
+// The regions a (re)build initialises: state words, child counters and
+// hash slots of every level (slots empty, the reserved slot unclaimed).
+static fj_status colt_fill_list(fj_colt *t) {
+    fj::FillList fl;
+    memset(&fl, 0, sizeof(fl));
+    u64 total = 0;
+    bool overflow = false;
+    auto add = [&](uint32_t *p, u64 nwords, std::initializer_list<uint32_t> pat) {
+        if (!p || !nwords) return;
+        if (fl.n >= fj::kMaxFill) { overflow = true; return; }
+        fj::FillRegion &r = fl.r[fl.n++];
+        r.p = p;
+        r.nwords = nwords;
+        r.period = (int)pat.size();
+        int i = 0;
+        for (uint32_t v : pat) r.pat[i++] = v;
+        total += nwords;
+    };
+    const u64 n = std::max<uint32_t>(t->cap_rows, 1);
     for (int l = 0; l < t->nlev; l++) {
         LevelDev &L = t->lev[l];
-        size_t n = std::max<uint32_t>(t->cap_rows, 1);
-        FJ_HIP(hipMemsetAsync(L.st, 0, n * sizeof(uint32_t), s));
+        add(L.st, l == 0 ? 1 : n, {0u});
         if (!L.cnt) continue;  // directly iterated base table
-        FJ_HIP(hipMemsetAsync(L.rank_ctr, 0, n * sizeof(uint32_t), s));
-        FJ_HIP(hipMemsetAsync(L.cnt, 0, n * sizeof(uint32_t), s));
-        if (L.table) FJ_HIP(fj::launch_table_init(L.table, t->table_slots[l], L.mode, s));
+        add(L.cnt, n, {0u});
+        if (!L.table) continue;
+        const u64 ns = t->table_slots[l];
+        uint32_t *T = (uint32_t *)L.table;
+        if (L.mode == fj::KM_K32) {
+            add(T, 2 * (ns - 1), {fj::kEmpty32, 0u});
+            add(T + 2 * (ns - 1), 2, {0u});
+        } else if (L.mode == fj::KM_K64) {
+            add(T, 4 * (ns - 1), {fj::kEmpty32, fj::kEmpty32, 0u, 0u});
+            add(T + 4 * (ns - 1), 4, {0u});
+        } else {
+            add(T, 4 * ns, {fj::kEmpty32, fj::kEmpty32, 0u, 0u});
+        }
     }
+    if (overflow) return fail(FJ_ERR_UNSUPPORTED, "too many COLT levels");
+    fj::FillList *d = nullptr;
+    FJ_TRY(colt_alloc(t, &d, 1));
+    FJ_HIP(hipMemcpy(d, &fl, sizeof(fl), hipMemcpyHostToDevice));
+    t->fill_dev = d;
+    t->fill_words = total;
+    return FJ_OK;
+}
+
+static fj_status colt_reset(fj_ctx *c, fj_colt *t) {
+    for (int l = 0; l <= t->nlev; l++) t->lev[l].nrows = (uint32_t)t->nrows;
     LevelDev &R = t->lev[0];
     R.offs = const_cast<uint32_t *>(t->sel);
-    FJ_HIP(fj::launch_root_init(R, t->nroot, s));
+    const bool force_root = t->root_built && t->nroot > 0;
+    uint32_t *pre = nullptr;
+    if (force_root) {
+        ForceScratch fs(1, t->nroot);
+        FJ_TRY(c->force.ensure(fs.bytes(t->nroot), c->stream));
+        pre = c->force.as<uint32_t>(fs.off_pre);
+    }
+    {
+        Timer tm(c, FJ_T_BUILD);
+        FJ_HIP(fj::launch_fill_list(t->fill_dev, t->fill_words, R, t->nroot, pre, c->stream));
+    }
     if (t->root_built) {
         if (t->nroot == 0) {
-            FJ_HIP(fj::launch_fill_u32(R.st, 1, 1u, s));  // forced, no keys
+            FJ_HIP(fj::launch_fill_u32(R.st, 1, 1u, c->stream));  // forced, no keys
         } else {
-            FJ_TRY(force_queue(c, t, 0, 1, t->nroot, FJ_T_BUILD, nullptr, -1));
+            FJ_TRY(force_queue(c, t, 0, 1, t->nroot, FJ_T_BUILD, nullptr, -1, true));
         }
     }
     return FJ_OK;
@@ -367,6 +427,11 @@ fj_status fj_ctx_create(int device, void *stream, const fj_options *opt, fj_ctx 
     fj_ctx *c = new fj_ctx();
     c->device = device;
     c->stream = (hipStream_t)stream;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+            c->num_cus = prop.multiProcessorCount;
+    }
     if (opt) c->opt = *opt;
     if (c->opt.tile <= 0) c->opt.tile = 1 << 24;
     if (c->opt.tile > (int64_t(1) << 30)) c->opt.tile = int64_t(1) << 30;
@@ -497,14 +562,43 @@ void fj_plan_free(fj_plan *p) { delete p; }
 fj_status fj_filter_lt(fj_ctx *c, const int32_t *col, int64_t nrows, int32_t bound, uint32_t *out_sel,
                        int64_t *out_n) {
     if (!c || !out_n || nrows < 0 || (nrows > 0 && (!col || !out_sel))) return fail(FJ_ERR_ARG, "bad argument");
+    if (nrows >= (int64_t(1) << 32)) return fail(FJ_ERR_UNSUPPORTED, "nrows must be below 2^32");
     FJ_HIP(hipSetDevice(c->device));
-    FJ_TRY(zero_status_field(c, offsetof(StatusDev, total), sizeof(u64)));
+    *out_n = 0;
+    if (nrows == 0) return FJ_OK;
+    FJ_TRY(c->scanb.ensure(((u64)nrows / 1024 + 2) * sizeof(uint32_t), c->stream));
     {
         Timer t(c, FJ_T_FILTER);
-        if (nrows > 0) FJ_HIP(fj::launch_filter_lt(col, (u64)nrows, bound, out_sel, &c->status_d->total, c->stream));
+        FJ_HIP(fj::launch_filter_lt(col, (u64)nrows, bound, out_sel, c->scanb.as<uint32_t>(),
+                                    &c->status_d->total32, c->stream));
     }
     FJ_TRY(sync_status(c));
-    *out_n = (int64_t)c->status_h->total;
+    *out_n = (int64_t)c->status_h->total32;
+    return FJ_OK;
+}
+
+fj_status fj_filter_lt_batch(fj_ctx *c, int32_t n, const int32_t *const *cols, const int64_t *nrows,
+                             const int32_t *bounds, uint32_t *const *outs, int64_t *counts) {
+    if (!c || n < 0 || n > FJ_MAX_ATOMS || (n && (!cols || !nrows || !bounds || !outs || !counts)))
+        return fail(FJ_ERR_ARG, "bad argument");
+    FJ_HIP(hipSetDevice(c->device));
+    size_t off[FJ_MAX_ATOMS + 1] = {0};
+    for (int i = 0; i < n; i++) {
+        if (nrows[i] < 0 || nrows[i] >= (int64_t(1) << 32)) return fail(FJ_ERR_ARG, "nrows out of range");
+        if (nrows[i] > 0 && (!cols[i] || !outs[i])) return fail(FJ_ERR_ARG, "null buffer");
+        off[i + 1] = off[i] + align256(((u64)nrows[i] / 1024 + 2) * sizeof(uint32_t));
+    }
+    FJ_TRY(c->scanb.ensure(off[n] + 256, c->stream));
+    FJ_TRY(zero_status_field(c, offsetof(StatusDev, ftotal), sizeof(c->status_h->ftotal)));
+    {
+        Timer t(c, FJ_T_FILTER);
+        for (int i = 0; i < n; i++)
+            if (nrows[i] > 0)
+                FJ_HIP(fj::launch_filter_lt(cols[i], (u64)nrows[i], bounds[i], outs[i], c->scanb.as<uint32_t>(off[i]),
+                                            &c->status_d->ftotal[i], c->stream));
+    }
+    FJ_TRY(sync_status(c));
+    for (int i = 0; i < n; i++) counts[i] = (int64_t)c->status_h->ftotal[i];
     return FJ_OK;
 }
 
@@ -540,7 +634,8 @@ fj_status fj_build_colt(fj_ctx *c, const fj_query *q, const fj_plan *p, int32_t 
             for (int j = 0; j < t->lev_nk[l]; j++)
                 for (int cc = 0; cc < q->atoms[atom].arity; cc++)
                     if (q->atoms[atom].vars[cc] == t->lev_var[l][j]) t->lev[l].kcol[j] = cc;
-        st = colt_reset(c, t);
+        st = colt_fill_list(t);
+        if (st == FJ_OK) st = colt_reset(c, t);
         if (st == FJ_OK) st = sync_status(c);
     }
     if (st != FJ_OK) {
@@ -690,14 +785,14 @@ fj_status exec_node(Exec &x, int k, uint32_t E) {
     std::vector<std::pair<int, int>> queues;
     for (size_t i = 0; i < p->nodes[k].size(); i++) queues.push_back({p->nodes[k][i].atom, p->sub_level[k][i]});
 
-    FJ_TRY(zero_status_field(c, offsetof(StatusDev, pending), sizeof(uint32_t)));
+    const uint32_t pend_base = c->status_h->pending;
     {
         Timer t(c, FJ_T_COVER);
         FJ_HIP(fj::launch_cover_choose(nd, E, cov, cnt, c->status_d, c->stream));
     }
     FJ_TRY(scan_u64(c, cnt, starts, E));
     FJ_TRY(sync_status(c));
-    if (c->status_h->pending) {
+    if (c->status_h->pending != pend_base) {
         FJ_TRY(force_pending_queues(x, k, queues));
         {
             Timer t(c, FJ_T_COVER);
@@ -711,7 +806,9 @@ fj_status exec_node(Exec &x, int k, uint32_t E) {
     const bool emit = (k == x.tail_from - 1);
     for (u64 t0 = 0; t0 < T; t0 += x.C) {
         uint32_t n = (uint32_t)std::min<u64>(x.C, T - t0);
-        FJ_TRY(zero_status_field(c, offsetof(StatusDev, survivors), 2 * sizeof(u64)));
+        // counters never reset: entries of this tile start at their bases
+        const u64 surv_base = c->status_h->survivors;
+        u64 def_base = c->status_h->deferred;
         fj::ProbeLaunch pl;
         pl.nd = nd;
         pl.starts = starts;
@@ -727,6 +824,8 @@ fj_status exec_node(Exec &x, int k, uint32_t E) {
         pl.count_stats = x.stats != nullptr;
         pl.block = c->opt.block;
         pl.dcap = (uint32_t)x.C;
+        pl.surv_base = surv_base;
+        pl.def_base = def_base;
         {
             Timer t(c, k == 0 ? FJ_T_PROBE0 : FJ_T_PROBE);
             FJ_HIP(fj::launch_probe(pl, c->stream));
@@ -736,20 +835,21 @@ fj_status exec_node(Exec &x, int k, uint32_t E) {
         uint32_t *din = x.dA, *dout = x.dB;
         uint8_t *din_j = x.dA_j, *dout_j = x.dB_j;
         int rounds = 0;
-        while (c->status_h->deferred) {
+        while (c->status_h->deferred != def_base) {
             // each round forces the tries the deferred tuples met, so a tuple
             // advances by at least one lookup per round
             if (++rounds > (int)p->nodes[k].size() + 1)
                 return fail(FJ_ERR_HIP, "lazy forcing made no progress");
-            uint32_t nd_n = (uint32_t)c->status_h->deferred;
+            uint32_t nd_n = (uint32_t)(c->status_h->deferred - def_base);
+            def_base = c->status_h->deferred;
             if (x.stats) x.stats->deferred += nd_n;
             FJ_TRY(force_pending_queues(x, k, queues));
-            FJ_TRY(zero_status_field(c, offsetof(StatusDev, deferred), sizeof(u64)));
             pl.din = din;
             pl.din_j = din_j;
             pl.dout = dout;
             pl.dout_j = dout_j;
             pl.n = nd_n;
+            pl.def_base = def_base;
             {
                 Timer t(c, FJ_T_PROBE);
                 FJ_HIP(fj::launch_probe(pl, c->stream));
@@ -758,7 +858,7 @@ fj_status exec_node(Exec &x, int k, uint32_t E) {
             std::swap(din, dout);
             std::swap(din_j, dout_j);
         }
-        const uint32_t surv = (uint32_t)c->status_h->survivors;
+        const uint32_t surv = (uint32_t)(c->status_h->survivors - surv_base);
         if (x.stats && !emit) x.stats->survivors[k] += surv;
         if (emit) {
             if (x.out) FJ_TRY(emit_rows(x, surv));
@@ -833,16 +933,17 @@ fj_status exec_scan_node(Exec &x, int cover_sub, u64 T, uint32_t) {
     if (x.stats) x.stats->cover[0] += T;
     for (u64 t0 = 0; t0 < T; t0 += x.C) {
         uint32_t n = (uint32_t)std::min<u64>(x.C, T - t0);
-        FJ_TRY(zero_status_field(c, offsetof(StatusDev, survivors), 2 * sizeof(u64)));
+        const u64 surv_base = c->status_h->survivors;
         sl.r0 = (uint32_t)t0;
         sl.n = n;
+        sl.surv_base = surv_base;
         {
             Timer t(c, FJ_T_PROBE0);
             FJ_HIP(fj::launch_scan_probe(sl, c->stream));
         }
         if (x.stats) x.stats->tiles++;
         FJ_TRY(sync_status(c));
-        const uint32_t surv = (uint32_t)c->status_h->survivors;
+        const uint32_t surv = (uint32_t)(c->status_h->survivors - surv_base);
         if (sl.emit) {
             if (x.out) FJ_TRY(emit_rows(x, surv));
         } else {
@@ -1033,8 +1134,10 @@ extern "C" fj_status fj_execute(fj_ctx *c, const fj_query *q, const fj_plan *p, 
         FJ_HIP(hipStreamSynchronize(c->stream));
     }
 
-    // clear the counters but keep any error a build left for the next check
+    // clear the counters but keep any error a build left for the next check;
+    // the host copy mirrors the cleared counters (they are read as bases)
     FJ_HIP(hipMemsetAsync(c->status_d, 0, offsetof(StatusDev, err_line), c->stream));
+    memset(c->status_h, 0, offsetof(StatusDev, err_line));
     fj_status st;
     if (x.tail_from == 0) {
         // every node is a product of base tables: one empty binding

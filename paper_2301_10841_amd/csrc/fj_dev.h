@@ -124,6 +124,19 @@ struct ScanLookup {
     int hcol;              // output handle column of this atom, or -1
 };
 
+// Regions a COLT (re)build initialises in one launch.
+struct FillRegion {
+    uint32_t *p;
+    unsigned long long nwords;
+    uint32_t pat[4];
+    int period;
+};
+constexpr int kMaxFill = 6 * kMaxLevels + 4;
+struct FillList {
+    int n;
+    FillRegion r[kMaxFill];
+};
+
 // Host <-> device status block, one per context.
 struct StatusDev {
     unsigned long long count;      // result tuples so far
@@ -135,6 +148,7 @@ struct StatusDev {
     uint32_t fq_n[FJ_MAX_ATOMS * kMaxLevels];  // force-queue lengths per (atom, level)
     uint32_t pending;              // entries whose cover had to be forced first
     uint32_t total32;              // 32-bit scan totals
+    uint32_t ftotal[FJ_MAX_ATOMS];  // counts of a batch of selections
     uint32_t err_line;             // first failed device bounds check (source line)
     uint32_t err_count;            // failed device bounds checks
 };

@@ -127,6 +127,12 @@ __device__ __forceinline__ void set_slot_val(const LevelDev &L, u64 i, uint32_t 
     else ((SlotRep *)L.table)[i].val = v;
 }
 
+__device__ __forceinline__ uint32_t *slot_val_ptr(const LevelDev &L, u64 i) {
+    if (L.mode == KM_K32) return &((Slot32 *)L.table)[i].val;
+    if (L.mode == KM_K64) return &((Slot64 *)L.table)[i].val;
+    return &((SlotRep *)L.table)[i].val;
+}
+
 // Insert-or-find for force(); `row` is the representative row for KM_REP.
 __device__ __forceinline__ u64 table_insert(const LevelDev &L, const int32_t *const *cols, const Key &k,
                                             uint32_t row, bool &claimed) {
@@ -141,7 +147,7 @@ __device__ __forceinline__ u64 table_insert(const LevelDev &L, const int32_t *co
         }
         u64 i = bucket_start<Slot32>(mix32(key), mask);
         for (u64 n = 0; n <= mask; n++) {
-            uint32_t c = __atomic_load_n(&T[i].key, __ATOMIC_RELAXED);
+            uint32_t c = T[i].key;   // may be stale-empty; the CAS settles it
             if (c == key) return i;
             if (c == kEmpty32) {
                 uint32_t old = atomicCAS(&T[i].key, kEmpty32, key);
@@ -159,7 +165,7 @@ __device__ __forceinline__ u64 table_insert(const LevelDev &L, const int32_t *co
         }
         u64 i = bucket_start<Slot64>(mix64(key), mask);
         for (u64 n = 0; n <= mask; n++) {
-            u64 c = __atomic_load_n(&T[i].key, __ATOMIC_RELAXED);
+            u64 c = T[i].key;        // may be stale-empty; the CAS settles it
             if (c == key) return i;
             if (c == kEmpty64) {
                 u64 old = atomicCAS(&T[i].key, kEmpty64, key);
@@ -173,7 +179,7 @@ __device__ __forceinline__ u64 table_insert(const LevelDev &L, const int32_t *co
         u64 mine = ((u64)row << 32) | k.h;
         u64 i = bucket_start<SlotRep>(rep_hash(k, L.nk), mask);
         for (u64 n = 0; n <= mask; n++) {
-            u64 c = __atomic_load_n(&T[i].hr, __ATOMIC_RELAXED);
+            u64 c = T[i].hr;         // may be stale-empty; the CAS settles it
             if (c == kEmpty64) {
                 u64 old = atomicCAS(&T[i].hr, kEmpty64, mine);
                 if (old == kEmpty64) { claimed = true; return i; }
@@ -246,11 +252,21 @@ __global__ void k_table_init(void *table, u64 nslots, int mode) {
     }
 }
 
-__global__ void k_root_init(LevelDev L, uint32_t nroot) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        L.len[0] = nroot;
-        L.st[0] = 0;
-        if (L.fq) L.fq[0] = 0;
+// Fill a list of regions with periodic 32-bit patterns (table slots, zeroed
+// state arrays) in one launch; also set the root handle and the one-handle
+// force queue of the root.
+__global__ void k_fill_list(const FillList *__restrict__ fl, LevelDev root, uint32_t nroot, uint32_t *pre) {
+    const u64 stride = (u64)gridDim.x * blockDim.x;
+    const u64 tid = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int k = 0; k < fl->n; k++) {
+        const FillRegion &r = fl->r[k];
+        for (u64 i = tid; i < r.nwords; i += stride) r.p[i] = r.pat[i % (u64)r.period];
+    }
+    if (tid == 0) {
+        root.len[0] = nroot;
+        root.st[0] = 0;
+        if (root.fq) root.fq[0] = 0;
+        if (pre) { pre[0] = 0; pre[1] = nroot; }
     }
 }
 
@@ -296,7 +312,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const T *in, u64 n
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kScanThreads) k_scan_blocks(T *bsum, u64 nb, T *total_out) {
+__global__ void __launch_bounds__(kScanThreads) k_scan_blocks(T *bsum, u64 nb, T *total_out, T *out_last) {
     __shared__ T lds[17];
     T carry = 0;
     for (u64 c = 0; c < nb; c += kScanThreads) {
@@ -307,7 +323,10 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_blocks(T *bsum, u64 nb, T
         if (i < nb) bsum[i] = carry + ex;
         carry += tot;
     }
-    if (threadIdx.x == 0 && total_out) *total_out = carry;
+    if (threadIdx.x == 0) {
+        if (total_out) *total_out = carry;
+        if (out_last) *out_last = carry;
+    }
 }
 
 template <typename T>
@@ -331,32 +350,45 @@ __global__ void k_scan_total(T *out, u64 n, const T *total) {
 }
 
 // ----------------------------------------------------------------- filter
-// sigma_{col < bound}: row offsets of passing rows.  Each workgroup scans a
-// contiguous chunk, counts its passing rows, reserves their output range
-// with one atomic and writes them; rows keep their order within a thread.
-constexpr int kFilterItems = 16;
+// sigma_{col < bound}: row offsets of passing rows, in row order.  Three
+// launches without atomics: per-block pass counts, a scan of the counts, and
+// a rescan that writes each block's rows at its offset.  Each thread reads
+// four consecutive rows with one 16-byte load.
+constexpr int kFilterRows = 4;
+constexpr int kFilterBlock = 256 * kFilterRows;
 
-__global__ void __launch_bounds__(256) k_filter_lt(const int32_t *__restrict__ col, u64 n, int32_t bound,
-                                                   uint32_t *__restrict__ out, u64 *counter) {
+__device__ __forceinline__ uint32_t filter_bits(const int32_t *col, u64 n, int32_t bound, u64 first, bool vec) {
+    uint32_t bits = 0;
+    if (vec && first + kFilterRows <= n) {
+        const int4 x = *(const int4 *)(col + first);
+        bits = (uint32_t)(x.x < bound) | ((uint32_t)(x.y < bound) << 1) | ((uint32_t)(x.z < bound) << 2) |
+               ((uint32_t)(x.w < bound) << 3);
+    } else {
+        for (int r = 0; r < kFilterRows; r++)
+            if (first + r < n && col[first + r] < bound) bits |= 1u << r;
+    }
+    return bits;
+}
+
+__global__ void __launch_bounds__(256) k_filter_count(const int32_t *__restrict__ col, u64 n, int32_t bound, int vec,
+                                                      uint32_t *bsum) {
     __shared__ uint32_t lds[17];
-    __shared__ u64 block_base;
-    const u64 chunk = (u64)blockDim.x * kFilterItems;
-    const u64 start = (u64)blockIdx.x * chunk;
-    uint32_t bits = 0, cnt = 0;
-    for (int k = 0; k < kFilterItems; k++) {
-        u64 i = start + (u64)k * blockDim.x + threadIdx.x;
-        bool pass = i < n && __builtin_nontemporal_load(col + i) < bound;
-        bits |= (uint32_t)pass << k;
-        cnt += pass;
-    }
+    const u64 first = ((u64)blockIdx.x * 256 + threadIdx.x) * kFilterRows;
+    const uint32_t bits = filter_bits(col, n, bound, first, vec);
     uint32_t tot;
-    uint32_t ex = block_excl_scan<uint32_t>(cnt, lds, tot);
-    if (threadIdx.x == 0) block_base = tot ? atomicAdd(counter, (u64)tot) : 0ull;
-    __syncthreads();
-    u64 pos = block_base + ex;
-    for (int k = 0; k < kFilterItems; k++) {
-        if (bits & (1u << k)) out[pos++] = (uint32_t)(start + (u64)k * blockDim.x + threadIdx.x);
-    }
+    block_excl_scan<uint32_t>((uint32_t)__popc(bits), lds, tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(256) k_filter_write(const int32_t *__restrict__ col, u64 n, int32_t bound, int vec,
+                                                      const uint32_t *bsum, uint32_t *__restrict__ out) {
+    __shared__ uint32_t lds[17];
+    const u64 first = ((u64)blockIdx.x * 256 + threadIdx.x) * kFilterRows;
+    const uint32_t bits = filter_bits(col, n, bound, first, vec);
+    uint32_t tot;
+    uint32_t pos = bsum[blockIdx.x] + block_excl_scan<uint32_t>((uint32_t)__popc(bits), lds, tot);
+    for (int r = 0; r < kFilterRows; r++)
+        if (bits & (1u << r)) out[pos++] = (uint32_t)(first + r);
 }
 
 // ------------------------------------------------------------------ checks
@@ -385,10 +417,9 @@ struct ForceArgs {
     const uint32_t *pre;    // exclusive scan of their lengths (nh + 1)
     uint32_t W;             // total offsets
     uint32_t wcap;          // capacity of the per-item scratch arrays
-    uint32_t *wslot;        // per item: slot index (low 32 bits)
-    uint32_t *wrank;        // per item: rank | kClaim
-    uint32_t *cntv;         // per item: cnt of child position
-    uint32_t *ex;           // per item: exclusive scan of cntv
+    uint32_t *wslot;        // per item: slot index | kClaim for the item that inserted the key
+    u64 *cntv;              // per item: (1 << 32 | offsets of the key) for claimers, else 0
+    u64 *ex;                // exclusive scan of cntv (W + 1)
     StatusDev *status;
 };
 
@@ -413,102 +444,92 @@ __global__ void __launch_bounds__(256) k_fq_lens(LevelDev L, const uint32_t *fq,
     lens[j] = CK(p < L.npos) ? L.len[p] : 0u;
 }
 
+// Pass 1: insert each offset's key (handle, key values) and count the
+// offsets per key in the slot's value word; the inserting item is marked.
 __global__ void __launch_bounds__(256) k_force_insert(ForceArgs a) {
     StatusDev *status = a.status;
     uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= a.W) return;
     uint32_t j, p, i, row;
-    if (!force_item(a, w, j, p, i, row)) return;
-    if (a.L.mode == KM_ZERO) {
-        if (i == 0) a.L.rank_ctr[p] = 1;
-        a.wrank[w] = i == 0 ? (0u | kClaim) : 0u;
+    if (!force_item(a, w, j, p, i, row)) { a.wslot[w] = 0; return; }
+    if (a.L.mode == KM_ZERO) {             // one key: the first offset claims it
+        a.wslot[w] = i == 0 ? kClaim : 0u;
         return;
     }
     Key k;
     k.h = p;
     for (int c = 0; c < a.L.nk; c++) k.v[c] = a.cols[a.L.kcol[c]][row];
     bool claimed;
-    u64 sl = table_insert(a.L, a.cols, k, row, claimed);
-    const bool good = CK(sl < a.L.nslots);
-    if (good) a.wslot[w] = (uint32_t)sl;
-    // new keys take consecutive ranks of their handle; lanes of a wave that
-    // claim keys of the same handle share one atomic
-    const bool want = good && claimed;
-    u64 pending = __ballot(want);
-    while (pending) {
-        const int leader = __ffsll((long long)pending) - 1;
-        const uint32_t pl = __shfl(p, leader, 64);
-        const u64 grp = __ballot(want && p == pl);
-        uint32_t base = 0;
-        if (__lane_id() == leader) base = atomicAdd(&a.L.rank_ctr[pl], (uint32_t)__popcll(grp));
-        base = __shfl(base, leader, 64);
-        if (want && p == pl) {
-            const uint32_t r = base + (uint32_t)__popcll(grp & ((1ull << __lane_id()) - 1ull));
-            set_slot_val(a.L, sl, r);
-            a.wrank[w] = r | kClaim;
+    const u64 sl = table_insert(a.L, a.cols, k, row, claimed);
+    if (!CK(sl < a.L.nslots && sl < kClaim)) { a.wslot[w] = 0; return; }
+    // the slot's value counts the offsets after the first: unique keys cost
+    // one CAS and no counter update
+    if (!claimed) atomicAdd(slot_val_ptr(a.L, sl), 1u);
+    a.wslot[w] = (uint32_t)sl | (claimed ? kClaim : 0u);
+}
+
+// Pass 2: each key's (1, offset count) at its inserting item; a scan of
+// these pairs gives every key its rank among its handle's keys (high half)
+// and the start of its child segment (low half).
+__global__ void __launch_bounds__(256) k_force_pack(ForceArgs a) {
+    uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= a.W) return;
+    const uint32_t ws = a.wslot[w];
+    u64 v = 0;
+    if (ws & kClaim) {
+        uint32_t cnt;
+        if (a.L.mode == KM_ZERO) {
+            const uint32_t j = a.nh == 1 ? 0u : upper_entry32(a.pre, 0, a.nh, w);
+            cnt = a.pre[j + 1] - a.pre[j];
+        } else {
+            cnt = *slot_val_ptr(a.L, ws & ~kClaim) + 1u;
         }
-        pending &= ~grp;
+        v = (1ull << 32) | cnt;
     }
-    if (good && !claimed) a.wrank[w] = 0;
+    a.cntv[w] = v;
 }
 
-__global__ void __launch_bounds__(256) k_force_count(ForceArgs a) {
-    StatusDev *status = a.status;
-    uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= a.W) return;
-    uint32_t j, p, i, row;
-    if (!force_item(a, w, j, p, i, row)) return;
-    uint32_t r = a.wrank[w];
-    if (!(r & kClaim)) {
-        if (a.L.mode == KM_ZERO) r = 0u;
-        else if (CK(a.wslot[w] < a.L.nslots)) r = slot_val(a.L, a.wslot[w]);
-        else return;
-        a.wrank[w] = r;
-    } else {
-        r &= ~kClaim;
-    }
-    if (!CK((u64)p + r < a.L.npos)) return;
-    atomicAdd(&a.L.cnt[p + r], 1u);
-}
-
-__global__ void __launch_bounds__(256) k_force_cntv(ForceArgs a) {
-    uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= a.W) return;
-    uint32_t j, p, i, row;
-    if (!force_item(a, w, j, p, i, row)) return;
-    a.cntv[w] = a.L.cnt[p + i];
-}
-
+// Pass 3: keys publish their child segment: key list entry, child length,
+// scatter cursor, and the map value becomes the child's start.  The first
+// item of each handle records its key count (the forced state).
 __global__ void __launch_bounds__(256) k_force_children(ForceArgs a) {
     StatusDev *status = a.status;
     uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= a.W) return;
     uint32_t j, p, i, row;
     if (!force_item(a, w, j, p, i, row)) return;
-    uint32_t nkeys = a.L.rank_ctr[p];
-    if (i < nkeys) {
-        uint32_t s = p + (a.ex[w] - a.pre[j]);
-        if (!CK(s < a.C.npos)) return;
-        a.L.kl[p + i] = s;
-        a.C.len[s] = a.L.cnt[p + i];
+    const u64 base = a.ex[a.pre[j]];
+    if (i == 0) {
+        const uint32_t nkeys = (uint32_t)(a.ex[a.pre[j + 1]] >> 32) - (uint32_t)(base >> 32);
+        a.L.rank_ctr[p] = nkeys;
+        a.L.st[p] = nkeys + 1;
     }
-    if (i == 0) a.L.st[p] = nkeys + 1;
+    const uint32_t ws = a.wslot[w];
+    if (!(ws & kClaim)) return;
+    const uint32_t rank = (uint32_t)(a.ex[w] >> 32) - (uint32_t)(base >> 32);
+    const uint32_t s = p + ((uint32_t)a.ex[w] - (uint32_t)base);
+    const uint32_t cnt = (uint32_t)a.cntv[w];
+    if (!CK((u64)p + rank < a.L.npos && s < a.C.npos && cnt > 0)) return;
+    a.L.kl[p + rank] = s;
+    a.C.len[s] = cnt;
+    a.L.cnt[s] = cnt;
+    if (a.L.mode != KM_ZERO) *slot_val_ptr(a.L, ws & ~kClaim) = s;
 }
 
+// Pass 4: every offset moves into its key's child segment.  The cursor
+// counts down to zero, leaving the counter array clean for the next force.
 __global__ void __launch_bounds__(256) k_force_scatter(ForceArgs a) {
     StatusDev *status = a.status;
     uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= a.W) return;
     uint32_t j, p, i, row;
     if (!force_item(a, w, j, p, i, row)) return;
-    uint32_t rw = a.wrank[w];
-    uint32_t r = rw & ~kClaim;
-    if (!CK((u64)p + r < a.L.npos)) return;
-    uint32_t s = a.L.kl[p + r];
-    uint32_t pos = s + atomicSub(&a.L.cnt[p + r], 1u) - 1u;
-    if (!CK(pos < a.C.npos && pos >= p && pos < p + a.L.len[p])) return;
+    const uint32_t ws = a.wslot[w];
+    const uint32_t s = a.L.mode == KM_ZERO ? p : *slot_val_ptr(a.L, ws & ~kClaim);
+    if (!CK(s >= p && s < a.C.npos)) return;
+    const uint32_t pos = s + atomicSub(&a.L.cnt[s], 1u) - 1u;
+    if (!CK(pos >= s && pos < p + a.L.len[p])) return;
     a.C.offs[pos] = row;
-    if ((rw & kClaim) && a.L.mode != KM_ZERO) set_slot_val(a.L, a.wslot[w], s);
 }
 
 // ----------------------------------------------------------- cover choice
@@ -602,6 +623,8 @@ struct ProbeArgs {
     uint32_t *dout;           // deferrals of this launch
     uint8_t *dout_j;
     uint32_t dcap;            // capacity of the deferral lists
+    u64 surv_base;            // survivor and deferral counters before this launch
+    u64 def_base;
     StatusDev *status;
     int count_stats;
 };
@@ -715,13 +738,14 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
         if (__lane_id() == 0 && c) atomicAdd(&a.status->count, c);
     }
     // deferred tuples
+    // the counters only grow; this launch's entries start at its base
     {
-        u64 pos = wave_reserve(defer, &a.status->deferred);
+        u64 pos = wave_reserve(defer, &a.status->deferred) - a.def_base;
         if (defer && CK(pos < a.dcap)) { a.dout[pos] = t; a.dout_j[pos] = (uint8_t)defer_j; }
     }
     // survivors to the output frontier
     const bool write = survive && (!nd.emit || nd.materialize);
-    u64 pos = wave_reserve(write, &a.status->survivors);
+    u64 pos = wave_reserve(write, &a.status->survivors) - a.surv_base;
     if (write && CK(pos < nd.out.cap)) {
         const FrontierDev &O = nd.out;
         for (int j = 0; j < nd.nout; j++) O.vals[(u64)j * O.cap + pos] = v[nd.out_slot[j]];
@@ -740,9 +764,6 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
 
 #ifndef FJ_SCAN_ROWS
 #define FJ_SCAN_ROWS 1
-#endif
-#ifndef FJ_SCAN_PRELOAD
-#define FJ_SCAN_PRELOAD 0
 #endif
 constexpr int kScanRows = FJ_SCAN_ROWS;
 constexpr int kScanMaxLookups = 8;
@@ -779,6 +800,7 @@ struct ScanArgs {
     StatusDev *status;
     int count_stats;
     int node;
+    u64 surv_base;            // survivor counter before this launch
 };
 
 // Bucket of a root map, held as 16-byte vector registers.
@@ -827,8 +849,7 @@ __device__ __forceinline__ int scan_bucket64(const Bucket &bk, u64 key, uint32_t
 // the reserved slot (mask + 1), whose key word is 1 once claimed.
 template <int MODE>
 __device__ __forceinline__ void scan_round(const ScanArgs &a, const ScanLookup &L, const uint32_t *row,
-                                           bool *alive, bool vec, uint32_t *val,
-                                           const int32_t (*pre)[FJ_MAX_COLS]) {
+                                           bool *alive, bool vec, uint32_t *val) {
     typedef typename std::conditional<MODE == KM_K32, Slot32, Slot64>::type SlotT;
     typedef typename std::conditional<MODE == KM_K32, uint32_t, u64>::type KeyT;
     constexpr u64 B = kBucketBytes / sizeof(SlotT);
@@ -837,19 +858,6 @@ __device__ __forceinline__ void scan_round(const ScanArgs &a, const ScanLookup &
     const int32_t *c0 = a.cols[L.kc[0]];
     const int32_t *c1 = a.cols[MODE == KM_K32 ? L.kc[0] : L.kc[1]];
     int32_t k0[kScanRows], k1[kScanRows];
-#if FJ_SCAN_PRELOAD
-    // keys come from the columns preloaded at kernel start
-#pragma unroll
-    for (int r = 0; r < kScanRows; r++) {
-        k0[r] = 0; k1[r] = 0;
-#pragma unroll
-        for (int c = 0; c < FJ_MAX_COLS; c++) {
-            k0[r] = c == L.kc[0] ? pre[r][c] : k0[r];
-            k1[r] = c == L.kc[1] ? pre[r][c] : k1[r];
-        }
-    }
-    bool all = false;
-#else
     // keys: one 16-byte load per column when the thread's rows are
     // consecutive and all alive, else one load per live row
     bool all = vec;
@@ -872,7 +880,6 @@ __device__ __forceinline__ void scan_round(const ScanArgs &a, const ScanLookup &
             if (MODE != KM_K32) k1[r] = alive[r] ? c1[row[r]] : 0;
         }
     }
-#endif
     KeyT key[kScanRows];
     u64 idx[kScanRows];
     Bucket bk[kScanRows];
@@ -931,15 +938,6 @@ __global__ void __launch_bounds__(256) k_scan_probe(ScanArgs a) {
     }
 #pragma unroll
     for (int r = 0; r < kScanRows; r++) alive[r] = alive[r] && CK(row[r] < a.nrows);
-    int32_t pre[kScanRows][FJ_MAX_COLS];
-#if FJ_SCAN_PRELOAD
-    // every key column of the thread's rows in one batch of loads
-#pragma unroll
-    for (int r = 0; r < kScanRows; r++)
-#pragma unroll
-        for (int c = 0; c < FJ_MAX_COLS; c++)
-            pre[r][c] = (c < a.ncols && a.keycol[c] && alive[r]) ? a.cols[c][row[r]] : 0;
-#endif
     // trie by trie over this thread's rows (Section 4.3's vectorized order)
     for (int j = 0; j < a.nl; j++) {
         const ScanLookup &L = a.lk[j];
@@ -948,8 +946,8 @@ __global__ void __launch_bounds__(256) k_scan_probe(ScanArgs a) {
 #pragma unroll
             for (int r = 0; r < kScanRows; r++) nprobe += alive[r];
         }
-        if (L.mode == KM_K32) scan_round<KM_K32>(a, L, row, alive, vec, val, pre);
-        else scan_round<KM_K64>(a, L, row, alive, vec, val, pre);
+        if (L.mode == KM_K32) scan_round<KM_K32>(a, L, row, alive, vec, val);
+        else scan_round<KM_K64>(a, L, row, alive, vec, val);
 #pragma unroll
         for (int r = 0; r < kScanRows; r++) {
             if (!alive[r]) continue;
@@ -1099,8 +1097,10 @@ hipError_t launch_table_init(void *table, u64 nslots, int mode, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_root_init(const LevelDev &L, uint32_t nroot, hipStream_t s) {
-    hipLaunchKernelGGL(k_root_init, dim3(1), dim3(64), 0, s, L, nroot);
+hipError_t launch_fill_list(const FillList *fl_dev, u64 total_words, const LevelDev &root, uint32_t nroot,
+                            uint32_t *pre, hipStream_t s) {
+    unsigned b = (unsigned)std::min<u64>(std::max<u64>(blocks_for(total_words, 256), 1), 4096);
+    hipLaunchKernelGGL(k_fill_list, dim3(b), dim3(256), 0, s, fl_dev, root, nroot, pre);
     return hipGetLastError();
 }
 
@@ -1114,10 +1114,9 @@ static hipError_t scan_impl(const T *in, T *out, u64 n, T *bsum, T *total, hipSt
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, bsum);
-    hipLaunchKernelGGL(k_scan_blocks<T>, dim3(1), dim3(kScanThreads), 0, s, bsum, nb, total);
+    hipLaunchKernelGGL(k_scan_blocks<T>, dim3(1), dim3(kScanThreads), 0, s, bsum, nb, total, out + n);
     hipLaunchKernelGGL(k_scan_apply<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n,
                        (const T *)bsum);
-    hipLaunchKernelGGL(k_scan_total<T>, dim3(1), dim3(64), 0, s, out, n, (const T *)total);
     return hipGetLastError();
 }
 
@@ -1129,9 +1128,15 @@ hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, u64 n, uint32_t *b
     return scan_impl<uint32_t>(in, out, n, bsum, total, s);
 }
 
-hipError_t launch_filter_lt(const int32_t *col, u64 n, int32_t bound, uint32_t *out, u64 *counter, hipStream_t s) {
-    unsigned b = (unsigned)std::max<u64>(blocks_for(n, 256 * kFilterItems), 1);
-    hipLaunchKernelGGL(k_filter_lt, dim3(b), dim3(256), 0, s, col, n, bound, out, counter);
+hipError_t launch_filter_lt(const int32_t *col, u64 n, int32_t bound, uint32_t *out, uint32_t *bsum,
+                            uint32_t *total, hipStream_t s) {
+    const u64 nb = std::max<u64>((n + kFilterBlock - 1) / kFilterBlock, 1);
+    const int vec = ((uintptr_t)col % 16) == 0;
+    hipLaunchKernelGGL(k_filter_count, dim3((unsigned)nb), dim3(256), 0, s, col, n, bound, vec, bsum);
+    hipLaunchKernelGGL(k_scan_blocks<uint32_t>, dim3(1), dim3(kScanThreads), 0, s, bsum, nb, total,
+                       (uint32_t *)nullptr);
+    hipLaunchKernelGGL(k_filter_write, dim3((unsigned)nb), dim3(256), 0, s, col, n, bound, vec, (const uint32_t *)bsum,
+                       out);
     return hipGetLastError();
 }
 
@@ -1146,16 +1151,15 @@ hipError_t launch_force_phase(int phase, const ForceLaunch &f, hipStream_t s) {
     a.L = f.L; a.C = f.C;
     for (int c = 0; c < FJ_MAX_COLS; c++) a.cols[c] = f.cols[c];
     a.fq = f.fq; a.nh = f.nh; a.pre = f.pre; a.W = f.W;
-    a.wslot = f.wslot; a.wrank = f.wrank; a.cntv = f.cntv; a.ex = f.ex;
+    a.wslot = f.wslot; a.cntv = f.cntv; a.ex = f.ex;
     a.wcap = f.wcap; a.status = f.status;
     dim3 g(blocks_for(f.W, 256)), b(256);
     if (f.W == 0) return hipSuccess;
     switch (phase) {
         case 0: hipLaunchKernelGGL(k_force_insert, g, b, 0, s, a); break;
-        case 1: hipLaunchKernelGGL(k_force_count, g, b, 0, s, a); break;
-        case 2: hipLaunchKernelGGL(k_force_cntv, g, b, 0, s, a); break;
-        case 3: hipLaunchKernelGGL(k_force_children, g, b, 0, s, a); break;
-        case 4: hipLaunchKernelGGL(k_force_scatter, g, b, 0, s, a); break;
+        case 1: hipLaunchKernelGGL(k_force_pack, g, b, 0, s, a); break;
+        case 2: hipLaunchKernelGGL(k_force_children, g, b, 0, s, a); break;
+        case 3: hipLaunchKernelGGL(k_force_scatter, g, b, 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1177,6 +1181,7 @@ hipError_t launch_probe(const ProbeLaunch &p, hipStream_t s) {
     a.nd = p.nd; a.starts = p.starts; a.cov = p.cov; a.E = p.E; a.t0 = p.t0; a.n = p.n;
     a.din = p.din; a.din_j = p.din_j; a.dout = p.dout; a.dout_j = p.dout_j;
     a.status = p.status; a.count_stats = p.count_stats; a.dcap = p.dcap;
+    a.surv_base = p.surv_base; a.def_base = p.def_base;
     if (p.n == 0) return hipSuccess;
     int bs = p.block > 0 ? p.block : 256;
     hipLaunchKernelGGL(k_probe, dim3(blocks_for(p.n, bs)), dim3(bs), 0, s, a);
@@ -1221,9 +1226,9 @@ hipError_t launch_scan_probe(const ScanLaunch &l, hipStream_t s) {
         a.tail_lk[q] = l.tail_lk[q]; a.tail_len[q] = l.tail_len[q];
         a.tail_npos[q] = l.tail_npos[q]; a.tail_root_len[q] = l.tail_root_len[q];
     }
-    a.status = l.status; a.count_stats = l.count_stats; a.node = l.node;
+    a.status = l.status; a.count_stats = l.count_stats; a.node = l.node; a.surv_base = l.surv_base;
     if (l.count_stats)
-            hipLaunchKernelGGL(k_scan_probe<true>, dim3(blocks_for(l.n, 256 * kScanRows)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_scan_probe<true>, dim3(blocks_for(l.n, 256 * kScanRows)), dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL(k_scan_probe<false>, dim3(blocks_for(l.n, 256 * kScanRows)), dim3(256), 0, s, a);
     return hipGetLastError();

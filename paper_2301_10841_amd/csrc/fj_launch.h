@@ -18,7 +18,8 @@ struct ForceLaunch {
     uint32_t nh;
     const uint32_t *pre;   // exclusive scan of their lengths (device, nh + 1)
     uint32_t W;            // total offsets of the queued handles
-    uint32_t *wslot, *wrank, *cntv, *ex;  // scratch, W (+1) entries each
+    uint32_t *wslot;       // scratch, W entries
+    unsigned long long *cntv, *ex;  // scratch, W and W + 1 entries
     uint32_t wcap;         // entries of each scratch array
     StatusDev *status;
 };
@@ -38,6 +39,7 @@ struct ProbeLaunch {
     int count_stats;
     int block;
     uint32_t dcap;         // capacity of the deferral lists
+    unsigned long long surv_base, def_base;  // counter values before the launch
 };
 
 struct ScanLaunch {
@@ -61,19 +63,21 @@ struct ScanLaunch {
     StatusDev *status;
     int count_stats;
     int node;
+    unsigned long long surv_base;
 };
 
 hipError_t launch_scan_probe(const ScanLaunch &l, hipStream_t s);
 int scan_max_lookups();
 hipError_t launch_fill_u32(uint32_t *p, unsigned long long n, uint32_t v, hipStream_t s);
 hipError_t launch_table_init(void *table, unsigned long long nslots, int mode, hipStream_t s);
-hipError_t launch_root_init(const LevelDev &L, uint32_t nroot, hipStream_t s);
+hipError_t launch_fill_list(const FillList *fl_dev, unsigned long long total_words, const LevelDev &root,
+                            uint32_t nroot, uint32_t *pre, hipStream_t s);
 hipError_t launch_scan_u64(const unsigned long long *in, unsigned long long *out, unsigned long long n,
                            unsigned long long *bsum, unsigned long long *total, hipStream_t s);
 hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, unsigned long long n, uint32_t *bsum,
                            uint32_t *total, hipStream_t s);
 hipError_t launch_filter_lt(const int32_t *col, unsigned long long n, int32_t bound, uint32_t *out,
-                            unsigned long long *counter, hipStream_t s);
+                            uint32_t *bsum, uint32_t *total, hipStream_t s);
 hipError_t launch_fq_lens(const LevelDev &L, const uint32_t *fq, uint32_t nh, uint32_t *lens, StatusDev *st,
                           hipStream_t s);
 hipError_t launch_force_phase(int phase, const ForceLaunch &f, hipStream_t s);

@@ -87,6 +87,7 @@ def lib():
         L.fj_plan_free.argtypes = [vp]
         L.fj_plan_free.restype = None
         L.fj_filter_lt.argtypes = [vp, vp, C.c_int64, C.c_int32, vp, P(C.c_int64)]
+        L.fj_filter_lt_batch.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp]
         L.fj_build_colt.argtypes = [vp, P(QueryS), vp, C.c_int32, P(Relation), P(vp)]
         L.fj_colt_rebuild.argtypes = [vp, vp, P(Relation)]
         L.fj_colt_free.argtypes = [vp]
@@ -94,7 +95,7 @@ def lib():
         L.fj_execute.argtypes = [vp, P(QueryS), vp, vp, P(C.c_uint64), vp, C.c_uint64,
                                  P(C.c_uint64), P(Stats)]
         for name in ("fj_ctx_create", "fj_timings", "fj_timings_reset", "fj_plan_from_binary",
-                     "fj_plan_from_nodes", "fj_plan_get", "fj_filter_lt", "fj_build_colt",
+                     "fj_plan_from_nodes", "fj_plan_get", "fj_filter_lt", "fj_filter_lt_batch", "fj_build_colt",
                      "fj_colt_rebuild", "fj_execute"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -229,6 +230,17 @@ class Context:
         _check(lib().fj_filter_lt(self.h, C.c_void_p(col.data_ptr()), n, int(bound),
                                   C.c_void_p(out_sel.data_ptr()), C.byref(cnt)))
         return out_sel, int(cnt.value)
+
+    def filter_lt_batch(self, specs):
+        """specs: list of (col tensor, bound, out tensor).  Returns the counts."""
+        n = len(specs)
+        cols = (C.c_void_p * max(n, 1))(*[c.data_ptr() for c, _, _ in specs])
+        nrows = (C.c_int64 * max(n, 1))(*[int(c.shape[0]) for c, _, _ in specs])
+        bounds = (C.c_int32 * max(n, 1))(*[int(b) for _, b, _ in specs])
+        outs = (C.c_void_p * max(n, 1))(*[o.data_ptr() for _, _, o in specs])
+        counts = (C.c_int64 * max(n, 1))()
+        _check(lib().fj_filter_lt_batch(self.h, n, cols, nrows, bounds, outs, counts))
+        return [int(counts[i]) for i in range(n)]
 
     # ---- COLTs
     def build_colt(self, q: QueryS, plan: Plan, atom: int, cols, sel=None, nsel: int = 0) -> "Colt":

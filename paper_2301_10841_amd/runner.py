@@ -30,12 +30,19 @@ class DeviceQuery:
         self.apply_filters()
 
     def apply_filters(self):
+        import torch
+        specs, atoms = [], []
         for a, f in enumerate(self.dq.filters):
             if f is None:
                 continue
             col = self.rel_cols[self.dq.atoms[a][0]][f[0]]
-            s, n = self.ctx.filter_lt(col, f[1], self.sel[a])
-            self.sel[a], self.nsel[a] = s, n
+            if self.sel[a] is None:
+                self.sel[a] = torch.empty(max(int(col.shape[0]), 1), dtype=torch.int32, device=col.device)
+            specs.append((col, f[1], self.sel[a]))
+            atoms.append(a)
+        if specs:
+            for a, n in zip(atoms, self.ctx.filter_lt_batch(specs)):
+                self.nsel[a] = n
 
     def atom_cols(self, a: int):
         return self.rel_cols[self.dq.atoms[a][0]]

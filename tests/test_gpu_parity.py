@@ -316,3 +316,20 @@ def test_scan_path_matches_generic_kernel(fjm, ctx):
             assert a["stats"].per_node()[0]["hit"] == b["stats"].per_node()[0]["hit"]
     finally:
         gen.close()
+
+
+def test_filters_match_numpy(fjm, ctx, torch_mod):
+    # the pushed-down selection returns the passing row offsets in row order
+    torch = torch_mod
+    rng = np.random.default_rng(4)
+    specs, want = [], []
+    for n, bound in ((1, 5), (1023, 50), (4097, 0), (100_003, 10), (1_000_000, 37)):
+        col = rng.integers(-20, 100, size=n).astype(np.int32)
+        want.append(np.nonzero(col < bound)[0].astype(np.int32))
+        specs.append((torch.from_numpy(col).cuda(), bound, torch.empty(n, dtype=torch.int32, device="cuda")))
+    counts = ctx.filter_lt_batch(specs)
+    for (c, b, out), w, k in zip(specs, want, counts):
+        assert k == w.shape[0]
+        assert np.array_equal(out[:k].cpu().numpy(), w)
+        out2, k2 = ctx.filter_lt(c, b)
+        assert k2 == k and np.array_equal(out2[:k2].cpu().numpy(), w)
