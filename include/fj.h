@@ -206,6 +206,39 @@ fj_status fj_execute(fj_ctx *ctx, const fj_query *q, const fj_plan *p, fj_colt *
                      uint64_t *count, int32_t *out, uint64_t cap, uint64_t *written,
                      fj_stats *stats);
 
+/* ------------------------------------------------------------------ batches */
+
+typedef struct fj_batch fj_batch;
+
+/* Batch options; zero fields take the defaults in brackets. */
+typedef struct {
+    int32_t chunk;       /* first-node rows per work item [1024] */
+    int32_t block;       /* threads per workgroup, a multiple of 64, <= 1024 [256] */
+    int32_t no_graph;    /* nonzero: launch directly instead of replaying a hipGraph [0] */
+    int32_t no_rebuild;  /* nonzero: runs reuse the COLTs as built instead of rebuilding [0] */
+    int32_t reserved[3];
+    const int32_t *query_chunk;  /* optional host array of n per-query chunks (0: use chunk) */
+} fj_batch_options;
+
+/* Prepare n independent queries for counting together.  qs[i], plans[i]
+   and colts[i] (a host array of qs[i]->natoms COLTs) are as for
+   fj_execute and must stay alive for the batch's lifetime.  Every plan must
+   probe only root maps keyed by one or two variables, with each later node
+   iterating the sub-trie a previous node reached (the shape of plans
+   converted from left-deep binary plans, Section 4.1); other plans give
+   FJ_ERR_UNSUPPORTED.  The whole run (optional COLT rebuilds and one
+   persistent kernel draining a static queue of (query, row chunk) work
+   items, largest first) is captured once in a hipGraph.  Each node iterates
+   a fixed cover (its first subatom when that is a pure cover, as in the
+   binary plan it came from) instead of choosing one per binding. */
+fj_status fj_batch_create(fj_ctx *ctx, int32_t n, const fj_query *const *qs, const fj_plan *const *plans,
+                          fj_colt *const *const *colts, const fj_batch_options *opt, fj_batch **out);
+
+/* Run the batch: counts (host, n entries) receive each query's exact result
+   count.  Synchronizes the context's stream. */
+fj_status fj_batch_run(fj_batch *b, uint64_t *counts);
+void fj_batch_free(fj_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

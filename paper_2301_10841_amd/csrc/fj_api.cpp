@@ -1163,3 +1163,246 @@ extern "C" fj_status fj_execute(fj_ctx *c, const fj_query *q, const fj_plan *p, 
     }
     return (x.out && *count > x.cap) ? FJ_TRUNCATED : FJ_OK;
 }
+
+// ------------------------------------------------------------------ batches
+
+struct fj_batch {
+    fj_ctx *c = nullptr;
+    int n = 0;
+    fj_batch_options opt{};
+    std::vector<const fj_query *> qs;
+    std::vector<const fj_plan *> plans;
+    std::vector<std::vector<fj_colt *>> colts;
+    fj::BQuery *q_dev = nullptr;
+    fj::BItem *items_dev = nullptr;
+    uint32_t nitems = 0;
+    u64 *counts_dev = nullptr;
+    u64 *counts_h = nullptr;
+    int grid = 0;
+    hipStream_t stream = nullptr;   // the batch's own stream (the null stream cannot be captured)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+fj_status batch_query(const fj_query *q, const fj_plan *p, fj_colt *const *colts, fj::BQuery &B) {
+    memset(&B, 0, sizeof(B));
+    if (q->nvars > fj::kBMaxVars) return fail(FJ_ERR_UNSUPPORTED, "batched queries have at most 16 variables");
+    const int nexec = p->tail_from;
+    if (nexec < 1 || nexec > fj::kBMaxNodes) return fail(FJ_ERR_UNSUPPORTED, "batched plans run 1..8 probing nodes");
+    B.nexec = nexec;
+    for (int k = 0; k < nexec; k++) {
+        const auto &node = p->nodes[k];
+        const auto &L = p->layout[k];
+        // static cover: the node's first subatom when it is a pure cover (the
+        // relation the binary plan iterates), else the first pure cover
+        if (L.pure.empty()) return fail(FJ_ERR_UNSUPPORTED, "no pure cover");
+        int ci = L.pure[0];
+        for (int pc : L.pure)
+            if (pc == 0) ci = 0;
+        const int ca = node[ci].atom, cl = p->sub_level[k][ci];
+        const fj_colt *ct = colts[ca];
+        fj::BNode &N = B.node[k];
+        N.catom = ca;
+        if (k == 0) {
+            if (p->root_built[ca] || p->nlev[ca] != 1)
+                return fail(FJ_ERR_UNSUPPORTED, "batched plans iterate a base table first");
+            N.offs = ct->sel;
+            B.n0 = ct->nroot;
+        } else {
+            if (cl == 0 || cl != p->nlev[ca] - 1)
+                return fail(FJ_ERR_UNSUPPORTED, "batched plans iterate the last level reached by a probe");
+            N.offs = ct->lev[cl].offs;
+            N.len = ct->lev[cl].len;
+        }
+        N.npos = ct->lev[cl].npos;
+        N.nrows = (uint32_t)ct->nrows;
+        N.nk = node[ci].nv;
+        for (int j = 0; j < N.nk; j++) {
+            N.kslot[j] = node[ci].vars[j];
+            N.kcol[j] = ct->cols[ct->lev[cl].kcol[j]];
+        }
+        for (int i = 0; i < (int)node.size(); i++) {
+            if (i == ci) continue;
+            const int a = node[i].atom;
+            const fj_colt *t = colts[a];
+            const LevelDev &R = t->lev[0];
+            if (p->sub_level[k][i] != 0 || !p->root_built[a] ||
+                !(R.mode == fj::KM_K32 || (R.mode == fj::KM_K64 && R.nk == 2)))
+                return fail(FJ_ERR_UNSUPPORTED, "batched plans probe root maps keyed by one or two variables");
+            if (N.nl >= fj::kBMaxLookups) return fail(FJ_ERR_UNSUPPORTED, "too many lookups in a node");
+            fj::BLookup &BL = N.lk[N.nl++];
+            BL.table = R.table;
+            BL.mask = R.mask;
+            BL.mode = R.mode;
+            BL.kslot[0] = node[i].vars[0];
+            BL.kslot[1] = node[i].nv > 1 ? node[i].vars[1] : node[i].vars[0];
+            BL.atom = a;
+            BL.child_leaf = p->nlev[a] == 1;
+            BL.clen = t->lev[1].len;
+            BL.cnpos = t->lev[1].npos;
+        }
+    }
+    const int nn = (int)p->nodes.size();
+    B.ntail = nn - nexec;
+    for (int k = nexec; k < nn; k++) {
+        const int q2 = k - nexec;
+        const int a = p->nodes[k][0].atom, l = p->sub_level[k][0];
+        B.tail_atom[q2] = a;
+        B.tail_root[q2] = l == 0;
+        B.tail_root_len[q2] = colts[a]->nroot;
+        B.tail_len[q2] = colts[a]->lev[l].len;
+        B.tail_npos[q2] = colts[a]->lev[l].npos;
+    }
+    return FJ_OK;
+}
+
+// The launches of one run (rebuilds, zeroed counts, the persistent kernel).
+fj_status batch_launches(fj_batch *b) {
+    fj_ctx *c = b->c;
+    if (!b->opt.no_rebuild)
+        for (int i = 0; i < b->n; i++)
+            for (fj_colt *t : b->colts[i]) FJ_TRY(colt_reset(c, t));
+    FJ_HIP(fj::launch_zero_u64(b->counts_dev, (uint32_t)b->n, c->stream));
+    FJ_HIP(fj::launch_batch_dfs(b->q_dev, b->items_dev, b->nitems, b->counts_dev, c->status_d, b->opt.block, b->grid,
+                                c->stream));
+    return FJ_OK;
+}
+
+void batch_release(fj_batch *b) {
+    if (!b) return;
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->q_dev) hipFree(b->q_dev);
+    if (b->items_dev) hipFree(b->items_dev);
+    if (b->counts_dev) hipFree(b->counts_dev);
+    if (b->counts_h) hipHostFree(b->counts_h);
+    if (b->stream) hipStreamDestroy(b->stream);
+    delete b;
+}
+
+// Run f with the context's work on the batch stream, ordered after
+// everything already queued on the context's own stream.
+template <typename F> fj_status on_batch_stream(fj_batch *b, F f) {
+    fj_ctx *c = b->c;
+    hipStream_t orig = c->stream;
+    FJ_HIP(hipStreamSynchronize(orig));
+    c->stream = b->stream;
+    fj_status st = f();
+    c->stream = orig;
+    return st;
+}
+
+}  // namespace
+
+extern "C" fj_status fj_batch_create(fj_ctx *c, int32_t n, const fj_query *const *qs, const fj_plan *const *plans,
+                                     fj_colt *const *const *colts, const fj_batch_options *opt, fj_batch **out) {
+    if (!c || n < 1 || !qs || !plans || !colts || !out) return fail(FJ_ERR_ARG, "bad argument");
+    *out = nullptr;
+    FJ_HIP(hipSetDevice(c->device));
+    fj_batch *b = new fj_batch();
+    b->c = c;
+    b->n = n;
+    if (opt) b->opt = *opt;
+    if (b->opt.chunk <= 0) b->opt.chunk = 1024;
+    if (b->opt.block <= 0) b->opt.block = 256;
+    if (b->opt.block % 64 || b->opt.block > 1024) { batch_release(b); return fail(FJ_ERR_ARG, "bad block size"); }
+    std::vector<fj::BQuery> hq(n);
+    std::vector<fj::BItem> items;
+    u64 max_rows = 0;
+    for (int i = 0; i < n; i++) {
+        if (!qs[i] || !plans[i] || !colts[i]) { batch_release(b); return fail(FJ_ERR_ARG, "null query"); }
+        fj_status st = check_exec_args(qs[i], plans[i], colts[i]);
+        if (st == FJ_OK) st = batch_query(qs[i], plans[i], colts[i], hq[i]);
+        if (st != FJ_OK) {
+            std::string m = g_err;
+            batch_release(b);
+            return fail(st, "query " + std::to_string(i) + ": " + m);
+        }
+        b->qs.push_back(qs[i]);
+        b->plans.push_back(plans[i]);
+        b->colts.emplace_back(colts[i], colts[i] + qs[i]->natoms);
+        for (fj_colt *t : b->colts.back()) max_rows = std::max<u64>(max_rows, t->cap_rows);
+        const uint32_t chunk =
+            (uint32_t)((b->opt.query_chunk && b->opt.query_chunk[i] > 0) ? b->opt.query_chunk[i] : b->opt.chunk);
+        for (uint32_t r0 = 0; r0 < hq[i].n0; r0 += chunk)
+            items.push_back({(uint32_t)i, r0, std::min<uint32_t>(hq[i].n0, r0 + chunk)});
+    }
+    // largest items first; workgroups take items round robin
+    std::stable_sort(items.begin(), items.end(),
+                     [](const fj::BItem &x, const fj::BItem &y) { return x.r1 - x.r0 > y.r1 - y.r0; });
+    b->nitems = (uint32_t)items.size();
+    const int per_cu = std::max(1, 2048 / b->opt.block);
+    b->grid = (int)std::max<u64>(1, std::min<u64>(b->nitems, (u64)c->num_cus * per_cu));
+    fj_status st = FJ_OK;
+    if (hipMalloc((void **)&b->q_dev, sizeof(fj::BQuery) * n) != hipSuccess ||
+        hipMalloc((void **)&b->items_dev, sizeof(fj::BItem) * std::max<size_t>(items.size(), 1)) != hipSuccess ||
+        hipMalloc((void **)&b->counts_dev, sizeof(u64) * n) != hipSuccess ||
+        hipHostMalloc((void **)&b->counts_h, sizeof(u64) * n, hipHostMallocDefault) != hipSuccess) {
+        batch_release(b);
+        return fail(FJ_ERR_OOM, "batch buffers");
+    }
+    if (hipMemcpy(b->q_dev, hq.data(), sizeof(fj::BQuery) * n, hipMemcpyHostToDevice) != hipSuccess ||
+        (!items.empty() && hipMemcpy(b->items_dev, items.data(), sizeof(fj::BItem) * items.size(),
+                                     hipMemcpyHostToDevice) != hipSuccess)) {
+        batch_release(b);
+        return fail(FJ_ERR_HIP, "batch upload");
+    }
+    // scratch the rebuilds need, sized before any capture
+    {
+        ForceScratch fs(1, max_rows);
+        st = c->force.ensure(fs.bytes(max_rows), c->stream);
+        if (st == FJ_OK) st = c->scanb.ensure((max_rows / 1024 + 2) * sizeof(u64), c->stream);
+        if (st != FJ_OK) { batch_release(b); return st; }
+    }
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+        batch_release(b);
+        return fail(FJ_ERR_HIP, "stream creation failed");
+    }
+    if (!b->opt.no_graph) {
+        const int timing = c->opt.timing;
+        c->opt.timing = 0;   // no event nodes in the graph
+        st = on_batch_stream(b, [&]() -> fj_status {
+            hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed);
+            if (e != hipSuccess) return fail(FJ_ERR_HIP, std::string("stream capture failed: ") + hipGetErrorString(e));
+            fj_status s1 = batch_launches(b);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+            b->graph = g;
+            if (s1 != FJ_OK) return s1;
+            if (e2 != hipSuccess) return fail(FJ_ERR_HIP, "graph capture failed");
+            if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
+                return fail(FJ_ERR_HIP, "graph instantiation failed");
+            return FJ_OK;
+        });
+        c->opt.timing = timing;
+        if (st != FJ_OK) { batch_release(b); return st; }
+    }
+    *out = b;
+    return FJ_OK;
+}
+
+extern "C" fj_status fj_batch_run(fj_batch *b, uint64_t *counts) {
+    if (!b || !counts) return fail(FJ_ERR_ARG, "null argument");
+    fj_ctx *c = b->c;
+    FJ_HIP(hipSetDevice(c->device));
+    FJ_TRY(on_batch_stream(b, [&]() -> fj_status {
+        {
+            Timer t(c, FJ_T_PROBE);
+            if (b->exec) FJ_HIP(hipGraphLaunch(b->exec, c->stream));
+            else FJ_TRY(batch_launches(b));
+        }
+        FJ_HIP(hipMemcpyAsync(b->counts_h, b->counts_dev, sizeof(u64) * b->n, hipMemcpyDeviceToHost, c->stream));
+        return sync_status(c);
+    }));
+    memcpy(counts, b->counts_h, sizeof(u64) * b->n);
+    return FJ_OK;
+}
+
+extern "C" void fj_batch_free(fj_batch *b) {
+    if (!b) return;
+    hipSetDevice(b->c->device);
+    hipStreamSynchronize(b->c->stream);
+    batch_release(b);
+}

@@ -1,0 +1,177 @@
+// Batched counting for plans that probe only root maps: one persistent
+// kernel drains a static queue of (query, row chunk) work items; each thread
+// runs the join of Section 3.3 (figure "fj-algo") depth first for one row of
+// the first node's cover, iterating later nodes' covers by offset and
+// probing root maps, and adds the multiplicities of its results.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "fj_dev.h"
+#include "fj_launch.h"
+
+namespace fj {
+
+typedef unsigned long long u64;
+
+__device__ __noinline__ void fjb_bad(StatusDev *st, int line) {
+    atomicCAS(&st->err_line, 0u, (uint32_t)line);
+    atomicAdd(&st->err_count, 1u);
+}
+#define BCK(cond) ((cond) ? true : (fjb_bad(status, __LINE__), false))
+
+__device__ __forceinline__ uint32_t bmix32(uint32_t h) {
+    h ^= h >> 16; h *= 0x85ebca6bu; h ^= h >> 13; h *= 0xc2b2ae35u; h ^= h >> 16;
+    return h;
+}
+__device__ __forceinline__ u64 bmix64(u64 k) {
+    k ^= k >> 33; k *= 0xff51afd7ed558ccdull; k ^= k >> 33; k *= 0xc4ceb9fe1a85ec53ull; k ^= k >> 33;
+    return k;
+}
+
+// get() on a root map: the child start, or ~0u.  Same probe sequence as the
+// maps' builder: 32-byte buckets walked forward; the empty-marker key lives
+// in the reserved slot after the last bucket.
+__device__ __forceinline__ uint32_t root_get(const BLookup &L, const int32_t *v) {
+    if (L.mode == KM_K32) {
+        const Slot32 *T = (const Slot32 *)L.table;
+        const uint32_t key = (uint32_t)v[L.kslot[0]];
+        if (key == kEmpty32) return T[L.mask + 1].key ? T[L.mask + 1].val : ~0u;
+        u64 i = (bmix32(key) & L.mask) & ~3ull;
+        for (u64 n = 0; n <= L.mask; n++) {
+            const Slot32 sl = T[i];
+            if (sl.key == key) return sl.val;
+            if (sl.key == kEmpty32) return ~0u;
+            i = (i + 1) & L.mask;
+        }
+    } else {
+        const Slot64 *T = (const Slot64 *)L.table;
+        const u64 key = ((u64)(uint32_t)v[L.kslot[0]] << 32) | (uint32_t)v[L.kslot[1]];
+        if (key == kEmpty64) return T[L.mask + 1].key ? T[L.mask + 1].val : ~0u;
+        u64 i = (bmix64(key) & L.mask) & ~1ull;
+        for (u64 n = 0; n <= L.mask; n++) {
+            const Slot64 sl = T[i];
+            if (sl.key == key) return sl.val;
+            if (sl.key == kEmpty64) return ~0u;
+            i = (i + 1) & L.mask;
+        }
+    }
+    return ~0u;
+}
+
+// Probe node k's lookups for the current binding; false on the first miss.
+__device__ __forceinline__ bool probe_node(const BNode &N, const int32_t *v, uint32_t *h, u64 &mult,
+                                           StatusDev *status) {
+    for (int j = 0; j < N.nl; j++) {
+        const BLookup &L = N.lk[j];
+        const uint32_t s = root_get(L, v);
+        if (s == ~0u) return false;
+        if (!BCK(s < L.cnpos)) return false;
+        if (L.child_leaf) mult *= L.clen[s];
+        else h[L.atom] = s;
+    }
+    return true;
+}
+
+__global__ void __launch_bounds__(1024) k_batch_dfs(const BQuery *__restrict__ qs, const BItem *__restrict__ items,
+                                                    uint32_t nitems, u64 *counts, StatusDev *status) {
+    __shared__ u64 red[16];
+    for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const BItem item = items[it];
+        const BQuery &Q = qs[item.q];
+        u64 total = 0;
+        for (uint32_t r = item.r0 + threadIdx.x; r < item.r1; r += blockDim.x) {
+            int32_t v[kBMaxVars];
+            uint32_t h[FJ_MAX_ATOMS];
+            uint32_t pos[kBMaxNodes], lim[kBMaxNodes], base[kBMaxNodes];
+            u64 mult[kBMaxNodes + 1];
+            // node 0: the cover is a base table (or its selection)
+            const BNode &N0 = Q.node[0];
+            const uint32_t row = N0.offs ? N0.offs[r] : r;
+            if (!BCK(row < N0.nrows)) continue;
+            for (int c = 0; c < N0.nk; c++) v[N0.kslot[c]] = N0.kcol[c][row];
+            u64 m = 1;
+            if (!probe_node(N0, v, h, m, status)) continue;
+            // later nodes, depth first
+            int k = 1;
+            mult[1] = m;
+            if (Q.nexec > 1) {
+                const BNode &N = Q.node[1];
+                base[1] = h[N.catom];
+                if (!BCK(base[1] < N.npos)) continue;
+                lim[1] = N.len[base[1]];
+                pos[1] = 0;
+            }
+            while (true) {
+                if (k >= Q.nexec) {
+                    // the remaining nodes are single-cover products
+                    u64 e = mult[k];
+                    for (int q = 0; q < Q.ntail; q++) {
+                        if (Q.tail_root[q]) { e *= Q.tail_root_len[q]; continue; }
+                        const uint32_t th = h[Q.tail_atom[q]];
+                        if (!BCK(th < Q.tail_npos[q])) { e = 0; break; }
+                        e *= Q.tail_len[q][th];
+                    }
+                    total += e;
+                    if (k == 1) break;      // a single probed node
+                    k--;
+                    pos[k]++;
+                    continue;
+                }
+                if (pos[k] >= lim[k]) {
+                    if (k == 1) break;
+                    k--;
+                    pos[k]++;
+                    continue;
+                }
+                const BNode &N = Q.node[k];
+                const uint32_t p = base[k] + pos[k];
+                if (!BCK(p < N.npos)) break;
+                const uint32_t rw = N.offs[p];
+                if (!BCK(rw < N.nrows)) break;
+                for (int c = 0; c < N.nk; c++) v[N.kslot[c]] = N.kcol[c][rw];
+                u64 mm = mult[k];
+                if (!probe_node(N, v, h, mm, status)) { pos[k]++; continue; }
+                mult[k + 1] = mm;
+                k++;
+                if (k < Q.nexec) {
+                    const BNode &M = Q.node[k];
+                    base[k] = h[M.catom];
+                    if (!BCK(base[k] < M.npos)) break;
+                    lim[k] = M.len[base[k]];
+                    pos[k] = 0;
+                }
+            }
+        }
+        // one atomic per work item
+        for (int o = 32; o > 0; o >>= 1) total += __shfl_xor(total, o, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = total;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            u64 t = 0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); w++) t += red[w];
+            if (t) atomicAdd(&counts[item.q], t);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_zero_u64(u64 *p, uint32_t n) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+hipError_t launch_batch_dfs(const BQuery *qs, const BItem *items, uint32_t nitems, u64 *counts, StatusDev *status,
+                            int block, int grid, hipStream_t s) {
+    if (nitems == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_dfs, dim3(grid), dim3(block), 0, s, qs, items, nitems, counts, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(u64 *p, uint32_t n, hipStream_t s) {
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u64, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+}  // namespace fj

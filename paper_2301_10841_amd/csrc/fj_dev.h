@@ -124,6 +124,52 @@ struct ScanLookup {
     int hcol;              // output handle column of this atom, or -1
 };
 
+// Batched counting of plans that probe only root maps (see fj_batch_create).
+constexpr int kBMaxNodes = 8;
+constexpr int kBMaxLookups = 8;
+constexpr int kBMaxVars = 16;
+
+struct BLookup {
+    const void *table;
+    unsigned long long mask;
+    int mode;                 // KM_K32 or KM_K64
+    int kslot[2];             // variables of the key
+    int atom;
+    int child_leaf;           // the child is an offset vector (a multiplicity)
+    const uint32_t *clen;     // child level lengths
+    uint32_t cnpos;
+};
+
+struct BNode {
+    int catom;                // atom whose trie the node iterates (by offset)
+    int nk;
+    int kslot[FJ_MAX_COLS];   // variables the cover binds
+    const int32_t *kcol[FJ_MAX_COLS];  // their columns
+    const uint32_t *offs;     // offsets of the cover's level (node 0: selection or null)
+    const uint32_t *len;      // lengths of the cover's level (unused at node 0)
+    uint32_t npos;
+    uint32_t nrows;
+    int nl;
+    BLookup lk[kBMaxLookups];
+};
+
+struct BQuery {
+    int nexec;                // nodes run tuple by tuple; the rest are products
+    int ntail;
+    uint32_t n0;              // rows of the first node's cover
+    BNode node[kBMaxNodes];
+    int tail_atom[kBMaxNodes];
+    int tail_root[kBMaxNodes];         // the tail iterates a root (its length is root_len)
+    const uint32_t *tail_len[kBMaxNodes];
+    uint32_t tail_npos[kBMaxNodes];
+    uint32_t tail_root_len[kBMaxNodes];
+};
+
+struct BItem {
+    uint32_t q;               // query
+    uint32_t r0, r1;          // first-node rows [r0, r1)
+};
+
 // Regions a COLT (re)build initialises in one launch.
 struct FillRegion {
     uint32_t *p;

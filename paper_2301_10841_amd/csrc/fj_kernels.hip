@@ -988,7 +988,7 @@ __global__ void __launch_bounds__(256) k_scan_probe(ScanArgs a) {
     if (!a.emit || a.materialize) {
 #pragma unroll
         for (int r = 0; r < kScanRows; r++) {
-            const u64 pos = wave_reserve(alive[r], &a.status->survivors);
+            const u64 pos = wave_reserve(alive[r], &a.status->survivors) - a.surv_base;
             if (!alive[r] || !CK(pos < a.out.cap)) continue;
             const FrontierDev &O = a.out;
             for (int j = 0; j < a.nout; j++) O.vals[(u64)j * O.cap + pos] = a.cols[a.out_col[j]][row[r]];

@@ -94,9 +94,13 @@ def lib():
         L.fj_colt_free.restype = None
         L.fj_execute.argtypes = [vp, P(QueryS), vp, vp, P(C.c_uint64), vp, C.c_uint64,
                                  P(C.c_uint64), P(Stats)]
+        L.fj_batch_create.argtypes = [vp, C.c_int32, vp, vp, vp, vp, P(vp)]
+        L.fj_batch_run.argtypes = [vp, vp]
+        L.fj_batch_free.argtypes = [vp]
+        L.fj_batch_free.restype = None
         for name in ("fj_ctx_create", "fj_timings", "fj_timings_reset", "fj_plan_from_binary",
                      "fj_plan_from_nodes", "fj_plan_get", "fj_filter_lt", "fj_filter_lt_batch", "fj_build_colt",
-                     "fj_colt_rebuild", "fj_execute"):
+                     "fj_colt_rebuild", "fj_execute", "fj_batch_create", "fj_batch_run"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -267,6 +271,51 @@ class Context:
                               C.byref(wr), C.byref(st) if st is not None else None)
         _check(rc, ok=(0, 1))
         return int(cnt.value), int(wr.value), st
+
+
+class BatchOptions(C.Structure):
+    _fields_ = [("chunk", C.c_int32), ("block", C.c_int32), ("no_graph", C.c_int32),
+                ("no_rebuild", C.c_int32), ("reserved", C.c_int32 * 3), ("query_chunk", C.c_void_p)]
+
+
+class Batch:
+    """Many queries counted by one persistent launch (captured in a hipGraph)."""
+
+    def __init__(self, ctx: "Context", items, chunk: int = 0, block: int = 0, graph: bool = True,
+                 rebuild: bool = True, query_chunk=None):
+        """items: list of (QueryS, Plan, [Colt per atom])."""
+        n = len(items)
+        self.ctx = ctx
+        self.keep = items
+        qs = (C.c_void_p * n)(*[C.addressof(q) for q, _, _ in items])
+        ps = (C.c_void_p * n)(*[p.h for _, p, _ in items])
+        self._colt_arrays = [(C.c_void_p * len(cs))(*[c.h for c in cs]) for _, _, cs in items]
+        cs = (C.c_void_p * n)(*[C.addressof(a) for a in self._colt_arrays])
+        opt = BatchOptions()
+        opt.chunk = chunk
+        opt.block = block
+        opt.no_graph = 0 if graph else 1
+        opt.no_rebuild = 0 if rebuild else 1
+        if query_chunk is not None:
+            self._qc = (C.c_int32 * n)(*[int(x) for x in query_chunk])
+            opt.query_chunk = C.addressof(self._qc)
+        h = C.c_void_p()
+        _check(lib().fj_batch_create(ctx.h, n, qs, ps, cs, C.byref(opt), C.byref(h)))
+        self.h = h.value
+        self.n = n
+
+    def run(self):
+        counts = (C.c_uint64 * self.n)()
+        _check(lib().fj_batch_run(self.h, counts))
+        return [int(x) for x in counts]
+
+    def free(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.fj_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.free()
 
 
 class Colt:
