@@ -8,9 +8,9 @@ pushed-down selections of the form ``column < constant`` (Section 2.1: the
 atom may be a selection over a base table).
 
 Nothing here evaluates a join.  The one exception to "no arithmetic over two
-relations" is ``_two_path_bound``, a degree product used only to reject
-oversized random triangle instances in ``batch_mix``; it is a workload filter
-and never an expected value.
+relations" is the size bound of ``batch_mix`` (``_two_path_bound`` times
+``_max_dup``), a degree product used only to reject oversized random triangle
+instances; it is a workload filter and never an expected value.
 """
 
 from __future__ import annotations
@@ -305,11 +305,19 @@ def random_tiny_query(seed: int, shape: str, max_rows: int = 10, domain: int = 4
 
 
 def _two_path_bound(a_dst: np.ndarray, b_src: np.ndarray, domain: int) -> int:
-    """sum_v deg_a(v) * deg_b(v): the size of the 2-path relation, an upper
-    bound on any triangle count that extends it (workload filter only)."""
+    """sum_v deg_a(v) * deg_b(v): the number of joined row pairs (the 2-path
+    relation of two bag relations)."""
     da = np.bincount(a_dst, minlength=domain).astype(np.int64)
     db = np.bincount(b_src, minlength=domain).astype(np.int64)
     return int(np.dot(da, db))
+
+
+def _max_dup(c0: np.ndarray, c1: np.ndarray, domain: int) -> int:
+    """Largest number of identical rows (c0, c1) of a bag relation."""
+    if c0.size == 0:
+        return 0
+    _, counts = np.unique(c0.astype(np.int64) * domain + c1.astype(np.int64), return_counts=True)
+    return int(counts.max())
 
 
 def _pk_sample(rng, n: int, domain: int) -> np.ndarray:
@@ -329,7 +337,9 @@ def batch_mix(seed: int, n_queries: int = 256, min_rows: int = 1_000,
     the referencing column is Zipf(s) over the same domain through the rank
     permutation shared with the referenced side.  Triangles use three
     distinct bag relations with Zipf(s) endpoints over D = ceil(rows^(2/3));
-    a triangle whose 2-path bound exceeds ``max_bound`` is redrawn.
+    a triangle whose result-size upper bound (joined pairs of two relations
+    times the largest row multiplicity of the third) exceeds ``max_bound`` is
+    redrawn.
 
     Returns (queries, redraws)."""
     out = []
@@ -389,8 +399,11 @@ def batch_mix(seed: int, n_queries: int = 256, min_rows: int = 1_000,
                 for n in rows:
                     cols.append((zipf_keys(rng, n, dom, s, perm), zipf_keys(rng, n, dom, s, perm)))
                 (rx, ry), (sy, sz), (tz, tx) = cols
-                b = min(_two_path_bound(ry, sy, dom), _two_path_bound(sz, tz, dom),
-                        _two_path_bound(tx, rx, dom))
+                # every joined pair of two relations extends through at most
+                # the largest multiplicity of a row of the third
+                b = min(_two_path_bound(ry, sy, dom) * _max_dup(tz, tx, dom),
+                        _two_path_bound(sz, tz, dom) * _max_dup(rx, ry, dom),
+                        _two_path_bound(tx, rx, dom) * _max_dup(sy, sz, dom))
                 if b <= max_bound:
                     break
                 redraws += 1

@@ -213,7 +213,7 @@ typedef struct fj_batch fj_batch;
 /* Batch options; zero fields take the defaults in brackets. */
 typedef struct {
     int32_t chunk;       /* first-node rows per work item [1024] */
-    int32_t block;       /* threads per workgroup, a multiple of 64, <= 1024 [256] */
+    int32_t block;       /* threads per workgroup, a multiple of 64, <= 512 [256] */
     int32_t no_graph;    /* nonzero: launch directly instead of replaying a hipGraph [0] */
     int32_t no_rebuild;  /* nonzero: runs reuse the COLTs as built instead of rebuilding [0] */
     int32_t reserved[3];

@@ -1307,7 +1307,7 @@ extern "C" fj_status fj_batch_create(fj_ctx *c, int32_t n, const fj_query *const
     if (opt) b->opt = *opt;
     if (b->opt.chunk <= 0) b->opt.chunk = 1024;
     if (b->opt.block <= 0) b->opt.block = 256;
-    if (b->opt.block % 64 || b->opt.block > 1024) { batch_release(b); return fail(FJ_ERR_ARG, "bad block size"); }
+    if (b->opt.block % 64 || b->opt.block > 512) { batch_release(b); return fail(FJ_ERR_ARG, "bad block size"); }
     std::vector<fj::BQuery> hq(n);
     std::vector<fj::BItem> items;
     u64 max_rows = 0;

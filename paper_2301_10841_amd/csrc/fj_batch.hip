@@ -32,12 +32,21 @@ __device__ __forceinline__ u64 bmix64(u64 k) {
 // get() on a root map: the child start, or ~0u.  Same probe sequence as the
 // maps' builder: 32-byte buckets walked forward; the empty-marker key lives
 // in the reserved slot after the last bucket.
-__device__ __forceinline__ uint32_t root_get(const BLookup &L, const int32_t *v) {
+// Per-thread variables and handles live in LDS: entry i of a thread is at
+// [i * blockDim.x + threadIdx.x], so a wave touches consecutive banks.
+struct Lane {
+    int32_t *v;     // variable values
+    uint32_t *h;    // handles per atom
+    __device__ __forceinline__ int32_t &var(int i) const { return v[i * blockDim.x + threadIdx.x]; }
+    __device__ __forceinline__ uint32_t &hdl(int a) const { return h[a * blockDim.x + threadIdx.x]; }
+};
+
+__device__ __forceinline__ uint32_t root_get(const BLookup &L, const Lane &ln) {
     if (L.mode == KM_K32) {
         const Slot32 *T = (const Slot32 *)L.table;
-        const uint32_t key = (uint32_t)v[L.kslot[0]];
+        const uint32_t key = (uint32_t)ln.var(L.kslot[0]);
         if (key == kEmpty32) return T[L.mask + 1].key ? T[L.mask + 1].val : ~0u;
-        u64 i = (bmix32(key) & L.mask) & ~3ull;
+        u64 i = (bmix32(key) & L.mask) & ~3ull;   // 4 slots of 8 bytes
         for (u64 n = 0; n <= L.mask; n++) {
             const Slot32 sl = T[i];
             if (sl.key == key) return sl.val;
@@ -46,9 +55,9 @@ __device__ __forceinline__ uint32_t root_get(const BLookup &L, const int32_t *v)
         }
     } else {
         const Slot64 *T = (const Slot64 *)L.table;
-        const u64 key = ((u64)(uint32_t)v[L.kslot[0]] << 32) | (uint32_t)v[L.kslot[1]];
+        const u64 key = ((u64)(uint32_t)ln.var(L.kslot[0]) << 32) | (uint32_t)ln.var(L.kslot[1]);
         if (key == kEmpty64) return T[L.mask + 1].key ? T[L.mask + 1].val : ~0u;
-        u64 i = (bmix64(key) & L.mask) & ~1ull;
+        u64 i = (bmix64(key) & L.mask) & ~1ull;   // 2 slots of 16 bytes
         for (u64 n = 0; n <= L.mask; n++) {
             const Slot64 sl = T[i];
             if (sl.key == key) return sl.val;
@@ -60,88 +69,73 @@ __device__ __forceinline__ uint32_t root_get(const BLookup &L, const int32_t *v)
 }
 
 // Probe node k's lookups for the current binding; false on the first miss.
-__device__ __forceinline__ bool probe_node(const BNode &N, const int32_t *v, uint32_t *h, u64 &mult,
-                                           StatusDev *status) {
+__device__ __forceinline__ bool probe_node(const BNode &N, const Lane &ln, u64 &mult, StatusDev *status) {
     for (int j = 0; j < N.nl; j++) {
         const BLookup &L = N.lk[j];
-        const uint32_t s = root_get(L, v);
+        const uint32_t s = root_get(L, ln);
         if (s == ~0u) return false;
         if (!BCK(s < L.cnpos)) return false;
         if (L.child_leaf) mult *= L.clen[s];
-        else h[L.atom] = s;
+        else ln.hdl(L.atom) = s;
     }
     return true;
 }
 
+// The join below node K for one binding, depth first.  The recursion is
+// unrolled at compile time (K is a template argument), so every depth keeps
+// its iterator in registers; the variable and handle arrays are indexed only
+// by values of the query's descriptor, which are the same for the whole
+// workgroup.
+template <int K>
+__device__ __forceinline__ void dfs(const BQuery &Q, const Lane &ln, u64 mult, u64 &total, StatusDev *status) {
+    if (K >= Q.nexec) {
+        // the remaining nodes are single-cover products
+        u64 e = mult;
+        for (int q = 0; q < Q.ntail; q++) {
+            if (Q.tail_root[q]) { e *= Q.tail_root_len[q]; continue; }
+            const uint32_t th = ln.hdl(Q.tail_atom[q]);
+            if (!BCK(th < Q.tail_npos[q])) return;
+            e *= Q.tail_len[q][th];
+        }
+        total += e;
+        return;
+    }
+    if constexpr (K < kBMaxNodes) {
+        const BNode &N = Q.node[K];
+        const uint32_t base = ln.hdl(N.catom);
+        if (!BCK(base < N.npos)) return;
+        const uint32_t lim = N.len[base];
+        for (uint32_t pos = 0; pos < lim; pos++) {
+            const uint32_t p = base + pos;
+            if (!BCK(p < N.npos)) return;
+            const uint32_t rw = N.offs[p];
+            if (!BCK(rw < N.nrows)) return;
+            for (int c = 0; c < N.nk; c++) ln.var(N.kslot[c]) = N.kcol[c][rw];
+            u64 mm = mult;
+            if (!probe_node(N, ln, mm, status)) continue;
+            dfs<K + 1>(Q, ln, mm, total, status);
+        }
+    }
+}
+
 __global__ void __launch_bounds__(1024) k_batch_dfs(const BQuery *__restrict__ qs, const BItem *__restrict__ items,
                                                     uint32_t nitems, u64 *counts, StatusDev *status) {
+    extern __shared__ uint32_t lds[];
     __shared__ u64 red[16];
+    const Lane ln{(int32_t *)lds, lds + kBMaxVars * blockDim.x};
     for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const BItem item = items[it];
         const BQuery &Q = qs[item.q];
         u64 total = 0;
         for (uint32_t r = item.r0 + threadIdx.x; r < item.r1; r += blockDim.x) {
-            int32_t v[kBMaxVars];
-            uint32_t h[FJ_MAX_ATOMS];
-            uint32_t pos[kBMaxNodes], lim[kBMaxNodes], base[kBMaxNodes];
-            u64 mult[kBMaxNodes + 1];
             // node 0: the cover is a base table (or its selection)
             const BNode &N0 = Q.node[0];
             const uint32_t row = N0.offs ? N0.offs[r] : r;
             if (!BCK(row < N0.nrows)) continue;
-            for (int c = 0; c < N0.nk; c++) v[N0.kslot[c]] = N0.kcol[c][row];
+            for (int c = 0; c < N0.nk; c++) ln.var(N0.kslot[c]) = N0.kcol[c][row];
             u64 m = 1;
-            if (!probe_node(N0, v, h, m, status)) continue;
-            // later nodes, depth first
-            int k = 1;
-            mult[1] = m;
-            if (Q.nexec > 1) {
-                const BNode &N = Q.node[1];
-                base[1] = h[N.catom];
-                if (!BCK(base[1] < N.npos)) continue;
-                lim[1] = N.len[base[1]];
-                pos[1] = 0;
-            }
-            while (true) {
-                if (k >= Q.nexec) {
-                    // the remaining nodes are single-cover products
-                    u64 e = mult[k];
-                    for (int q = 0; q < Q.ntail; q++) {
-                        if (Q.tail_root[q]) { e *= Q.tail_root_len[q]; continue; }
-                        const uint32_t th = h[Q.tail_atom[q]];
-                        if (!BCK(th < Q.tail_npos[q])) { e = 0; break; }
-                        e *= Q.tail_len[q][th];
-                    }
-                    total += e;
-                    if (k == 1) break;      // a single probed node
-                    k--;
-                    pos[k]++;
-                    continue;
-                }
-                if (pos[k] >= lim[k]) {
-                    if (k == 1) break;
-                    k--;
-                    pos[k]++;
-                    continue;
-                }
-                const BNode &N = Q.node[k];
-                const uint32_t p = base[k] + pos[k];
-                if (!BCK(p < N.npos)) break;
-                const uint32_t rw = N.offs[p];
-                if (!BCK(rw < N.nrows)) break;
-                for (int c = 0; c < N.nk; c++) v[N.kslot[c]] = N.kcol[c][rw];
-                u64 mm = mult[k];
-                if (!probe_node(N, v, h, mm, status)) { pos[k]++; continue; }
-                mult[k + 1] = mm;
-                k++;
-                if (k < Q.nexec) {
-                    const BNode &M = Q.node[k];
-                    base[k] = h[M.catom];
-                    if (!BCK(base[k] < M.npos)) break;
-                    lim[k] = M.len[base[k]];
-                    pos[k] = 0;
-                }
-            }
+            if (!probe_node(N0, ln, m, status)) continue;
+            dfs<1>(Q, ln, m, total, status);
         }
         // one atomic per work item
         for (int o = 32; o > 0; o >>= 1) total += __shfl_xor(total, o, 64);
@@ -164,7 +158,9 @@ __global__ void k_zero_u64(u64 *p, uint32_t n) {
 hipError_t launch_batch_dfs(const BQuery *qs, const BItem *items, uint32_t nitems, u64 *counts, StatusDev *status,
                             int block, int grid, hipStream_t s) {
     if (nitems == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_dfs, dim3(grid), dim3(block), 0, s, qs, items, nitems, counts, status);
+    if (block > 512) return hipErrorInvalidValue;   // LDS: 128 bytes per thread
+    const size_t lds = sizeof(uint32_t) * (size_t)(kBMaxVars + FJ_MAX_ATOMS) * block;
+    hipLaunchKernelGGL(k_batch_dfs, dim3(grid), dim3(block), lds, s, qs, items, nitems, counts, status);
     return hipGetLastError();
 }
 
