@@ -239,6 +239,113 @@ fj_status fj_batch_create(fj_ctx *ctx, int32_t n, const fj_query *const *qs, con
 fj_status fj_batch_run(fj_batch *b, uint64_t *counts);
 void fj_batch_free(fj_batch *b);
 
+/* ------------------------------------------------------- column statistics */
+
+#define FJ_SKETCH_TOPK 8
+
+/* Exact statistics of the rows an atom ranges over: the learned plan
+   chooser's inputs and the cardinality estimates of the greedy left-deep
+   optimizer below.  top[j] holds the FJ_SKETCH_TOPK largest frequencies of
+   the values of column j in descending order (zero-padded when the column
+   has fewer distinct values). */
+typedef struct {
+    int64_t rows;                                /* rel->nsel when sel is set, else nrows */
+    int32_t ncols;
+    int64_t distinct[FJ_MAX_COLS];
+    int64_t top[FJ_MAX_COLS][FJ_SKETCH_TOPK];
+} fj_sketch;
+
+/* Count, on the GPU, the distinct values of every column of rel (over
+   rel->sel when set) and their largest frequencies into *out (host).  Uses
+   a hash table of at least 2 x rows slots of 8 bytes in device scratch owned
+   by the context.  Synchronizes the stream. */
+fj_status fj_sketch_relation(fj_ctx *ctx, const fj_relation *rel, fj_sketch *out);
+
+/* ----------------------------------------------------------- plan choosing */
+
+/* Greedy left-deep join order from textbook estimates, the stand-in for the
+   cost-based optimizer that produces the binary plans Section 4.1 converts.
+   The order starts at atom `first`, or at the atom with the most rows when
+   first < 0 (a traditional binary plan iterates its largest relation,
+   Section 4.4); then it repeatedly appends the remaining atom sharing a
+   variable with those already placed that minimizes the estimate
+   |J| |R| / prod over shared v of max(V(J,v), V(R,v)), where V is a
+   distinct count and V(J,v) is the smallest V over placed atoms holding v;
+   an atom sharing nothing is taken only when nothing connected is left, the
+   smallest first.  Ties go to the lower atom index.  sk: host array of
+   q->natoms sketches; order: host array receiving q->natoms atom indices. */
+fj_status fj_greedy_order(const fj_query *q, const fj_sketch *sk, int32_t first, int32_t *order);
+
+#define FJ_CAND_MAX 32
+#define FJ_FEATURES 128
+#define FJ_CAND_BINARY 0   /* left-deep order, converted and factored (Section 4.1) */
+#define FJ_CAND_GJ 1       /* Generic Join plan: one variable per node (Section 3.2, eq. "gj") */
+
+typedef struct {
+    int32_t kind;                /* FJ_CAND_BINARY or FJ_CAND_GJ */
+    int32_t n;                   /* entries of order */
+    int32_t order[FJ_MAX_VARS];  /* atom order (binary) or variable order (GJ) */
+} fj_candidate;
+
+/* Enumerate candidate Free Join plans for q and describe each by a row of
+   FJ_FEATURES floats.  Candidate 0 is always the plain plan: the greedy
+   order from the largest atom, converted and factored.  Then, for every
+   start atom, the greedy order from it (converted and factored), and the
+   Generic Join plan over the variable order that order induces (variables
+   by first appearance); duplicates are dropped and at most cap (<=
+   FJ_CAND_MAX) are kept.  The features hold the plan's shape, per-atom
+   statistics in plan order (rows, distinct counts, top frequencies, whether
+   the root map is built, trie depth) and per-node textbook estimates of
+   frontier and cover sizes.  All arrays are host memory; features has room
+   for cap x FJ_FEATURES floats. */
+fj_status fj_plan_candidates(const fj_query *q, const fj_sketch *sk, int32_t cap, fj_candidate *out, int32_t *n,
+                             float *features);
+
+/* The plan of a candidate (as fj_plan_from_binary / fj_plan_from_nodes). */
+fj_status fj_candidate_plan(const fj_query *q, const fj_candidate *c, fj_plan **out);
+
+/* ------------------------------------------------------------ perceptron */
+
+typedef struct fj_mlp fj_mlp;
+
+/* A three-layer FP32 perceptron y = W3 relu(W2 relu(W1 x + b1) + b2) + b3
+   (in_dim -> hidden -> hidden -> 1) trained on the GPU by the library's own
+   kernels, here to predict the run time of a candidate plan from its
+   features.  Parameters are one host-visible vector in the order W1 (in_dim
+   x hidden, row-major), b1, W2 (hidden x hidden), b2, W3 (hidden), b3;
+   they start at zero.  in_dim and hidden are 1..1024.  Device buffers grow
+   with the largest batch seen. */
+fj_status fj_mlp_create(fj_ctx *ctx, int32_t in_dim, int32_t hidden, fj_mlp **out);
+int64_t fj_mlp_param_count(const fj_mlp *m);
+/* Copy n = fj_mlp_param_count(m) host floats in / out.  Setting parameters
+   also clears the optimizer state. */
+fj_status fj_mlp_set_params(fj_mlp *m, const float *params, int64_t n);
+fj_status fj_mlp_get_params(fj_mlp *m, float *params, int64_t n);
+/* y[i] = f(x[i]) for batch rows: x is device batch x in_dim row-major, y is
+   device batch floats.  Stream-ordered, no synchronization. */
+fj_status fj_mlp_forward(fj_mlp *m, const float *x, int32_t batch, float *y);
+/* Gradient of the mean squared error (1/batch) sum_i (f(x[i]) - t[i])^2
+   with respect to every parameter, in parameter order, into grad (host,
+   param_count floats), and the loss into *loss (host).  x and t are device.
+   Synchronizes the stream. */
+fj_status fj_mlp_gradient(fj_mlp *m, const float *x, const float *t, int32_t batch, float *grad, float *loss);
+/* One Adam step (beta1 0.9, beta2 0.999, epsilon 1e-8, bias-corrected)
+   with learning rate lr on that loss.  *loss (host, nullable) receives the
+   loss before the step, which synchronizes the stream; without it the call
+   only enqueues work. */
+fj_status fj_mlp_train_step(fj_mlp *m, const float *x, const float *t, int32_t batch, float lr, float *loss);
+void fj_mlp_free(fj_mlp *m);
+
+/* Learned choice: enumerate the candidates of q (fj_plan_candidates),
+   score them with m on the GPU and return in *out the plan with the lowest
+   predicted time, unless it beats the plain plan (candidate 0) by less than
+   `margin` in the model's output units, or q has more atoms than the
+   features describe (6), or m is NULL: then the plain converted plan is
+   returned.  *chosen (host, nullable) receives the candidate index, scores
+   (host, nullable, FJ_CAND_MAX floats) the predictions.  Synchronizes. */
+fj_status fj_choose_plan(fj_ctx *ctx, fj_mlp *m, const fj_query *q, const fj_sketch *sk, float margin,
+                         fj_plan **out, int32_t *chosen, float *scores);
+
 #ifdef __cplusplus
 }
 #endif

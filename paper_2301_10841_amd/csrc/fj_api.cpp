@@ -12,6 +12,7 @@
 
 #include "fj.h"
 #include "fj_dev.h"
+#include "fj_host.h"
 #include "fj_launch.h"
 #include "fj_plan.h"
 
@@ -104,6 +105,8 @@ struct fj_ctx {
     DevBuf scanb;                   // block sums for scans
     DevBuf desc;                    // node + emit descriptors
     DevBuf emitbuf;                 // emit counts and starts
+    DevBuf sketch;                  // column sketch table and results
+    unsigned long long *sketch_h = nullptr;  // pinned sketch results
     void *desc_h = nullptr;         // pinned staging for descriptors
     size_t desc_h_bytes = 0;
     // timing
@@ -413,6 +416,12 @@ static fj_status check_relation(const fj_relation *r, int arity) {
     return FJ_OK;
 }
 
+namespace fj {
+hipStream_t ctx_stream(const fj_ctx *c) { return c->stream; }
+int ctx_device(const fj_ctx *c) { return c->device; }
+fj_status set_error(fj_status st, const std::string &msg) { return fail(st, msg); }
+}  // namespace fj
+
 extern "C" {
 
 const char *fj_last_error(void) { return g_err.c_str(); }
@@ -460,6 +469,8 @@ void fj_ctx_destroy(fj_ctx *c) {
     c->scanb.release();
     c->desc.release();
     c->emitbuf.release();
+    c->sketch.release();
+    if (c->sketch_h) hipHostFree(c->sketch_h);
     if (c->desc_h) hipHostFree(c->desc_h);
     for (auto &p : c->pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
     for (auto e : c->pool) hipEventDestroy(e);
@@ -603,6 +614,55 @@ fj_status fj_filter_lt_batch(fj_ctx *c, int32_t n, const int32_t *const *cols, c
 }
 
 // ------------------------------------------------------------------- COLTs
+
+fj_status fj_sketch_relation(fj_ctx *c, const fj_relation *rel, fj_sketch *out) {
+    if (!c || !rel || !out) return fail(FJ_ERR_ARG, "null argument");
+    if (rel->ncols < 1 || rel->ncols > FJ_MAX_COLS) return fail(FJ_ERR_ARG, "relation arity out of range");
+    if (rel->nrows < 0 || rel->nrows >= (int64_t(1) << 31)) return fail(FJ_ERR_ARG, "nrows out of range");
+    const bool use_sel = rel->sel != nullptr;
+    const int64_t n = use_sel ? rel->nsel : rel->nrows;
+    if (n < 0 || n > rel->nrows) return fail(FJ_ERR_ARG, "nsel out of range");
+    for (int j = 0; j < rel->ncols; j++)
+        if (n && !rel->cols[j]) return fail(FJ_ERR_ARG, "null column");
+    FJ_HIP(hipSetDevice(c->device));
+    memset(out, 0, sizeof(*out));
+    out->rows = n;
+    out->ncols = rel->ncols;
+    // table of at least twice the rows, so linear probing always ends
+    uint64_t cap = 256;
+    while (cap < 2 * (uint64_t)n) cap <<= 1;
+    const uint32_t max_blocks = 2048;
+    const size_t o_cnt = align256(cap * 4), o_part = o_cnt + align256(cap * 4),
+                 o_res = o_part + align256(size_t(max_blocks) * fj::kSketchTop * 4),
+                 total = o_res + align256(fj::kSketchRes * 8);
+    FJ_TRY(c->sketch.ensure(total, c->stream));
+    if (!c->sketch_h) {
+        hipError_t e = hipHostMalloc((void **)&c->sketch_h, fj::kSketchRes * 8 * FJ_MAX_COLS, hipHostMallocDefault);
+        if (e != hipSuccess) { c->sketch_h = nullptr; return fail(FJ_ERR_OOM, "pinned sketch results"); }
+    }
+    for (int j = 0; j < rel->ncols; j++) {
+        fj::SketchLaunch a{};
+        a.col = rel->cols[j];
+        a.sel = use_sel ? rel->sel : nullptr;
+        a.n = (uint32_t)n;
+        a.keys = c->sketch.as<uint32_t>(0);
+        a.cnt = c->sketch.as<uint32_t>(o_cnt);
+        a.mask = (uint32_t)(cap - 1);
+        a.part = c->sketch.as<uint32_t>(o_part);
+        a.max_blocks = max_blocks;
+        a.res = c->sketch.as<unsigned long long>(o_res);
+        FJ_HIP(fj::launch_sketch(a, c->stream));
+        FJ_HIP(hipMemcpyAsync(c->sketch_h + j * fj::kSketchRes, a.res, fj::kSketchRes * 8, hipMemcpyDeviceToHost,
+                              c->stream));
+    }
+    FJ_HIP(hipStreamSynchronize(c->stream));
+    for (int j = 0; j < rel->ncols; j++) {
+        const unsigned long long *r = c->sketch_h + j * fj::kSketchRes;
+        out->distinct[j] = (int64_t)r[fj::kSkDistinct];
+        for (int k = 0; k < FJ_SKETCH_TOPK; k++) out->top[j][k] = (int64_t)r[fj::kSkTop + k];
+    }
+    return FJ_OK;
+}
 
 fj_status fj_build_colt(fj_ctx *c, const fj_query *q, const fj_plan *p, int32_t atom, const fj_relation *rel,
                         fj_colt **out) {

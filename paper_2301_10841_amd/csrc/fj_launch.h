@@ -98,4 +98,34 @@ void emit_dev_fill(void *host_buf, const FrontierDev &F, const std::vector<int> 
                    const std::vector<int> &in_h_atom, const TailDev *tails, int ntail, const int *head_src,
                    int nhead, int32_t *out, unsigned long long out_rows);
 
+// ---- learned plan chooser: column sketch and perceptron
+
+constexpr int kSketchTop = 8;         // largest frequencies kept per column
+constexpr int kSkDistinct = 0;        // result slots (u64) of a sketch
+constexpr int kSkOther = 1;
+constexpr int kSkTop = 2;
+constexpr int kSketchRes = kSkTop + kSketchTop;
+
+struct SketchLaunch {
+    const int32_t *col;
+    const uint32_t *sel;   // nullable: rows are sel[0..n) instead of 0..n
+    uint32_t n;
+    uint32_t *keys, *cnt;  // table of mask + 1 slots
+    uint32_t mask;
+    uint32_t *part;        // max_blocks * kSketchTop
+    uint32_t max_blocks;
+    unsigned long long *res;  // kSketchRes
+};
+
+hipError_t launch_sketch(const SketchLaunch &a, hipStream_t s);
+
+hipError_t mlp_gemm(const float *A, const float *B, const float *bias, float *C, int M, int N, int K, bool ta,
+                    bool tb, bool relu, bool accumulate, hipStream_t s);
+hipError_t mlp_mse_grad(const float *y, const float *t, float *dy, float *sq, int B, hipStream_t s);
+hipError_t mlp_relu_back(const float *h, float *dz, int n, hipStream_t s);
+hipError_t mlp_colsum(const float *dz, float *db, int B, int N, hipStream_t s);
+hipError_t mlp_sum(const float *x, int n, float *out, hipStream_t s);
+hipError_t mlp_adam(float *w, const float *g, float *m, float *v, int n, float lr, float b1, float b2, float eps,
+                    float c1, float c2, hipStream_t s);
+
 }  // namespace fj

@@ -19,6 +19,11 @@ MAX_ATOMS = 16
 MAX_VARS = 32
 MAX_NODES = 16
 FACTOR = 1
+SKETCH_TOPK = 8
+CAND_MAX = 32
+FEATURES = 128
+CAND_BINARY = 0
+CAND_GJ = 1
 
 STATUS = {0: "FJ_OK", 1: "FJ_TRUNCATED", -1: "FJ_ERR_ARG", -2: "FJ_ERR_PLAN_INVALID",
           -3: "FJ_ERR_PLAN_NO_PURE_COVER", -4: "FJ_ERR_OOM", -5: "FJ_ERR_HIP", -6: "FJ_ERR_UNSUPPORTED"}
@@ -63,6 +68,23 @@ class Stats(C.Structure):
         return [{k: int(getattr(self, k)[i]) for k in keys} for i in range(n)]
 
 
+class Sketch(C.Structure):
+    _fields_ = [("rows", C.c_int64), ("ncols", C.c_int32), ("distinct", C.c_int64 * MAX_COLS),
+                ("top", (C.c_int64 * SKETCH_TOPK) * MAX_COLS)]
+
+    def as_dict(self):
+        n = self.ncols
+        return {"rows": int(self.rows), "distinct": [int(self.distinct[j]) for j in range(n)],
+                "top": [[int(self.top[j][k]) for k in range(SKETCH_TOPK)] for j in range(n)]}
+
+
+class Candidate(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n", C.c_int32), ("order", C.c_int32 * MAX_VARS)]
+
+    def key(self):
+        return (int(self.kind), tuple(int(self.order[i]) for i in range(self.n)))
+
+
 _lib = None
 
 
@@ -98,9 +120,27 @@ def lib():
         L.fj_batch_run.argtypes = [vp, vp]
         L.fj_batch_free.argtypes = [vp]
         L.fj_batch_free.restype = None
+        L.fj_sketch_relation.argtypes = [vp, P(Relation), P(Sketch)]
+        L.fj_greedy_order.argtypes = [P(QueryS), vp, C.c_int32, vp]
+        L.fj_plan_candidates.argtypes = [P(QueryS), vp, C.c_int32, vp, P(C.c_int32), vp]
+        L.fj_candidate_plan.argtypes = [P(QueryS), P(Candidate), P(vp)]
+        L.fj_mlp_create.argtypes = [vp, C.c_int32, C.c_int32, P(vp)]
+        L.fj_mlp_param_count.argtypes = [vp]
+        L.fj_mlp_param_count.restype = C.c_int64
+        L.fj_mlp_set_params.argtypes = [vp, vp, C.c_int64]
+        L.fj_mlp_get_params.argtypes = [vp, vp, C.c_int64]
+        L.fj_mlp_forward.argtypes = [vp, vp, C.c_int32, vp]
+        L.fj_mlp_gradient.argtypes = [vp, vp, vp, C.c_int32, vp, P(C.c_float)]
+        L.fj_mlp_train_step.argtypes = [vp, vp, vp, C.c_int32, C.c_float, vp]
+        L.fj_mlp_free.argtypes = [vp]
+        L.fj_mlp_free.restype = None
+        L.fj_choose_plan.argtypes = [vp, vp, P(QueryS), vp, C.c_float, P(vp), P(C.c_int32), vp]
         for name in ("fj_ctx_create", "fj_timings", "fj_timings_reset", "fj_plan_from_binary",
                      "fj_plan_from_nodes", "fj_plan_get", "fj_filter_lt", "fj_filter_lt_batch", "fj_build_colt",
-                     "fj_colt_rebuild", "fj_execute", "fj_batch_create", "fj_batch_run"):
+                     "fj_colt_rebuild", "fj_execute", "fj_batch_create", "fj_batch_run", "fj_sketch_relation",
+                     "fj_greedy_order", "fj_plan_candidates", "fj_candidate_plan", "fj_mlp_create",
+                     "fj_mlp_set_params", "fj_mlp_get_params", "fj_mlp_forward", "fj_mlp_gradient",
+                     "fj_mlp_train_step", "fj_choose_plan"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -271,6 +311,116 @@ class Context:
                               C.byref(wr), C.byref(st) if st is not None else None)
         _check(rc, ok=(0, 1))
         return int(cnt.value), int(wr.value), st
+
+
+    # ---- statistics and plan choice
+    def sketch(self, cols, sel=None, nsel: int = 0) -> Sketch:
+        """Exact distinct counts and top frequencies of each column (GPU)."""
+        rel = _relation(cols, sel, nsel)
+        sk = Sketch()
+        _check(lib().fj_sketch_relation(self.h, C.byref(rel), C.byref(sk)))
+        return sk
+
+    def choose_plan(self, q: QueryS, sketches: Sequence[Sketch], mlp: Optional["Mlp"], margin: float = 0.0):
+        """Returns (Plan, chosen candidate index, scores or None)."""
+        arr = _sketch_array(sketches)
+        h = C.c_void_p()
+        chosen = C.c_int32(0)
+        scores = (C.c_float * CAND_MAX)()
+        _check(lib().fj_choose_plan(self.h, mlp.h if mlp is not None else None, C.byref(q), arr,
+                                    float(margin), C.byref(h), C.byref(chosen), scores))
+        return Plan(h.value, q), int(chosen.value), [float(x) for x in scores]
+
+
+def _sketch_array(sketches: Sequence[Sketch]):
+    return (Sketch * len(sketches))(*sketches)
+
+
+def greedy_order(q: QueryS, sketches: Sequence[Sketch], first: int = -1) -> List[int]:
+    order = (C.c_int32 * MAX_ATOMS)()
+    _check(lib().fj_greedy_order(C.byref(q), _sketch_array(sketches), int(first), order))
+    return [int(order[i]) for i in range(q.natoms)]
+
+
+def plan_candidates(q: QueryS, sketches: Sequence[Sketch], cap: int = CAND_MAX):
+    """Returns (list of Candidate, numpy float32 features [n, FEATURES])."""
+    import numpy as np
+    cands = (Candidate * CAND_MAX)()
+    n = C.c_int32(0)
+    feat = np.zeros((CAND_MAX, FEATURES), dtype=np.float32)
+    _check(lib().fj_plan_candidates(C.byref(q), _sketch_array(sketches), int(cap), cands, C.byref(n),
+                                    C.c_void_p(feat.ctypes.data)))
+    k = int(n.value)
+    out = []
+    for i in range(k):
+        c = Candidate()
+        C.pointer(c)[0] = cands[i]
+        out.append(c)
+    return out, feat[:k].copy()
+
+
+def candidate_plan(q: QueryS, cand: Candidate) -> Plan:
+    h = C.c_void_p()
+    _check(lib().fj_candidate_plan(C.byref(q), C.byref(cand), C.byref(h)))
+    return Plan(h.value, q)
+
+
+class Mlp:
+    """The chooser's perceptron (in_dim -> hidden -> hidden -> 1, FP32), trained
+    and evaluated by libfj's kernels.  Inputs and targets are device float32
+    tensors on the context's device."""
+
+    def __init__(self, ctx: Context, in_dim: int = FEATURES, hidden: int = 128):
+        h = C.c_void_p()
+        _check(lib().fj_mlp_create(ctx.h, int(in_dim), int(hidden), C.byref(h)))
+        self.h = h.value
+        self.ctx = ctx
+        self.in_dim = in_dim
+        self.hidden = hidden
+        self.n = int(lib().fj_mlp_param_count(self.h))
+
+    def set_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        if p.size != self.n:
+            raise ValueError(f"expected {self.n} parameters, got {p.size}")
+        _check(lib().fj_mlp_set_params(self.h, C.c_void_p(p.ctypes.data), self.n))
+
+    def get_params(self):
+        import numpy as np
+        p = np.empty(self.n, dtype=np.float32)
+        _check(lib().fj_mlp_get_params(self.h, C.c_void_p(p.ctypes.data), self.n))
+        return p
+
+    def forward(self, x, y=None):
+        import torch
+        b = int(x.shape[0])
+        if y is None:
+            y = torch.empty(b, dtype=torch.float32, device=x.device)
+        _check(lib().fj_mlp_forward(self.h, C.c_void_p(x.data_ptr()), b, C.c_void_p(y.data_ptr())))
+        return y
+
+    def gradient(self, x, t):
+        import numpy as np
+        g = np.empty(self.n, dtype=np.float32)
+        loss = C.c_float(0)
+        _check(lib().fj_mlp_gradient(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()), int(x.shape[0]),
+                                     C.c_void_p(g.ctypes.data), C.byref(loss)))
+        return g, float(loss.value)
+
+    def train_step(self, x, t, lr: float, want_loss: bool = False):
+        loss = C.c_float(0)
+        _check(lib().fj_mlp_train_step(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
+                                       int(x.shape[0]), float(lr), C.byref(loss) if want_loss else None))
+        return float(loss.value) if want_loss else None
+
+    def free(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.fj_mlp_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.free()
 
 
 class BatchOptions(C.Structure):

@@ -53,6 +53,20 @@ class DeviceQuery:
     def plan_nodes(self, nodes) -> fj.Plan:
         return fj.plan_from_nodes(self.q, nodes)
 
+    def sketches(self) -> List[fj.Sketch]:
+        """Exact per-atom column statistics of the (selected) rows, on the GPU."""
+        return [self.ctx.sketch(self.atom_cols(a), self.sel[a], self.nsel[a]) for a in range(len(self.dq.atoms))]
+
+    def candidates(self, sketches):
+        return fj.plan_candidates(self.q, sketches)
+
+    def candidate_plan(self, cand) -> fj.Plan:
+        return fj.candidate_plan(self.q, cand)
+
+    def choose(self, mlp, sketches, margin: float = 0.0):
+        """(plan, candidate index, scores) chosen by the learned chooser."""
+        return self.ctx.choose_plan(self.q, sketches, mlp, margin)
+
     def build(self, plan: fj.Plan):
         return [self.ctx.build_colt(self.q, plan, a, self.atom_cols(a), self.sel[a], self.nsel[a])
                 for a in range(len(self.dq.atoms))]
