@@ -44,15 +44,24 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-reps", type=int, default=5)
     ap.add_argument("--seed-rep", type=int, default=0)
-    ap.add_argument("--workload", choices=("star", "batch"), default="star")
+    ap.add_argument("--workload", choices=("star", "batch", "rmat"), default="star")
+    ap.add_argument("--rmat-scale", type=int, default=22)
+    ap.add_argument("--rmat-edges", type=int, default=50_000_000)
+    ap.add_argument("--cycle4-scale", type=int, default=16, help="rmat workload: scale of the 4-cycle run")
     ap.add_argument("--queries", type=int, default=256, help="batch workload: number of queries")
     ap.add_argument("--tune-queries", type=int, default=48, help="batch workload: calibration batch size")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        return calibrate_copy()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "rmat":
+        return bench_rmat(args)
 
     import numpy as np
     import torch
@@ -106,6 +115,12 @@ def main():
     achieved = alg_bytes / (avg_probe0_ms * 1e-3) / 1e9
     phases = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps}
               for k, v in tim.items() if v[1]}
+    tr = measured_traffic()
+    traffic_bytes, traffic_note = None, "no counter summary for the current kernel source"
+    if tr:
+        traffic_bytes = tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
+        traffic_note = (f"rocprofv3 FETCH_SIZE + WRITE_SIZE per launch, scaled by a 1 GiB copy "
+                        f"(factors {tr['copy_factor_fetch']:.3f}, {tr['copy_factor_write']:.3f})")
 
     # sanity: exact count against the closed form (numpy, not the GPU)
     from oracle import closed
@@ -150,8 +165,9 @@ def main():
         "count": count,
         "output_tuples_per_s": out_tps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_probe (node 0)", "avg_launch_ms": avg_probe0_ms,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes,
+                     "traffic_note": traffic_note,
+                     "kernel": "k_scan_probe (node 0)", "avg_launch_ms": avg_probe0_ms,
                      "alg_bytes_per_launch": alg_bytes},
         "phases": phases,
         "cpu_baseline": cpu,
@@ -160,6 +176,180 @@ def main():
         c.free()
     ctx.close()
     print(json.dumps(res), flush=True)
+
+
+def sampled_triangles(src, dst, xs):
+    """Exact number of triangles E(x,y), E(y,z), E(z,x) whose x is in xs,
+    by intersecting adjacency lists with numpy (edges are distinct)."""
+    import numpy as np
+    order = np.argsort(src, kind="stable")
+    s_sorted, d_by_src = src[order], dst[order]
+    out_ptr = np.searchsorted(s_sorted, np.arange(int(max(src.max(), dst.max())) + 2))
+    order_in = np.argsort(dst, kind="stable")
+    d_sorted, s_by_dst = dst[order_in], src[order_in]
+    in_ptr = np.searchsorted(d_sorted, np.arange(int(max(src.max(), dst.max())) + 2))
+    total = 0
+    for x in xs:
+        ys = d_by_src[out_ptr[x]:out_ptr[x + 1]]
+        ins = s_by_dst[in_ptr[x]:in_ptr[x + 1]]
+        if ys.size == 0 or ins.size == 0:
+            continue
+        zs = np.concatenate([d_by_src[out_ptr[y]:out_ptr[y + 1]] for y in ys])
+        total += int(np.isin(zs, ins).sum())
+    return total
+
+
+def bench_rmat(args):
+    """Cyclic joins on an R-MAT graph (2^scale vertices, the first n distinct
+    edges, self-loops dropped).  Triangle count with the Generic Join plan
+    [[R(x),T(x)],[R(y),S(y)],[S(z),T(z)]]; one step = COLT root builds + the
+    join (inner tries forced lazily).  Checks: the converted plan gives the
+    same count, and the triangles through 64 sampled x vertices equal an
+    independent numpy count.  Then the 4-cycle at a reduced scale, counted
+    with its Generic Join plan and checked against trace(A^4)."""
+    import numpy as np
+    import torch
+
+    import datagen
+    from datagen import synth
+    from paper_2301_10841_amd import fj, runner
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    src, dst = datagen.rmat_edges(datagen.seed_for(3, 1 + args.seed_rep), args.rmat_scale, args.rmat_edges)
+    log(f"generated {src.size} R-MAT edges (scale {args.rmat_scale}) in {time.time() - t0:.1f}s")
+    ctx = fj.Context(0, timing=True)
+    dq = synth.triangle_query((src, dst))
+    d = runner.DeviceQuery(ctx, dq)
+    gj = d.plan_nodes([[(0, (0,)), (2, (0,))], [(0, (1,)), (1, (1,))], [(1, (2,)), (2, (2,))]])
+    colts = d.build(gj)
+
+    def step():
+        d.rebuild(colts)
+        return ctx.execute(d.q, gj, colts)[0]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timings_reset()
+    ts = time.perf_counter()
+    counts = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - ts
+    tim = ctx.timings()
+    assert len(set(counts)) == 1, counts
+    tri = counts[0]
+    d.rebuild(colts)
+    _, _, st = ctx.execute(d.q, gj, colts, stats=True)
+    nodes = st.per_node()
+    probe_tuples = sum(n["cover"] for n in nodes)
+    probes = sum(n["probe"] for n in nodes)
+    # plan invariance: the converted, factored plan of [R, S, T]
+    conv = d.plan_binary([0, 1, 2], True)
+    t1 = time.perf_counter()
+    r = d.run(conv, materialize=False)
+    conv_s = time.perf_counter() - t1
+    for c in r["colts"]:
+        c.free()
+    assert r["count"] == tri, (r["count"], tri)
+    # sampled parity: triangles through 64 random x vertices
+    rng = np.random.default_rng(12345)
+    xs = np.sort(rng.choice(np.unique(src), size=64, replace=False))
+    want = sampled_triangles(src, dst, xs)
+    keep = np.isin(src, xs)
+    es = synth.Relation("Es", [src[keep], dst[keep]])
+    sq = synth.make_query(["x", "y", "z"], [es, dq.relations[0]], [(0, (0, 1)), (1, (1, 2)), (1, (2, 0))])
+    ds = runner.DeviceQuery(ctx, sq)
+    rs = ds.run(ds.plan_binary([0, 1, 2], True), materialize=False)
+    for c in rs["colts"]:
+        c.free()
+    assert rs["count"] == want, (rs["count"], want)
+    for c in colts:
+        c.free()
+    del d, ds
+    # 4-cycle at a reduced scale against trace(A^4)
+    from oracle import closed
+    s4, d4 = datagen.rmat_edges(datagen.seed_for(3, 1 + args.seed_rep), args.cycle4_scale,
+                                int(round(11.92 * (1 << args.cycle4_scale))))
+    q4 = synth.four_cycle_query((s4, d4))
+    dc = runner.DeviceQuery(ctx, q4)
+    gj4 = dc.plan_nodes([[(0, (0,)), (3, (0,))], [(0, (1,)), (1, (1,))], [(1, (2,)), (2, (2,))],
+                         [(2, (3,)), (3, (3,))]])
+    c4 = dc.build(gj4)
+    dc.rebuild(c4)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    cyc, _, st4 = ctx.execute(dc.q, gj4, c4, stats=True)
+    cyc_s = time.perf_counter() - t2
+    for c in c4:
+        c.free()
+    want4 = closed.cycle_count(s4, d4, 4)
+    assert cyc == want4, (cyc, want4)
+    probes4 = sum(n["probe"] for n in st4.per_node())
+    per = elapsed / args.steps
+    pr_ms, pr_n = tim["probe"]
+    res = {
+        "metric": "probe tuples/sec + output tuples/sec, achieved HBM GB/s; learned vs plain plan time",
+        "value": probe_tuples / per,
+        "unit": "probe tuples/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": per * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic (seeded R-MAT a=.57 b=.19 c=.19 d=.05)",
+        "config": {"workload": f"R-MAT triangle count: 2^{args.rmat_scale} vertices, {src.size} distinct edges, "
+                               f"Generic Join plan; 4-cycle count at 2^{args.cycle4_scale}",
+                   "edges": int(src.size)},
+        "triangles": tri,
+        "probes_per_s": probes / per,
+        "output_tuples_per_s": tri / per,
+        "probe_kernel_ms_per_step": pr_ms / args.steps,
+        "probe_launches_per_step": pr_n / args.steps,
+        "phases": {k: v[0] / args.steps for k, v in tim.items() if v[1]},
+        "converted_plan_s": conv_s,
+        "sampled_x": int(xs.size), "sampled_triangles": want,
+        "cycle4": {"scale": args.cycle4_scale, "edges": int(s4.size), "count": cyc, "seconds": cyc_s,
+                   "probes": probes4, "probes_per_s": probes4 / cyc_s, "check": "trace(A^4)"},
+        "cpu_baseline": None,
+    }
+    ctx.close()
+    print(json.dumps(res), flush=True)
+
+
+def calibrate_copy():
+    """A plain device-to-device copy of 1 GiB, five times: the profiler's
+    FETCH_SIZE / WRITE_SIZE for this kernel divided by 1 GiB is the factor
+    that turns the counters into bytes."""
+    import torch
+    n = 1 << 28
+    src = torch.arange(n, dtype=torch.int32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    assert bool((dst[-4:] == src[-4:]).all())
+    print(json.dumps({"copy_bytes": 4 * n, "launches": 5}), flush=True)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "star_10M_scan_probe_pmc.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2301_10841_amd", "csrc", "fj_kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per node-0 probe launch from the committed counter summary,
+    or None when the kernel source has changed since it was taken."""
+    import hashlib
+    import re
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    m = re.search(r"^traffic_json: (\{.*\})$", open(TRAFFIC_FILE).read(), flags=re.M)
+    if not m:
+        return None
+    t = json.loads(m.group(1))
+    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if t.get("source_sha256") != src:
+        return None
+    return t
 
 
 def bench_batch(args):

@@ -16,5 +16,6 @@ from .synth import (  # noqa: F401
     zipf_keys,
     random_tiny_query,
     batch_mix,
+    batch_query,
     seed_for,
 )

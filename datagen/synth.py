@@ -329,7 +329,22 @@ def batch_mix(seed: int, n_queries: int = 256, min_rows: int = 1_000,
               frac_chain: float = 0.3, frac_star: float = 0.3):
     """The batched workload: 30% chains, 30% stars (3 to 6 relations), 40%
     triangles; rows per relation log-uniform in [min_rows, max_rows]; a
-    per-query Zipf exponent s ~ U[0, 1.5].
+    per-query Zipf exponent s ~ U[0, 1.5].  Query i is ``batch_query(seed,
+    i, ...)``.
+
+    Returns (queries, redraws)."""
+    out = []
+    redraws = 0
+    for qi in range(n_queries):
+        q, r = batch_query(seed, qi, min_rows, max_rows, max_bound, frac_chain, frac_star)
+        out.append(q)
+        redraws += r
+    return out, redraws
+
+
+def batch_query(seed: int, qi: int, min_rows: int = 1_000, max_rows: int = 2_000_000,
+                max_bound: int = 1 << 26, frac_chain: float = 0.3, frac_star: float = 0.3):
+    """Query qi of the batched workload, drawn from its own seeded stream.
 
     Acyclic queries are primary-key/foreign-key joins: the referenced column
     holds distinct keys sampled from a domain of twice the referenced
@@ -341,74 +356,71 @@ def batch_mix(seed: int, n_queries: int = 256, min_rows: int = 1_000,
     times the largest row multiplicity of the third) exceeds ``max_bound`` is
     redrawn.
 
-    Returns (queries, redraws)."""
-    out = []
+    Returns (query, redraws)."""
     redraws = 0
-    for qi in range(n_queries):
-        rng = np.random.Generator(np.random.PCG64(seed * 1_000_003 + qi))
-        u = rng.random()
-        s = float(rng.uniform(0.0, 1.5))
-        lr = lambda: int(round(math.exp(rng.uniform(math.log(min_rows), math.log(max_rows)))))
-        if u < frac_chain:
-            m = int(rng.integers(3, 7))
-            rows = [lr() for _ in range(m)]
-            # R_i(x_i, x_{i+1}); for i >= 1 the column x_i of R_i is a key
-            # (distinct values from a domain of 2 * rows[i]) and the column
-            # x_i of R_{i-1} references it with Zipf(s) skew.
-            doms = [0] + [2 * rows[i] for i in range(1, m)]
-            perms = [None] + [rng.permutation(doms[i]).astype(np.int64) for i in range(1, m)]
-            rels = []
-            for i in range(m):
-                n = rows[i]
-                if i == 0:
-                    first = rng.integers(0, max(2, n), size=n).astype(np.int32)
-                else:
-                    first = rng.choice(doms[i], size=n, replace=False).astype(np.int32)
-                if i == m - 1:
-                    last = rng.integers(0, max(2, n), size=n).astype(np.int32)
-                else:
-                    last = zipf_keys(rng, n, doms[i + 1], s, perms[i + 1])
-                rels.append(Relation(f"R{i}", [first, last]))
-            names = [f"x{i}" for i in range(m + 1)]
-            atoms = [(i, (i, i + 1)) for i in range(m)]
-            out.append(make_query(names, rels, atoms, kind=f"chain{m}"))
-        elif u < frac_chain + frac_star:
-            m = int(rng.integers(3, 7))
-            d = m - 1
-            nf = lr()
-            rels = [None]
-            fcols = []
-            for i in range(d):
-                nd = lr()
-                dom = 2 * nd
-                perm = rng.permutation(dom).astype(np.int64)
-                pk = perm[rng.choice(dom, size=nd, replace=False)].astype(np.int32)
-                attr = rng.integers(0, 100, size=nd).astype(np.int32)
-                rels.append(Relation(f"D{i}", [pk, attr]))
-                fcols.append(zipf_keys(rng, nf, dom, s, perm))
-            rels[0] = Relation("F", fcols)
-            names = [f"k{i}" for i in range(d)] + [f"a{i}" for i in range(d)]
-            atoms = [(0, tuple(range(d)))] + [(i + 1, (i, d + i)) for i in range(d)]
-            out.append(make_query(names, rels, atoms, kind=f"star{m}"))
-        else:
-            while True:
-                rows = [lr() for _ in range(3)]
-                dom = int(math.ceil(max(rows) ** (2.0 / 3.0)))
-                perm = rng.permutation(dom).astype(np.int64)
-                cols = []
-                for n in rows:
-                    cols.append((zipf_keys(rng, n, dom, s, perm), zipf_keys(rng, n, dom, s, perm)))
-                (rx, ry), (sy, sz), (tz, tx) = cols
-                # every joined pair of two relations extends through at most
-                # the largest multiplicity of a row of the third
-                b = min(_two_path_bound(ry, sy, dom) * _max_dup(tz, tx, dom),
-                        _two_path_bound(sz, tz, dom) * _max_dup(rx, ry, dom),
-                        _two_path_bound(tx, rx, dom) * _max_dup(sy, sz, dom))
-                if b <= max_bound:
-                    break
-                redraws += 1
-                s = float(rng.uniform(0.0, 1.5))
-            rels = [Relation("R", [rx, ry]), Relation("S", [sy, sz]), Relation("T", [tz, tx])]
-            out.append(make_query(["x", "y", "z"], rels, [(0, (0, 1)), (1, (1, 2)), (2, (2, 0))],
-                                  kind="triangle"))
-    return out, redraws
+    rng = np.random.Generator(np.random.PCG64(seed * 1_000_003 + qi))
+    u = rng.random()
+    s = float(rng.uniform(0.0, 1.5))
+    lr = lambda: int(round(math.exp(rng.uniform(math.log(min_rows), math.log(max_rows)))))
+    if u < frac_chain:
+        m = int(rng.integers(3, 7))
+        rows = [lr() for _ in range(m)]
+        # R_i(x_i, x_{i+1}); for i >= 1 the column x_i of R_i is a key
+        # (distinct values from a domain of 2 * rows[i]) and the column
+        # x_i of R_{i-1} references it with Zipf(s) skew.
+        doms = [0] + [2 * rows[i] for i in range(1, m)]
+        perms = [None] + [rng.permutation(doms[i]).astype(np.int64) for i in range(1, m)]
+        rels = []
+        for i in range(m):
+            n = rows[i]
+            if i == 0:
+                first = rng.integers(0, max(2, n), size=n).astype(np.int32)
+            else:
+                first = rng.choice(doms[i], size=n, replace=False).astype(np.int32)
+            if i == m - 1:
+                last = rng.integers(0, max(2, n), size=n).astype(np.int32)
+            else:
+                last = zipf_keys(rng, n, doms[i + 1], s, perms[i + 1])
+            rels.append(Relation(f"R{i}", [first, last]))
+        names = [f"x{i}" for i in range(m + 1)]
+        atoms = [(i, (i, i + 1)) for i in range(m)]
+        return make_query(names, rels, atoms, kind=f"chain{m}"), redraws
+    elif u < frac_chain + frac_star:
+        m = int(rng.integers(3, 7))
+        d = m - 1
+        nf = lr()
+        rels = [None]
+        fcols = []
+        for i in range(d):
+            nd = lr()
+            dom = 2 * nd
+            perm = rng.permutation(dom).astype(np.int64)
+            pk = perm[rng.choice(dom, size=nd, replace=False)].astype(np.int32)
+            attr = rng.integers(0, 100, size=nd).astype(np.int32)
+            rels.append(Relation(f"D{i}", [pk, attr]))
+            fcols.append(zipf_keys(rng, nf, dom, s, perm))
+        rels[0] = Relation("F", fcols)
+        names = [f"k{i}" for i in range(d)] + [f"a{i}" for i in range(d)]
+        atoms = [(0, tuple(range(d)))] + [(i + 1, (i, d + i)) for i in range(d)]
+        return make_query(names, rels, atoms, kind=f"star{m}"), redraws
+    else:
+        while True:
+            rows = [lr() for _ in range(3)]
+            dom = int(math.ceil(max(rows) ** (2.0 / 3.0)))
+            perm = rng.permutation(dom).astype(np.int64)
+            cols = []
+            for n in rows:
+                cols.append((zipf_keys(rng, n, dom, s, perm), zipf_keys(rng, n, dom, s, perm)))
+            (rx, ry), (sy, sz), (tz, tx) = cols
+            # every joined pair of two relations extends through at most
+            # the largest multiplicity of a row of the third
+            b = min(_two_path_bound(ry, sy, dom) * _max_dup(tz, tx, dom),
+                    _two_path_bound(sz, tz, dom) * _max_dup(rx, ry, dom),
+                    _two_path_bound(tx, rx, dom) * _max_dup(sy, sz, dom))
+            if b <= max_bound:
+                break
+            redraws += 1
+            s = float(rng.uniform(0.0, 1.5))
+        rels = [Relation("R", [rx, ry]), Relation("S", [sy, sz]), Relation("T", [tz, tx])]
+        return make_query(["x", "y", "z"], rels, [(0, (0, 1)), (1, (1, 2)), (2, (2, 0))],
+                          kind="triangle"), redraws

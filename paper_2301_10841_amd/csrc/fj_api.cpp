@@ -1187,7 +1187,9 @@ extern "C" fj_status fj_execute(fj_ctx *c, const fj_query *q, const fj_plan *p, 
     if (x.out) {
         // the emit descriptor follows the node descriptors in the staging buffer
         FJ_HIP(hipStreamSynchronize(c->stream));
-        fj::emit_dev_fill(c->desc_h, x.F[x.tail_from], p->layout[x.tail_from].in_var, p->layout[x.tail_from].in_hatom,
+        const fj::NodeLayout &LT0 = p->layout[x.tail_from];
+        fj::emit_dev_fill(c->desc_h, x.F[x.tail_from], LT0.in_var.data(), LT0.in_var.size(), LT0.in_hatom.data(),
+                          LT0.in_hatom.size(),
                           x.tails.data(), (int)x.tails.size(), x.head_src.data(), (int)x.head_src.size(), x.out,
                           x.cap);
         FJ_HIP(hipMemcpyAsync(x.emit_d, c->desc_h, fj::emit_dev_size(), hipMemcpyHostToDevice, c->stream));

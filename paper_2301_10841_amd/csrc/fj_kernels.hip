@@ -1238,15 +1238,15 @@ int scan_max_lookups() { return kScanMaxLookups; }
 
 size_t emit_dev_size() { return sizeof(EmitDev); }
 
-void emit_dev_fill(void *host_buf, const FrontierDev &F, const std::vector<int> &in_var,
-                   const std::vector<int> &in_h_atom, const TailDev *tails, int ntail, const int *head_src,
-                   int nhead, int32_t *out, u64 out_rows) {
+void emit_dev_fill(void *host_buf, const FrontierDev &F, const int *in_var, int nin, const int *in_h_atom,
+                   int nin_h, const TailDev *tails, int ntail, const int *head_src, int nhead, int32_t *out,
+                   u64 out_rows) {
     EmitDev *d = (EmitDev *)host_buf;
     memset(d, 0, sizeof(EmitDev));
     d->F = F;
-    d->nin = (int)in_var.size();
+    d->nin = nin;
     for (int j = 0; j < d->nin; j++) d->in_var[j] = in_var[j];
-    d->nin_h = (int)in_h_atom.size();
+    d->nin_h = nin_h;
     for (int j = 0; j < d->nin_h; j++) d->in_h_atom[j] = in_h_atom[j];
     d->ntail = ntail;
     for (int q = 0; q < ntail; q++) d->tail[q] = tails[q];

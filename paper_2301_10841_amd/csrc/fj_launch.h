@@ -94,9 +94,9 @@ hipError_t launch_emit_count(const void *emit_dev, uint32_t E, unsigned long lon
 hipError_t launch_emit_rows(const void *emit_dev, uint32_t E, const unsigned long long *starts,
                             unsigned long long nrows, unsigned long long base, StatusDev *st, hipStream_t s);
 size_t emit_dev_size();
-void emit_dev_fill(void *host_buf, const FrontierDev &F, const std::vector<int> &in_var,
-                   const std::vector<int> &in_h_atom, const TailDev *tails, int ntail, const int *head_src,
-                   int nhead, int32_t *out, unsigned long long out_rows);
+void emit_dev_fill(void *host_buf, const FrontierDev &F, const int *in_var, int nin, const int *in_h_atom,
+                   int nin_h, const TailDev *tails, int ntail, const int *head_src, int nhead, int32_t *out,
+                   unsigned long long out_rows);
 
 // ---- learned plan chooser: column sketch and perceptron
 
@@ -121,6 +121,8 @@ hipError_t launch_sketch(const SketchLaunch &a, hipStream_t s);
 
 hipError_t mlp_gemm(const float *A, const float *B, const float *bias, float *C, int M, int N, int K, bool ta,
                     bool tb, bool relu, bool accumulate, hipStream_t s);
+hipError_t mlp_rows(const float *x, int B, int D, int H, const float *w, const int64_t off[6], float *y,
+                    hipStream_t s);
 hipError_t mlp_mse_grad(const float *y, const float *t, float *dy, float *sq, int B, hipStream_t s);
 hipError_t mlp_relu_back(const float *h, float *dz, int n, hipStream_t s);
 hipError_t mlp_colsum(const float *dz, float *db, int B, int N, hipStream_t s);

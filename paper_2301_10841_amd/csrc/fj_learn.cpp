@@ -232,7 +232,7 @@ Est estimate(const fj_query &q, const fj_sketch *sk, const fj_plan &p) {
     return E;
 }
 
-void featurize(const fj_query &q, const fj_sketch *sk, const fj_plan &p, int kind, float *f) {
+void featurize(const fj_query &q, const fj_sketch *sk, const fj_plan &p, int kind, bool is_cyclic, float *f) {
     std::fill(f, f + FJ_FEATURES, 0.0f);
     const int nn = (int)p.nodes.size();
     double sum_rows = 0, max_rows = 0, min_rows = 1e300, built_rows = 0;
@@ -254,7 +254,7 @@ void featurize(const fj_query &q, const fj_sketch *sk, const fj_plan &p, int kin
     f[2] = nn / 16.0f;
     f[3] = q.natoms / 16.0f;
     f[4] = q.nvars / 32.0f;
-    f[5] = cyclic(q);
+    f[5] = is_cyclic;
     f[6] = lg(sum_rows);
     f[7] = lg(max_rows);
     f[8] = lg(min_rows);
@@ -266,9 +266,10 @@ void featurize(const fj_query &q, const fj_sketch *sk, const fj_plan &p, int kin
     f[14] = lg(built_rows);
     f[15] = nbuilt / 16.0f;
     // atoms in plan order (first appearance of a subatom)
-    std::vector<int> seen;
-    std::vector<int> first_node(q.natoms, -1);
-    std::vector<char> first_pure(q.natoms, 0);
+    int seen[FJ_MAX_ATOMS], nseen = 0;
+    int first_node[FJ_MAX_ATOMS];
+    char first_pure[FJ_MAX_ATOMS] = {0};
+    std::fill(first_node, first_node + FJ_MAX_ATOMS, -1);
     for (int k = 0; k < nn; k++)
         for (size_t i = 0; i < p.nodes[k].size(); i++) {
             const int a = p.nodes[k][i].atom;
@@ -276,9 +277,9 @@ void featurize(const fj_query &q, const fj_sketch *sk, const fj_plan &p, int kin
             first_node[a] = k;
             const auto &pure = p.layout[k].pure;
             first_pure[a] = !pure.empty() && pure[0] == (int)i;
-            seen.push_back(a);
+            seen[nseen++] = a;
         }
-    for (int sl = 0; sl < kSlots && sl < (int)seen.size(); sl++) {
+    for (int sl = 0; sl < kSlots && sl < nseen; sl++) {
         const int a = seen[sl];
         float *g = f + kAtomBase + sl * kSlotF;
         const fj::Subatom &root = p.lev[a][0];
@@ -355,13 +356,18 @@ fj_status make_plan(const fj_query &q, const fj_candidate &c, fj_plan *p) {
 struct Candidates {
     std::vector<fj_candidate> c;
     std::vector<float> feat;
+    std::vector<fj_plan *> plans;  // owned; kept when keep_plans
+    ~Candidates() {
+        for (fj_plan *p : plans) delete p;
+    }
 };
 
-fj_status enumerate(const fj_query &q, const fj_sketch *sk, int cap, Candidates &out) {
+fj_status enumerate(const fj_query &q, const fj_sketch *sk, int cap, Candidates &out, bool keep_plans = false) {
     std::string err;
     FJ_TRY(fj::check_query(q, err) == FJ_OK ? FJ_OK : set_error(FJ_ERR_ARG, err));
     out.c.clear();
     out.feat.clear();
+    const bool is_cyclic = cyclic(q);
     std::vector<std::vector<int>> orders;
     std::vector<int> ord;
     greedy(q, sk, -1, ord);
@@ -397,14 +403,21 @@ fj_status enumerate(const fj_query &q, const fj_sketch *sk, int cap, Candidates 
     }
     for (const auto &c : cands) {
         if ((int)out.c.size() >= cap) break;
-        fj_plan p;
-        if (make_plan(q, c, &p) != FJ_OK) {
-            if (out.c.empty()) return FJ_ERR_PLAN_INVALID;  // the plain plan must exist
+        fj_plan *p = new fj_plan();
+        fj_status st = make_plan(q, c, p);
+        if (st != FJ_OK) {
+            delete p;
+            if (out.c.empty()) return st;  // the plain plan must exist
             continue;
         }
         out.c.push_back(c);
         out.feat.resize(out.c.size() * FJ_FEATURES);
-        featurize(q, sk, p, c.kind, out.feat.data() + (out.c.size() - 1) * FJ_FEATURES);
+        featurize(q, sk, *p, c.kind, is_cyclic, out.feat.data() + (out.c.size() - 1) * FJ_FEATURES);
+        if (keep_plans) {
+            out.plans.push_back(p);
+        } else {
+            delete p;
+        }
     }
     return FJ_OK;
 }
@@ -424,9 +437,8 @@ struct fj_mlp {
     int cap = 0;
     float *loss_h = nullptr;  // pinned
     int64_t step = 0;
-    // chooser staging
-    float *feat_d = nullptr, *score_d = nullptr;
-    float *feat_h = nullptr, *score_h = nullptr;  // pinned
+    // chooser staging (pinned, mapped, coherent)
+    float *feat_h = nullptr, *score_h = nullptr;
     float *h1() const { return act; }
     float *h2() const { return act + (size_t)cap * H; }
     float *dz1() const { return act + 2 * (size_t)cap * H; }
@@ -523,12 +535,10 @@ fj_status fj_mlp_create(fj_ctx *ctx, int32_t in_dim, int32_t hidden, fj_mlp **ou
     float **bufs[4] = {&m->w, &m->g, &m->m, &m->v};
     for (auto b : bufs)
         if (hipMalloc((void **)b, m->np * sizeof(float)) != hipSuccess) return cleanup(FJ_ERR_OOM, "parameters");
-    if (hipMalloc((void **)&m->feat_d, FJ_CAND_MAX * FJ_FEATURES * sizeof(float)) != hipSuccess ||
-        hipMalloc((void **)&m->score_d, FJ_CAND_MAX * sizeof(float)) != hipSuccess)
-        return cleanup(FJ_ERR_OOM, "chooser buffers");
-    if (hipHostMalloc((void **)&m->feat_h, FJ_CAND_MAX * FJ_FEATURES * sizeof(float), hipHostMallocDefault) !=
-            hipSuccess ||
-        hipHostMalloc((void **)&m->score_h, FJ_CAND_MAX * sizeof(float), hipHostMallocDefault) != hipSuccess ||
+    // the chooser's staging is read and written by the GPU directly
+    const unsigned coh = hipHostMallocMapped | hipHostMallocCoherent;
+    if (hipHostMalloc((void **)&m->feat_h, FJ_CAND_MAX * FJ_FEATURES * sizeof(float), coh) != hipSuccess ||
+        hipHostMalloc((void **)&m->score_h, FJ_CAND_MAX * sizeof(float), coh) != hipSuccess ||
         hipHostMalloc((void **)&m->loss_h, sizeof(float), hipHostMallocDefault) != hipSuccess)
         return cleanup(FJ_ERR_OOM, "pinned buffers");
     std::vector<float> zero(m->np, 0.0f);
@@ -600,7 +610,7 @@ void fj_mlp_free(fj_mlp *m) {
     if (!m) return;
     hipSetDevice(m->dev);
     hipStreamSynchronize(m->s);
-    for (float *p : {m->w, m->g, m->m, m->v, m->act, m->feat_d, m->score_d})
+    for (float *p : {m->w, m->g, m->m, m->v, m->act})
         if (p) hipFree(p);
     for (float *p : {m->feat_h, m->score_h, m->loss_h})
         if (p) hipHostFree(p);
@@ -649,15 +659,16 @@ fj_status fj_choose_plan(fj_ctx *ctx, fj_mlp *m, const fj_query *q, const fj_ske
     *out = nullptr;
     if (m && m->D != FJ_FEATURES) return set_error(FJ_ERR_ARG, "the perceptron's input is not FJ_FEATURES wide");
     Candidates C;
-    FJ_TRY(enumerate(*q, sk, FJ_CAND_MAX, C));
+    FJ_TRY(enumerate(*q, sk, FJ_CAND_MAX, C, true));
     const int nc = (int)C.c.size();
     int pick = 0;
     if (m && q->natoms <= kSlots && nc > 1) {
-        FJ_TRY(mlp_check(m, C.feat.data(), nc));
+        // one launch reads the features from and writes the scores to
+        // pinned host memory
+        FJ_HIP(hipSetDevice(m->dev));
         std::copy(C.feat.begin(), C.feat.end(), m->feat_h);
-        FJ_HIP(hipMemcpyAsync(m->feat_d, m->feat_h, C.feat.size() * sizeof(float), hipMemcpyHostToDevice, m->s));
-        FJ_TRY(mlp_fwd(m, m->feat_d, nc, m->score_d));
-        FJ_HIP(hipMemcpyAsync(m->score_h, m->score_d, nc * sizeof(float), hipMemcpyDeviceToHost, m->s));
+        const int64_t off[6] = {m->oW1, m->ob1, m->oW2, m->ob2, m->oW3, m->ob3};
+        FJ_HIP(fj::mlp_rows(m->feat_h, nc, m->D, m->H, m->w, off, m->score_h, m->s));
         FJ_HIP(hipStreamSynchronize(m->s));
         int best = 0;
         for (int i = 1; i < nc; i++)
@@ -666,7 +677,9 @@ fj_status fj_choose_plan(fj_ctx *ctx, fj_mlp *m, const fj_query *q, const fj_ske
         if (scores) std::copy(m->score_h, m->score_h + nc, scores);
     }
     if (chosen) *chosen = pick;
-    return fj_candidate_plan(q, &C.c[pick], out);
+    *out = C.plans[pick];
+    C.plans[pick] = nullptr;
+    return FJ_OK;
 }
 
 }  // extern "C"

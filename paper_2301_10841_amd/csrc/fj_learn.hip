@@ -65,6 +65,38 @@ __global__ void __launch_bounds__(kTile *kTile) k_gemm(const float *__restrict__
     }
 }
 
+// Inference for a few rows in one launch: one workgroup per input row, one
+// thread per hidden unit; the row and both hidden layers stay in LDS.  Each
+// dot product runs in index order in one thread.  x and y may be pinned
+// host memory.
+__global__ void k_mlp_rows(const float *__restrict__ x, int D, int H, const float *__restrict__ w, int64_t oW1,
+                           int64_t ob1, int64_t oW2, int64_t ob2, int64_t oW3, int64_t ob3, float *__restrict__ y) {
+    extern __shared__ float sm[];
+    float *xs = sm, *h1 = sm + D, *h2 = h1 + H;
+    const int r = blockIdx.x, j = threadIdx.x;
+    for (int i = j; i < D; i += blockDim.x) xs[i] = x[(size_t)r * D + i];
+    __syncthreads();
+    if (j < H) {
+        const float *W1 = w + oW1;
+        float a = 0.f;
+        for (int i = 0; i < D; i++) a = fmaf(xs[i], W1[(size_t)i * H + j], a);
+        h1[j] = fmaxf(a + w[ob1 + j], 0.f);
+    }
+    __syncthreads();
+    if (j < H) {
+        const float *W2 = w + oW2;
+        float a = 0.f;
+        for (int k = 0; k < H; k++) a = fmaf(h1[k], W2[(size_t)k * H + j], a);
+        h2[j] = fmaxf(a + w[ob2 + j], 0.f);
+    }
+    __syncthreads();
+    if (j == 0) {
+        float a = 0.f;
+        for (int k = 0; k < H; k++) a = fmaf(h2[k], w[oW3 + k], a);
+        y[r] = a + w[ob3];
+    }
+}
+
 // dY = 2 (y - t) / B, and the loss terms
 __global__ void k_mse_grad(const float *y, const float *t, float *dy, float *sq, int B) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -288,6 +320,15 @@ hipError_t mlp_gemm(const float *A, const float *B, const float *bias, float *C,
                     bool tb, bool relu, bool accumulate, hipStream_t s) {
     hipLaunchKernelGGL(k_gemm, grid2(M, N), dim3(kTile * kTile), 0, s, A, B, bias, C, M, N, K, (int)ta, (int)tb,
                        (int)relu, (int)accumulate);
+    return hipGetLastError();
+}
+
+hipError_t mlp_rows(const float *x, int B, int D, int H, const float *w, const int64_t off[6], float *y,
+                    hipStream_t s) {
+    const int block = ((H + 63) / 64) * 64;
+    const size_t lds = (size_t)(D + 2 * H) * sizeof(float);
+    hipLaunchKernelGGL(k_mlp_rows, dim3(B), dim3(block), lds, s, x, D, H, w, off[0], off[1], off[2], off[3], off[4],
+                       off[5], y);
     return hipGetLastError();
 }
 

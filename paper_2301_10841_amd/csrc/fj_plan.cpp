@@ -120,15 +120,20 @@ static fj_status finish_plan(const fj_query &q, const std::vector<std::vector<Su
                              fj_plan *out, std::string &err) {
     int nn = (int)nodes.size();
     if (nn < 1 || nn > FJ_MAX_NODES) { err = "plan must have 1..FJ_MAX_NODES nodes"; return FJ_ERR_UNSUPPORTED; }
-    *out = fj_plan{};
     out->q = q;
     out->nodes = nodes;
+    for (int a = 0; a < FJ_MAX_ATOMS; a++) {
+        out->nlev[a] = 0;
+        out->root_built[a] = false;
+    }
+    out->tail_from = 0;
     // partition check and schemas
     VarSet seen[FJ_MAX_ATOMS] = {0};
-    out->sub_level.assign(nn, {});
     for (int k = 0; k < nn; k++) {
         if (nodes[k].empty()) { err = "empty plan node"; return FJ_ERR_PLAN_INVALID; }
+        if ((int)nodes[k].size() > FJ_MAX_ATOMS) { err = "validity (a): an atom occurs twice in a node"; return FJ_ERR_PLAN_INVALID; }
         uint32_t atoms_here = 0;
+        int si = 0;
         for (const auto &s : nodes[k]) {
             if (s.atom < 0 || s.atom >= q.natoms) { err = "subatom names an unknown atom"; return FJ_ERR_PLAN_INVALID; }
             if (atoms_here & (1u << s.atom)) { err = "validity (a): an atom occurs twice in a node"; return FJ_ERR_PLAN_INVALID; }
@@ -141,15 +146,21 @@ static fj_status finish_plan(const fj_query &q, const std::vector<std::vector<Su
             if (seen[s.atom] & sv) { err = "the nodes do not partition an atom"; return FJ_ERR_PLAN_INVALID; }
             seen[s.atom] |= sv;
             int l = out->nlev[s.atom]++;
+            if (l >= kMaxLev) { err = "an atom has more levels than nodes"; return FJ_ERR_PLAN_INVALID; }
             out->lev[s.atom][l] = s;
-            out->sub_level[k].push_back(l);
+            out->sub_level[k][si++] = l;
         }
     }
     for (int a = 0; a < q.natoms; a++) {
         if (seen[a] != atom_vset(q, a) || out->nlev[a] == 0) { err = "the nodes do not partition an atom"; return FJ_ERR_PLAN_INVALID; }
     }
     // covers (validity (b)) and pure covers; per-node frontier layout
-    out->layout.assign(nn + 1, {});
+    for (int k = 0; k <= nn; k++) {
+        out->layout[k].in_var.clear();
+        out->layout[k].in_hatom.clear();
+        out->layout[k].new_vars.clear();
+        out->layout[k].pure.clear();
+    }
     VarSet bound = 0;
     int lev_at[FJ_MAX_ATOMS] = {0};  // current level of each atom before node k
     for (int k = 0; k <= nn; k++) {

@@ -12,6 +12,23 @@ namespace fj {
 
 constexpr int kMaxLev = FJ_MAX_NODES;  // a schema has at most one level per node
 
+// A vector of at most N elements stored inline (plans are built per
+// candidate while choosing, so they avoid heap allocations).
+template <typename T, int N>
+struct SmallVec {
+    T v[N];
+    int n = 0;
+    void push_back(const T &x) { v[n++] = x; }
+    int size() const { return n; }
+    bool empty() const { return n == 0; }
+    void clear() { n = 0; }
+    const T &operator[](int i) const { return v[i]; }
+    T &operator[](int i) { return v[i]; }
+    const T *data() const { return v; }
+    const T *begin() const { return v; }
+    const T *end() const { return v + n; }
+};
+
 struct Subatom {
     int atom = -1;
     int nv = 0;
@@ -23,10 +40,10 @@ struct Subatom {
 // that is part-way through its schema, the start position of its current
 // sub-trie at that level (in_hatom).
 struct NodeLayout {
-    std::vector<int> in_var;      // variable ids stored in the input frontier
-    std::vector<int> in_hatom;    // atoms whose inner handle the frontier carries
-    std::vector<int> new_vars;    // variables bound by this node's cover
-    std::vector<int> pure;        // subatom indices (within node) of pure covers
+    SmallVec<int, FJ_MAX_VARS> in_var;     // variable ids stored in the input frontier
+    SmallVec<int, FJ_MAX_ATOMS> in_hatom;  // atoms whose inner handle the frontier carries
+    SmallVec<int, FJ_MAX_VARS> new_vars;   // variables bound by this node's cover
+    SmallVec<int, FJ_MAX_ATOMS> pure;      // subatom indices (within node) of pure covers
 };
 
 }  // namespace fj
@@ -37,8 +54,8 @@ struct fj_plan {
     // schema per atom: level l of atom a is subatom lev[a][l]
     int nlev[FJ_MAX_ATOMS] = {0};
     fj::Subatom lev[FJ_MAX_ATOMS][fj::kMaxLev];
-    std::vector<std::vector<int>> sub_level;  // [node][subatom] -> level in its atom
-    std::vector<fj::NodeLayout> layout;       // nnodes + 1 entries (last = final)
+    int sub_level[FJ_MAX_NODES][FJ_MAX_ATOMS] = {};  // [node][subatom] -> level in its atom
+    fj::NodeLayout layout[FJ_MAX_NODES + 1];          // nnodes + 1 used (last = final)
     bool root_built[FJ_MAX_ATOMS] = {false};
     int tail_from = 0;                        // nodes >= tail_from are single-cover products
 };
