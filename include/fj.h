@@ -191,6 +191,11 @@ fj_status fj_build_colt(fj_ctx *ctx, const fj_query *q, const fj_plan *p, int32_
    unforced) without reallocating; rel may change its row count only
    downward and must keep its arity. */
 fj_status fj_colt_rebuild(fj_ctx *ctx, fj_colt *colt, const fj_relation *rel);
+/* Rebuild n COLTs at once (as fj_colt_rebuild for each colts[k] with
+   rels[k], host arrays): every root build runs in the same few launches.
+   No COLT may appear twice.  Device scratch for the combined root rows is
+   owned by the context and grows when needed. */
+fj_status fj_colt_rebuild_many(fj_ctx *ctx, int32_t n, fj_colt *const *colts, const fj_relation *rels);
 void fj_colt_free(fj_colt *colt);
 
 /* --------------------------------------------------------------------- join */

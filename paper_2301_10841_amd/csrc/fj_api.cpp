@@ -106,6 +106,7 @@ struct fj_ctx {
     DevBuf desc;                    // node + emit descriptors
     DevBuf emitbuf;                 // emit counts and starts
     DevBuf sketch;                  // column sketch table and results
+    struct ColtGroup *group = nullptr;  // fj_colt_rebuild_many's descriptors and scratch
     unsigned long long *sketch_h = nullptr;  // pinned sketch results
     void *desc_h = nullptr;         // pinned staging for descriptors
     size_t desc_h_bytes = 0;
@@ -201,8 +202,16 @@ struct fj_colt {
     int lev_var[fj::kMaxLevels][FJ_MAX_COLS] = {{0}};
     LevelDev lev[fj::kMaxLevels + 1];
     u64 table_slots[fj::kMaxLevels] = {0};
-    fj::FillList *fill_dev = nullptr;   // regions the (re)build initialises
+    // Regions a (re)build initialises: the root level's counters and map and
+    // every level's state words.  An inner level's counters and map are
+    // initialised before its first force after a rebuild (lev_ready).
+    fj::FillList fill_h{};
+    fj::FillList *fill_dev = nullptr;
     u64 fill_words = 0;
+    fj::FillList fill_lev_h[fj::kMaxLevels]{};
+    fj::FillList *fill_lev_dev[fj::kMaxLevels] = {nullptr};
+    u64 fill_lev_words[fj::kMaxLevels] = {0};
+    bool lev_ready[fj::kMaxLevels] = {false};
     std::vector<void *> allocs;
 };
 
@@ -272,6 +281,8 @@ void colt_free_all(fj_colt *t) {
 
 }  // namespace
 
+static fj_status colt_level_ready(fj_ctx *c, fj_colt *t, int l);
+
 // Scratch layout of one force: lens (nh) | pre (nh + 1) | wslot (W) |
 // cntv (W, 64-bit) | ex (W + 1, 64-bit).
 struct ForceScratch {
@@ -292,6 +303,7 @@ struct ForceScratch {
 static fj_status force_queue(fj_ctx *c, fj_colt *t, int l, uint32_t nh, u64 W_known, int timer_cls,
                              fj_stats *stats, int node, bool pre_ready = false) {
     if (nh == 0) return FJ_OK;
+    FJ_TRY(colt_level_ready(c, t, l));
     LevelDev &L = t->lev[l];
     LevelDev &C = t->lev[l + 1];
     u64 Wmax = W_known != ~0ull ? W_known : t->nroot;
@@ -335,14 +347,13 @@ static fj_status force_queue(fj_ctx *c, fj_colt *t, int l, uint32_t nh, u64 W_kn
     return FJ_OK;
 }
 
-// The regions a (re)build initialises: state words, child counters and
-// hash slots of every level (slots empty, the reserved slot unclaimed).
+// The regions a (re)build initialises (the root level's counters and map,
+// every level's state words) and, per inner level, the counters and map its
+// first force initialises.  Map slots start empty, the reserved slot
+// unclaimed.
 static fj_status colt_fill_list(fj_colt *t) {
-    fj::FillList fl;
-    memset(&fl, 0, sizeof(fl));
-    u64 total = 0;
     bool overflow = false;
-    auto add = [&](uint32_t *p, u64 nwords, std::initializer_list<uint32_t> pat) {
+    auto add = [&](fj::FillList &fl, u64 &total, uint32_t *p, u64 nwords, std::initializer_list<uint32_t> pat) {
         if (!p || !nwords) return;
         if (fl.n >= fj::kMaxFill) { overflow = true; return; }
         fj::FillRegion &r = fl.r[fl.n++];
@@ -354,35 +365,61 @@ static fj_status colt_fill_list(fj_colt *t) {
         total += nwords;
     };
     const u64 n = std::max<uint32_t>(t->cap_rows, 1);
+    memset(&t->fill_h, 0, sizeof(t->fill_h));
+    t->fill_words = 0;
     for (int l = 0; l < t->nlev; l++) {
         LevelDev &L = t->lev[l];
-        add(L.st, l == 0 ? 1 : n, {0u});
+        add(t->fill_h, t->fill_words, L.st, l == 0 ? 1 : n, {0u});
+        fj::FillList &fl = l == 0 ? t->fill_h : t->fill_lev_h[l];
+        u64 &words = l == 0 ? t->fill_words : t->fill_lev_words[l];
+        if (l > 0) {
+            memset(&fl, 0, sizeof(fl));
+            words = 0;
+        }
         if (!L.cnt) continue;  // directly iterated base table
-        add(L.cnt, n, {0u});
+        add(fl, words, L.cnt, n, {0u});
         if (!L.table) continue;
         const u64 ns = t->table_slots[l];
         uint32_t *T = (uint32_t *)L.table;
         if (L.mode == fj::KM_K32) {
-            add(T, 2 * (ns - 1), {fj::kEmpty32, 0u});
-            add(T + 2 * (ns - 1), 2, {0u});
+            add(fl, words, T, 2 * (ns - 1), {fj::kEmpty32, 0u});
+            add(fl, words, T + 2 * (ns - 1), 2, {0u});
         } else if (L.mode == fj::KM_K64) {
-            add(T, 4 * (ns - 1), {fj::kEmpty32, fj::kEmpty32, 0u, 0u});
-            add(T + 4 * (ns - 1), 4, {0u});
+            add(fl, words, T, 4 * (ns - 1), {fj::kEmpty32, fj::kEmpty32, 0u, 0u});
+            add(fl, words, T + 4 * (ns - 1), 4, {0u});
         } else {
-            add(T, 4 * ns, {fj::kEmpty32, fj::kEmpty32, 0u, 0u});
+            add(fl, words, T, 4 * ns, {fj::kEmpty32, fj::kEmpty32, 0u, 0u});
         }
     }
     if (overflow) return fail(FJ_ERR_UNSUPPORTED, "too many COLT levels");
     fj::FillList *d = nullptr;
     FJ_TRY(colt_alloc(t, &d, 1));
-    FJ_HIP(hipMemcpy(d, &fl, sizeof(fl), hipMemcpyHostToDevice));
+    FJ_HIP(hipMemcpy(d, &t->fill_h, sizeof(t->fill_h), hipMemcpyHostToDevice));
     t->fill_dev = d;
-    t->fill_words = total;
+    for (int l = 1; l < t->nlev; l++) {
+        if (!t->fill_lev_words[l]) continue;
+        FJ_TRY(colt_alloc(t, &t->fill_lev_dev[l], 1));
+        FJ_HIP(hipMemcpy(t->fill_lev_dev[l], &t->fill_lev_h[l], sizeof(fj::FillList), hipMemcpyHostToDevice));
+    }
+    return FJ_OK;
+}
+
+// Initialise inner level l's counters and map before its first force since
+// the last rebuild.
+static fj_status colt_level_ready(fj_ctx *c, fj_colt *t, int l) {
+    if (l == 0 || t->lev_ready[l]) return FJ_OK;
+    if (t->fill_lev_words[l]) {
+        LevelDev none;
+        memset(&none, 0, sizeof(none));
+        FJ_HIP(fj::launch_fill_list(t->fill_lev_dev[l], t->fill_lev_words[l], none, 0, nullptr, c->stream));
+    }
+    t->lev_ready[l] = true;
     return FJ_OK;
 }
 
 static fj_status colt_reset(fj_ctx *c, fj_colt *t) {
     for (int l = 0; l <= t->nlev; l++) t->lev[l].nrows = (uint32_t)t->nrows;
+    for (int l = 0; l < t->nlev; l++) t->lev_ready[l] = false;
     LevelDev &R = t->lev[0];
     R.offs = const_cast<uint32_t *>(t->sel);
     const bool force_root = t->root_built && t->nroot > 0;
@@ -405,6 +442,154 @@ static fj_status colt_reset(fj_ctx *c, fj_colt *t) {
     }
     return FJ_OK;
 }
+
+// ---------------------------------------------------------- grouped rebuilds
+// The root builds of many COLTs in one launch per phase (fill, root words,
+// the four force passes and one scan), with descriptors and scratch owned by
+// the group.  Member k's work items are the rows of its root when the root
+// map is built.
+
+struct ColtGroup {
+    int n = 0;
+    u64 wtot = 0;
+    uint32_t nfill = 0;
+    DevBuf meta;   // descs | wpre | roots | pre | fill blocks
+    DevBuf work;   // wslot | cntv | ex | block sums | total
+    size_t o_wpre = 0, o_roots = 0, o_pre = 0, o_fill = 0, meta_bytes = 0;
+    size_t w_cntv = 0, w_ex = 0, w_bsum = 0, w_total = 0;
+    std::vector<char> stage, last;   // host image of meta, and the last one uploaded
+    char *stage_h = nullptr;         // pinned copy source
+    size_t stage_h_bytes = 0;
+    void release() {
+        meta.release();
+        work.release();
+        if (stage_h) hipHostFree(stage_h);
+        stage_h = nullptr;
+        stage_h_bytes = 0;
+        last.clear();
+    }
+};
+
+static void destroy_group(ColtGroup *g) {
+    if (!g) return;
+    g->release();
+    delete g;
+}
+
+namespace {
+
+constexpr u64 kFillChunk = 65536;   // words per fill block
+
+// Lay out and upload the group's descriptors for the COLTs' current
+// relations; wcap_min sizes the scratch (at least the current total).
+fj_status group_prepare(fj_ctx *c, ColtGroup &G, fj_colt *const *colts, int n, u64 wcap_min) {
+    G.n = n;
+    std::vector<u64> wpre(n + 1, 0);
+    for (int k = 0; k < n; k++) {
+        const fj_colt *t = colts[k];
+        wpre[k + 1] = wpre[k] + ((t->root_built && t->nroot > 0) ? t->nroot : 0);
+    }
+    G.wtot = wpre[n];
+    const u64 wcap = std::max<u64>(G.wtot, wcap_min);
+    std::vector<fj::FillBlock> fb;
+    for (int k = 0; k < n; k++) {
+        const fj::FillList &fl = colts[k]->fill_h;
+        for (int r = 0; r < fl.n; r++)
+            for (u64 off = 0; off < fl.r[r].nwords; off += kFillChunk) {
+                fj::FillBlock b;
+                b.p = fl.r[r].p;
+                b.start = off;
+                b.n = std::min<u64>(kFillChunk, fl.r[r].nwords - off);
+                for (int q = 0; q < 4; q++) b.pat[q] = fl.r[r].pat[q];
+                b.period = fl.r[r].period;
+                fb.push_back(b);
+            }
+    }
+    if (fb.size() > 0x7fffffff) return fail(FJ_ERR_UNSUPPORTED, "too many fill blocks");
+    G.nfill = (uint32_t)fb.size();
+    G.o_wpre = align256(sizeof(fj::ForceArgs) * n);
+    G.o_roots = G.o_wpre + align256(sizeof(u64) * (n + 1));
+    G.o_pre = G.o_roots + align256(sizeof(fj::GroupRoot) * n);
+    G.o_fill = G.o_pre + align256(sizeof(uint32_t) * 2 * n);
+    G.meta_bytes = G.o_fill + align256(sizeof(fj::FillBlock) * std::max<size_t>(fb.size(), 1));
+    G.w_cntv = align256(sizeof(uint32_t) * (wcap + 1));
+    G.w_ex = G.w_cntv + align256(sizeof(u64) * (wcap + 1));
+    G.w_bsum = G.w_ex + align256(sizeof(u64) * (wcap + 2));
+    G.w_total = G.w_bsum + align256(sizeof(u64) * (wcap / 1024 + 2));
+    FJ_TRY(G.meta.ensure(G.meta_bytes, c->stream));
+    FJ_TRY(G.work.ensure(G.w_total + 256, c->stream));
+    char *meta = G.meta.as<char>();
+    uint32_t *wslot = G.work.as<uint32_t>();
+    u64 *cntv = G.work.as<u64>(G.w_cntv), *ex = G.work.as<u64>(G.w_ex);
+    G.stage.assign(G.meta_bytes, 0);
+    char *h = G.stage.data();
+    fj::ForceArgs *descs = (fj::ForceArgs *)h;
+    fj::GroupRoot *roots = (fj::GroupRoot *)(h + G.o_roots);
+    memcpy(h + G.o_wpre, wpre.data(), sizeof(u64) * (n + 1));
+    for (int k = 0; k < n; k++) {
+        fj_colt *t = colts[k];
+        for (int l = 0; l <= t->nlev; l++) t->lev[l].nrows = (uint32_t)t->nrows;
+        for (int l = 0; l < t->nlev; l++) t->lev_ready[l] = false;
+        LevelDev &R = t->lev[0];
+        R.offs = const_cast<uint32_t *>(t->sel);
+        uint32_t *pre_d = (uint32_t *)(meta + G.o_pre) + 2 * k;
+        fj::ForceArgs &a = descs[k];
+        a.L = R;
+        a.C = t->lev[1];
+        for (int j = 0; j < FJ_MAX_COLS; j++) a.cols[j] = t->cols[j];
+        a.fq = R.fq;
+        a.nh = 1;
+        a.pre = pre_d;
+        a.W = (uint32_t)(wpre[k + 1] - wpre[k]);
+        a.wcap = a.W + 1;
+        a.wslot = wslot + wpre[k];
+        a.cntv = cntv + wpre[k];
+        a.ex = ex + wpre[k];
+        a.status = c->status_d;
+        fj::GroupRoot &g = roots[k];
+        g.len = R.len;
+        g.st = R.st;
+        g.fq = R.fq;
+        g.pre = t->root_built ? pre_d : nullptr;
+        g.nroot = t->nroot;
+        g.built = t->root_built ? 1 : 0;
+    }
+    if (!fb.empty()) memcpy(h + G.o_fill, fb.data(), sizeof(fj::FillBlock) * fb.size());
+    if (G.stage != G.last) {
+        FJ_HIP(hipStreamSynchronize(c->stream));   // the pinned source may still be in use
+        if (G.stage_h_bytes < G.meta_bytes) {
+            if (G.stage_h) hipHostFree(G.stage_h);
+            G.stage_h = nullptr;
+            G.stage_h_bytes = 0;
+            FJ_HIP(hipHostMalloc((void **)&G.stage_h, G.meta_bytes, hipHostMallocDefault));
+            G.stage_h_bytes = G.meta_bytes;
+        }
+        memcpy(G.stage_h, h, G.meta_bytes);
+        FJ_HIP(hipMemcpyAsync(meta, G.stage_h, G.meta_bytes, hipMemcpyHostToDevice, c->stream));
+        G.last = G.stage;
+    }
+    return FJ_OK;
+}
+
+// The launches of a grouped rebuild (no allocation, no host synchronization).
+fj_status group_launch(fj_ctx *c, ColtGroup &G) {
+    char *meta = G.meta.as<char>();
+    const fj::ForceArgs *descs = (const fj::ForceArgs *)meta;
+    const u64 *wpre = (const u64 *)(meta + G.o_wpre);
+    Timer tm(c, FJ_T_BUILD);
+    FJ_HIP(fj::launch_group_fill((const fj::FillBlock *)(meta + G.o_fill), G.nfill,
+                                 (const fj::GroupRoot *)(meta + G.o_roots), G.n, c->stream));
+    if (G.wtot == 0) return FJ_OK;
+    FJ_HIP(fj::launch_group_force(0, descs, wpre, G.n, G.wtot, c->stream));   // insert and count
+    FJ_HIP(fj::launch_group_force(1, descs, wpre, G.n, G.wtot, c->stream));   // (1, count) per new key
+    FJ_HIP(fj::launch_scan_u64(G.work.as<u64>(G.w_cntv), G.work.as<u64>(G.w_ex), G.wtot, G.work.as<u64>(G.w_bsum),
+                               G.work.as<u64>(G.w_total), c->stream));       // ranks and child starts
+    FJ_HIP(fj::launch_group_force(2, descs, wpre, G.n, G.wtot, c->stream));   // publish children
+    FJ_HIP(fj::launch_group_force(3, descs, wpre, G.n, G.wtot, c->stream));   // scatter offsets
+    return FJ_OK;
+}
+
+}  // namespace
 
 static fj_status check_relation(const fj_relation *r, int arity) {
     if (!r) return fail(FJ_ERR_ARG, "null relation");
@@ -471,6 +656,7 @@ void fj_ctx_destroy(fj_ctx *c) {
     c->emitbuf.release();
     c->sketch.release();
     if (c->sketch_h) hipHostFree(c->sketch_h);
+    destroy_group(c->group);
     if (c->desc_h) hipHostFree(c->desc_h);
     for (auto &p : c->pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
     for (auto e : c->pool) hipEventDestroy(e);
@@ -721,6 +907,33 @@ fj_status fj_colt_rebuild(fj_ctx *c, fj_colt *t, const fj_relation *rel) {
     t->nrows = rel->nrows;
     t->nroot = nroot;
     return colt_reset(c, t);
+}
+
+fj_status fj_colt_rebuild_many(fj_ctx *c, int32_t n, fj_colt *const *colts, const fj_relation *rels) {
+    if (!c || n < 0 || (n > 0 && (!colts || !rels))) return fail(FJ_ERR_ARG, "null argument");
+    if (n == 0) return FJ_OK;
+    for (int k = 0; k < n; k++) {
+        if (!colts[k]) return fail(FJ_ERR_ARG, "null COLT");
+        FJ_TRY(check_relation(&rels[k], colts[k]->ncols));
+        const uint32_t nroot = (uint32_t)(rels[k].sel ? rels[k].nsel : rels[k].nrows);
+        if (nroot > colts[k]->cap_rows) return fail(FJ_ERR_ARG, "relation grew beyond the COLT's capacity");
+        if (colts[k]->device != c->device) return fail(FJ_ERR_ARG, "COLT of another device");
+    }
+    for (int k = 0; k < n; k++)
+        for (int j = k + 1; j < n; j++)
+            if (colts[k] == colts[j]) return fail(FJ_ERR_ARG, "a COLT is listed twice");
+    FJ_HIP(hipSetDevice(c->device));
+    for (int k = 0; k < n; k++) {
+        fj_colt *t = colts[k];
+        const fj_relation &r = rels[k];
+        for (int j = 0; j < r.ncols; j++) t->cols[j] = r.cols[j];
+        t->sel = r.sel;
+        t->nrows = r.nrows;
+        t->nroot = (uint32_t)(r.sel ? r.nsel : r.nrows);
+    }
+    if (!c->group) c->group = new ColtGroup();
+    FJ_TRY(group_prepare(c, *c->group, colts, n, 0));
+    return group_launch(c, *c->group);
 }
 
 void fj_colt_free(fj_colt *t) {
@@ -1241,6 +1454,8 @@ struct fj_batch {
     u64 *counts_dev = nullptr;
     u64 *counts_h = nullptr;
     int grid = 0;
+    ColtGroup *group = nullptr;     // every COLT's root build, with its own scratch
+    std::vector<fj_colt *> members;
     hipStream_t stream = nullptr;   // the batch's own stream (the null stream cannot be captured)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1323,9 +1538,7 @@ fj_status batch_query(const fj_query *q, const fj_plan *p, fj_colt *const *colts
 // The launches of one run (rebuilds, zeroed counts, the persistent kernel).
 fj_status batch_launches(fj_batch *b) {
     fj_ctx *c = b->c;
-    if (!b->opt.no_rebuild)
-        for (int i = 0; i < b->n; i++)
-            for (fj_colt *t : b->colts[i]) FJ_TRY(colt_reset(c, t));
+    if (!b->opt.no_rebuild) FJ_TRY(group_launch(c, *b->group));
     FJ_HIP(fj::launch_zero_u64(b->counts_dev, (uint32_t)b->n, c->stream));
     FJ_HIP(fj::launch_batch_dfs(b->q_dev, b->items_dev, b->nitems, b->counts_dev, c->status_d, b->opt.block, b->grid,
                                 c->stream));
@@ -1341,6 +1554,7 @@ void batch_release(fj_batch *b) {
     if (b->counts_dev) hipFree(b->counts_dev);
     if (b->counts_h) hipHostFree(b->counts_h);
     if (b->stream) hipStreamDestroy(b->stream);
+    destroy_group(b->group);
     delete b;
 }
 
@@ -1411,11 +1625,19 @@ extern "C" fj_status fj_batch_create(fj_ctx *c, int32_t n, const fj_query *const
         batch_release(b);
         return fail(FJ_ERR_HIP, "batch upload");
     }
-    // scratch the rebuilds need, sized before any capture
-    {
-        ForceScratch fs(1, max_rows);
-        st = c->force.ensure(fs.bytes(max_rows), c->stream);
-        if (st == FJ_OK) st = c->scanb.ensure((max_rows / 1024 + 2) * sizeof(u64), c->stream);
+    // the grouped root build of every distinct COLT, with descriptors and
+    // scratch owned by the batch (the captured graph keeps their addresses)
+    if (!b->opt.no_rebuild) {
+        u64 wcap = 0;
+        for (int i = 0; i < n; i++)
+            for (fj_colt *t : b->colts[i])
+                if (std::find(b->members.begin(), b->members.end(), t) == b->members.end()) {
+                    b->members.push_back(t);
+                    if (t->root_built) wcap += t->cap_rows;
+                }
+        b->group = new ColtGroup();
+        st = group_prepare(c, *b->group, b->members.data(), (int)b->members.size(), wcap);
+        if (st == FJ_OK) st = sync_status(c);
         if (st != FJ_OK) { batch_release(b); return st; }
     }
     if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
@@ -1458,6 +1680,9 @@ extern "C" fj_status fj_batch_run(fj_batch *b, uint64_t *counts) {
         FJ_HIP(hipMemcpyAsync(b->counts_h, b->counts_dev, sizeof(u64) * b->n, hipMemcpyDeviceToHost, c->stream));
         return sync_status(c);
     }));
+    // the run rebuilt every root: inner levels need initialising again
+    for (fj_colt *t : b->members)
+        for (int l = 0; l < t->nlev; l++) t->lev_ready[l] = false;
     memcpy(counts, b->counts_h, sizeof(u64) * b->n);
     return FJ_OK;
 }

@@ -183,6 +183,37 @@ struct FillList {
     FillRegion r[kMaxFill];
 };
 
+// One force: the handles queued on level L regrouped into child level C.
+// Per-item scratch (wslot, cntv, ex) is indexed by the item's position among
+// the queued handles' offsets.
+struct ForceArgs {
+    LevelDev L;
+    LevelDev C;
+    const int32_t *cols[FJ_MAX_COLS];
+    const uint32_t *fq;     // queued handle starts
+    uint32_t nh;            // number of queued handles
+    const uint32_t *pre;    // exclusive scan of their lengths (nh + 1)
+    uint32_t W;             // total offsets
+    uint32_t wcap;          // capacity of the per-item scratch arrays
+    uint32_t *wslot;        // per item: slot index | kClaim for the item that inserted the key
+    unsigned long long *cntv;  // per item: (1 << 32 | offsets of the key) for claimers, else 0
+    unsigned long long *ex;    // exclusive scan of cntv (W + 1)
+    struct StatusDev *status;
+};
+
+// Grouped root builds: a chunk of a fill region, and a COLT's root words.
+struct FillBlock {
+    uint32_t *p;
+    unsigned long long start, n;   // words [start, start + n) of the region at p
+    uint32_t pat[4];
+    int period;
+};
+struct GroupRoot {
+    uint32_t *len, *st, *fq, *pre;
+    uint32_t nroot;
+    int built;
+};
+
 // Host <-> device status block, one per context.
 struct StatusDev {
     unsigned long long count;      // result tuples so far

@@ -262,7 +262,7 @@ __global__ void k_fill_list(const FillList *__restrict__ fl, LevelDev root, uint
         const FillRegion &r = fl->r[k];
         for (u64 i = tid; i < r.nwords; i += stride) r.p[i] = r.pat[i % (u64)r.period];
     }
-    if (tid == 0) {
+    if (tid == 0 && root.len) {
         root.len[0] = nroot;
         root.st[0] = 0;
         if (root.fq) root.fq[0] = 0;
@@ -408,20 +408,6 @@ __device__ __noinline__ void fj_bad(StatusDev *st, int line) {
 // occupying the handle's own position range, and fill the level's map with
 // (handle, key) -> child start.
 
-struct ForceArgs {
-    LevelDev L;
-    LevelDev C;
-    const int32_t *cols[FJ_MAX_COLS];
-    const uint32_t *fq;     // queued handle starts
-    uint32_t nh;            // number of queued handles
-    const uint32_t *pre;    // exclusive scan of their lengths (nh + 1)
-    uint32_t W;             // total offsets
-    uint32_t wcap;          // capacity of the per-item scratch arrays
-    uint32_t *wslot;        // per item: slot index | kClaim for the item that inserted the key
-    u64 *cntv;              // per item: (1 << 32 | offsets of the key) for claimers, else 0
-    u64 *ex;                // exclusive scan of cntv (W + 1)
-    StatusDev *status;
-};
 
 // Locate work item w: queue entry j, handle p, index i in it, base row.
 __device__ __forceinline__ bool force_item(const ForceArgs &a, uint32_t w, uint32_t &j, uint32_t &p,
@@ -446,10 +432,8 @@ __global__ void __launch_bounds__(256) k_fq_lens(LevelDev L, const uint32_t *fq,
 
 // Pass 1: insert each offset's key (handle, key values) and count the
 // offsets per key in the slot's value word; the inserting item is marked.
-__global__ void __launch_bounds__(256) k_force_insert(ForceArgs a) {
+__device__ __forceinline__ void force_insert_item(const ForceArgs &a, uint32_t w) {
     StatusDev *status = a.status;
-    uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= a.W) return;
     uint32_t j, p, i, row;
     if (!force_item(a, w, j, p, i, row)) { a.wslot[w] = 0; return; }
     if (a.L.mode == KM_ZERO) {             // one key: the first offset claims it
@@ -468,12 +452,15 @@ __global__ void __launch_bounds__(256) k_force_insert(ForceArgs a) {
     a.wslot[w] = (uint32_t)sl | (claimed ? kClaim : 0u);
 }
 
+__global__ void __launch_bounds__(256) k_force_insert(ForceArgs a) {
+    uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w < a.W) force_insert_item(a, w);
+}
+
 // Pass 2: each key's (1, offset count) at its inserting item; a scan of
 // these pairs gives every key its rank among its handle's keys (high half)
 // and the start of its child segment (low half).
-__global__ void __launch_bounds__(256) k_force_pack(ForceArgs a) {
-    uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= a.W) return;
+__device__ __forceinline__ void force_pack_item(const ForceArgs &a, uint32_t w) {
     const uint32_t ws = a.wslot[w];
     u64 v = 0;
     if (ws & kClaim) {
@@ -489,13 +476,16 @@ __global__ void __launch_bounds__(256) k_force_pack(ForceArgs a) {
     a.cntv[w] = v;
 }
 
+__global__ void __launch_bounds__(256) k_force_pack(ForceArgs a) {
+    uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w < a.W) force_pack_item(a, w);
+}
+
 // Pass 3: keys publish their child segment: key list entry, child length,
 // scatter cursor, and the map value becomes the child's start.  The first
 // item of each handle records its key count (the forced state).
-__global__ void __launch_bounds__(256) k_force_children(ForceArgs a) {
+__device__ __forceinline__ void force_children_item(const ForceArgs &a, uint32_t w) {
     StatusDev *status = a.status;
-    uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= a.W) return;
     uint32_t j, p, i, row;
     if (!force_item(a, w, j, p, i, row)) return;
     const u64 base = a.ex[a.pre[j]];
@@ -516,12 +506,15 @@ __global__ void __launch_bounds__(256) k_force_children(ForceArgs a) {
     if (a.L.mode != KM_ZERO) *slot_val_ptr(a.L, ws & ~kClaim) = s;
 }
 
+__global__ void __launch_bounds__(256) k_force_children(ForceArgs a) {
+    uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w < a.W) force_children_item(a, w);
+}
+
 // Pass 4: every offset moves into its key's child segment.  The cursor
 // counts down to zero, leaving the counter array clean for the next force.
-__global__ void __launch_bounds__(256) k_force_scatter(ForceArgs a) {
+__device__ __forceinline__ void force_scatter_item(const ForceArgs &a, uint32_t w) {
     StatusDev *status = a.status;
-    uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= a.W) return;
     uint32_t j, p, i, row;
     if (!force_item(a, w, j, p, i, row)) return;
     const uint32_t ws = a.wslot[w];
@@ -530,6 +523,64 @@ __global__ void __launch_bounds__(256) k_force_scatter(ForceArgs a) {
     const uint32_t pos = s + atomicSub(&a.L.cnt[s], 1u) - 1u;
     if (!CK(pos >= s && pos < p + a.L.len[p])) return;
     a.C.offs[pos] = row;
+}
+
+__global__ void __launch_bounds__(256) k_force_scatter(ForceArgs a) {
+    uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w < a.W) force_scatter_item(a, w);
+}
+
+// ------------------------------------------------------- grouped root builds
+// The root builds of many COLTs in one launch per phase: work item g of the
+// group belongs to the COLT k with wpre[k] <= g < wpre[k + 1] and is that
+// COLT's item g - wpre[k].  Each COLT's descriptor points at its own slice of
+// the group's scratch, so one scan over the concatenated per-item pairs gives
+// every COLT its ranks and child starts.
+
+__device__ __forceinline__ int group_member(const u64 *__restrict__ wpre, int n, u64 g) {
+    int lo = 0, hi = n;   // wpre[lo] <= g < wpre[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (wpre[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <int PHASE>
+__global__ void __launch_bounds__(256) k_group_force(const ForceArgs *__restrict__ descs, const u64 *__restrict__ wpre,
+                                                     int n, u64 wtot) {
+    const u64 g = (u64)blockIdx.x * 256 + threadIdx.x;
+    if (g >= wtot) return;
+    const int k = group_member(wpre, n, g);
+    const ForceArgs &a = descs[k];
+    const uint32_t w = (uint32_t)(g - wpre[k]);
+    if (w >= a.W) return;
+    if (PHASE == 0) force_insert_item(a, w);
+    else if (PHASE == 1) force_pack_item(a, w);
+    else if (PHASE == 2) force_children_item(a, w);
+    else force_scatter_item(a, w);
+}
+
+// One block per FillBlock: a chunk of one region set to its periodic pattern.
+__global__ void __launch_bounds__(256) k_group_fill(const FillBlock *__restrict__ fb) {
+    const FillBlock &b = fb[blockIdx.x];
+    for (u64 i = threadIdx.x; i < b.n; i += 256) {
+        const u64 word = b.start + i;
+        b.p[word] = b.pat[word % (u64)b.period];
+    }
+}
+
+// Per COLT: the root handle spans every root row; a built root with no rows
+// is forced with no keys; the root's force queue holds the root handle.
+__global__ void k_group_roots(const GroupRoot *__restrict__ r, int n) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const GroupRoot &g = r[k];
+    g.len[0] = g.nroot;
+    g.st[0] = (g.built && g.nroot == 0) ? 1u : 0u;
+    if (g.fq) g.fq[0] = 0;
+    if (g.pre) { g.pre[0] = 0; g.pre[1] = g.nroot; }
 }
 
 // ----------------------------------------------------------- cover choice
@@ -1160,6 +1211,25 @@ hipError_t launch_force_phase(int phase, const ForceLaunch &f, hipStream_t s) {
         case 1: hipLaunchKernelGGL(k_force_pack, g, b, 0, s, a); break;
         case 2: hipLaunchKernelGGL(k_force_children, g, b, 0, s, a); break;
         case 3: hipLaunchKernelGGL(k_force_scatter, g, b, 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_group_fill(const FillBlock *fb, uint32_t nblocks, const GroupRoot *roots, int n, hipStream_t s) {
+    if (nblocks) hipLaunchKernelGGL(k_group_fill, dim3(nblocks), dim3(256), 0, s, fb);
+    if (n) hipLaunchKernelGGL(k_group_roots, dim3((n + 255) / 256), dim3(256), 0, s, roots, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_force(int phase, const ForceArgs *descs, const u64 *wpre, int n, u64 wtot, hipStream_t s) {
+    if (wtot == 0) return hipSuccess;
+    dim3 g((unsigned)((wtot + 255) / 256)), b(256);
+    switch (phase) {
+        case 0: hipLaunchKernelGGL(k_group_force<0>, g, b, 0, s, descs, wpre, n, wtot); break;
+        case 1: hipLaunchKernelGGL(k_group_force<1>, g, b, 0, s, descs, wpre, n, wtot); break;
+        case 2: hipLaunchKernelGGL(k_group_force<2>, g, b, 0, s, descs, wpre, n, wtot); break;
+        case 3: hipLaunchKernelGGL(k_group_force<3>, g, b, 0, s, descs, wpre, n, wtot); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -84,6 +84,9 @@ hipError_t launch_filter_lt(const int32_t *col, unsigned long long n, int32_t bo
 hipError_t launch_fq_lens(const LevelDev &L, const uint32_t *fq, uint32_t nh, uint32_t *lens, StatusDev *st,
                           hipStream_t s);
 hipError_t launch_force_phase(int phase, const ForceLaunch &f, hipStream_t s);
+hipError_t launch_group_fill(const FillBlock *fb, uint32_t nblocks, const GroupRoot *roots, int n, hipStream_t s);
+hipError_t launch_group_force(int phase, const ForceArgs *descs, const unsigned long long *wpre, int n,
+                              unsigned long long wtot, hipStream_t s);
 hipError_t launch_cover_choose(const NodeDev *nd, uint32_t E, uint8_t *cov, unsigned long long *cnt,
                                StatusDev *st, hipStream_t s);
 hipError_t launch_cover_fill(const NodeDev *nd, uint32_t E, const uint8_t *cov, unsigned long long *cnt,

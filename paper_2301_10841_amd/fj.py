@@ -112,6 +112,7 @@ def lib():
         L.fj_filter_lt_batch.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp]
         L.fj_build_colt.argtypes = [vp, P(QueryS), vp, C.c_int32, P(Relation), P(vp)]
         L.fj_colt_rebuild.argtypes = [vp, vp, P(Relation)]
+        L.fj_colt_rebuild_many.argtypes = [vp, C.c_int32, vp, vp]
         L.fj_colt_free.argtypes = [vp]
         L.fj_colt_free.restype = None
         L.fj_execute.argtypes = [vp, P(QueryS), vp, vp, P(C.c_uint64), vp, C.c_uint64,
@@ -137,7 +138,7 @@ def lib():
         L.fj_choose_plan.argtypes = [vp, vp, P(QueryS), vp, C.c_float, P(vp), P(C.c_int32), vp]
         for name in ("fj_ctx_create", "fj_timings", "fj_timings_reset", "fj_plan_from_binary",
                      "fj_plan_from_nodes", "fj_plan_get", "fj_filter_lt", "fj_filter_lt_batch", "fj_build_colt",
-                     "fj_colt_rebuild", "fj_execute", "fj_batch_create", "fj_batch_run", "fj_sketch_relation",
+                     "fj_colt_rebuild", "fj_colt_rebuild_many", "fj_execute", "fj_batch_create", "fj_batch_run", "fj_sketch_relation",
                      "fj_greedy_order", "fj_plan_candidates", "fj_candidate_plan", "fj_mlp_create",
                      "fj_mlp_set_params", "fj_mlp_get_params", "fj_mlp_forward", "fj_mlp_gradient",
                      "fj_mlp_train_step", "fj_choose_plan"):
@@ -297,6 +298,17 @@ class Context:
         rel = _relation(cols, sel, nsel)
         _check(lib().fj_colt_rebuild(self.h, colt.h, C.byref(rel)))
         colt.keep = (cols, sel)
+
+    def rebuild_colts(self, colts: Sequence["Colt"], specs):
+        """Rebuild many COLTs in one grouped pass; specs[k] = (cols, sel, nsel)."""
+        n = len(colts)
+        if n == 0:
+            return
+        rels = (Relation * n)(*[_relation(*sp) for sp in specs])
+        arr = (C.c_void_p * n)(*[c.h for c in colts])
+        _check(lib().fj_colt_rebuild_many(self.h, n, arr, rels))
+        for c, sp in zip(colts, specs):
+            c.keep = (sp[0], sp[1])
 
     # ---- join
     def execute(self, q: QueryS, plan: Plan, colts: Sequence["Colt"], out=None, stats: bool = False):

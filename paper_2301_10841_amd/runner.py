@@ -72,8 +72,8 @@ class DeviceQuery:
                 for a in range(len(self.dq.atoms))]
 
     def rebuild(self, colts):
-        for a, c in enumerate(colts):
-            self.ctx.rebuild_colt(c, self.atom_cols(a), self.sel[a], self.nsel[a])
+        """Rebuild every COLT of the query in one grouped pass."""
+        self.ctx.rebuild_colts(colts, [(self.atom_cols(a), self.sel[a], self.nsel[a]) for a in range(len(colts))])
 
     def run(self, plan: fj.Plan, materialize: bool = True, cap: Optional[int] = None,
             stats: bool = False, colts=None):

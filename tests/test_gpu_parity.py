@@ -297,6 +297,47 @@ def test_repeat_and_rebuild(fjm, ctx):
         c.free()
 
 
+def test_grouped_rebuild_matches_single_rebuilds(fjm, ctx):
+    # one grouped pass over the COLTs of several queries (built and
+    # directly iterated roots, an empty relation, inner levels forced lazily
+    # afterwards) gives the same results as rebuilding them one by one
+    fj, runner = fjm
+    e = datagen.triangle_edges(7, n_edges=3000, n_vertices=300)
+    tri = datagen.synth.triangle_query(e)
+    empty = datagen.synth.triangle_query((np.zeros(0, np.int32), np.zeros(0, np.int32)))
+    star = datagen.star_schema(11, n_fact=60_000, n_dim=6_000)
+    chain = datagen.batch_mix(31, n_queries=4, max_rows=30_000)[0]
+    runs = []
+    for dq, nodes in [(tri, gj_nodes(tri, [0, 1, 2])), (tri, None), (empty, None), (star, None)] + \
+            [(q, None) for q in chain]:
+        d = runner.DeviceQuery(ctx, dq)
+        plan = d.plan_nodes(nodes) if nodes else d.plan_binary(list(range(len(dq.atoms))), True)
+        colts = d.build(plan)
+        want = oracle_run(dq, plan.nodes(), materialize=False, counters=False)["count"]
+        runs.append((d, plan, colts, want))
+    for rep in range(3):
+        allc, specs = [], []
+        for d, plan, colts, _ in runs:
+            for a, c in enumerate(colts):
+                allc.append(c)
+                specs.append((d.atom_cols(a), d.sel[a], d.nsel[a]))
+        ctx.rebuild_colts(allc, specs)
+        for d, plan, colts, want in runs:
+            assert ctx.execute(d.q, plan, colts)[0] == want, (rep, d.dq.kind)
+        # single rebuilds in between
+        for d, plan, colts, want in runs:
+            for a, c in enumerate(colts):
+                ctx.rebuild_colt(c, d.atom_cols(a), d.sel[a], d.nsel[a])
+            assert ctx.execute(d.q, plan, colts)[0] == want
+    d, plan, colts, _ = runs[0]
+    with pytest.raises(fj.FJError) as ex:
+        ctx.rebuild_colts([colts[0], colts[0]], [(d.atom_cols(0), None, 0)] * 2)
+    assert ex.value.status == -1
+    for _, _, colts, _ in runs:
+        for c in colts:
+            c.free()
+
+
 def test_scan_path_matches_generic_kernel(fjm, ctx):
     # the specialised first-node kernel and the generic one give the same
     # results and the same lookup counts
