@@ -355,7 +355,10 @@ static fj_status colt_fill_list(fj_colt *t) {
     bool overflow = false;
     auto add = [&](fj::FillList &fl, u64 &total, uint32_t *p, u64 nwords, std::initializer_list<uint32_t> pat) {
         if (!p || !nwords) return;
-        if (fl.n >= fj::kMaxFill) { overflow = true; return; }
+        if (fl.n >= fj::kMaxFill || (pat.size() != 1 && pat.size() != 2 && pat.size() != 4)) {
+            overflow = true;   // the fill kernels take periods of 1, 2 or 4 words
+            return;
+        }
         fj::FillRegion &r = fl.r[fl.n++];
         r.p = p;
         r.nwords = nwords;
@@ -1454,6 +1457,7 @@ struct fj_batch {
     u64 *counts_dev = nullptr;
     u64 *counts_h = nullptr;
     int grid = 0;
+    int lv = 1, la = 1;             // largest variable and atom counts (lane state sizes)
     ColtGroup *group = nullptr;     // every COLT's root build, with its own scratch
     std::vector<fj_colt *> members;
     hipStream_t stream = nullptr;   // the batch's own stream (the null stream cannot be captured)
@@ -1469,6 +1473,8 @@ fj_status batch_query(const fj_query *q, const fj_plan *p, fj_colt *const *colts
     const int nexec = p->tail_from;
     if (nexec < 1 || nexec > fj::kBMaxNodes) return fail(FJ_ERR_UNSUPPORTED, "batched plans run 1..8 probing nodes");
     B.nexec = nexec;
+    B.nvars = q->nvars;
+    B.natoms = q->natoms;
     for (int k = 0; k < nexec; k++) {
         const auto &node = p->nodes[k];
         const auto &L = p->layout[k];
@@ -1541,7 +1547,7 @@ fj_status batch_launches(fj_batch *b) {
     if (!b->opt.no_rebuild) FJ_TRY(group_launch(c, *b->group));
     FJ_HIP(fj::launch_zero_u64(b->counts_dev, (uint32_t)b->n, c->stream));
     FJ_HIP(fj::launch_batch_dfs(b->q_dev, b->items_dev, b->nitems, b->counts_dev, c->status_d, b->opt.block, b->grid,
-                                c->stream));
+                                b->lv, b->la, c->stream));
     return FJ_OK;
 }
 
@@ -1598,6 +1604,8 @@ extern "C" fj_status fj_batch_create(fj_ctx *c, int32_t n, const fj_query *const
         }
         b->qs.push_back(qs[i]);
         b->plans.push_back(plans[i]);
+        b->lv = std::max<int>(b->lv, qs[i]->nvars);
+        b->la = std::max<int>(b->la, qs[i]->natoms);
         b->colts.emplace_back(colts[i], colts[i] + qs[i]->natoms);
         for (fj_colt *t : b->colts.back()) max_rows = std::max<u64>(max_rows, t->cap_rows);
         const uint32_t chunk =
@@ -1609,7 +1617,9 @@ extern "C" fj_status fj_batch_create(fj_ctx *c, int32_t n, const fj_query *const
     std::stable_sort(items.begin(), items.end(),
                      [](const fj::BItem &x, const fj::BItem &y) { return x.r1 - x.r0 > y.r1 - y.r0; });
     b->nitems = (uint32_t)items.size();
-    const int per_cu = std::max(1, 2048 / b->opt.block);
+    // workgroups that fit a CU's 160 KB of LDS at once
+    const size_t lds_per = 2 * sizeof(uint32_t) * (size_t)(b->lv + b->la) * b->opt.block;
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(2048 / b->opt.block, (160 * 1024) / lds_per));
     b->grid = (int)std::max<u64>(1, std::min<u64>(b->nitems, (u64)c->num_cus * per_cu));
     fj_status st = FJ_OK;
     if (hipMalloc((void **)&b->q_dev, sizeof(fj::BQuery) * n) != hipSuccess ||

@@ -118,24 +118,97 @@ __device__ __forceinline__ void dfs(const BQuery &Q, const Lane &ln, u64 mult, u
     }
 }
 
-__global__ void __launch_bounds__(1024) k_batch_dfs(const BQuery *__restrict__ qs, const BItem *__restrict__ items,
-                                                    uint32_t nitems, u64 *counts, StatusDev *status) {
+// Node 1 for the node-0 bindings of a whole wave, balanced over its lanes:
+// the (binding, child offset) pairs of the 64 lanes are numbered by a wave
+// scan of the bindings' child counts and dealt out to the lanes in turn, so
+// a binding with many children (a heavy key under skew) does not keep the
+// rest of the wave idle.  A lane takes a pair's binding from its owner's
+// lane state (LDS) into its own scratch state and goes on depth first.
+// Called by every lane of the wave (lim = 0 for lanes with no binding).
+__device__ __forceinline__ void expand_node1(const BQuery &Q, const Lane &ln, const Lane &sc, uint32_t base,
+                                             uint32_t lim, u64 m, u64 &total, StatusDev *status) {
+    const BNode &N = Q.node[1];
+    const int lane = threadIdx.x & 63;
+    const int wbase = threadIdx.x & ~63;
+    u64 x = lim;   // inclusive prefix of the child counts over the wave
+    for (int o = 1; o < 64; o <<= 1) {
+        const u64 y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    const u64 tot = __shfl(x, 63, 64);
+    __builtin_amdgcn_wave_barrier();
+    for (u64 t0 = 0; t0 < tot; t0 += 64) {
+        const u64 t = t0 + lane;
+        int lo = 0, hi = 63;   // owner: the first lane whose prefix exceeds t
+#pragma unroll
+        for (int step = 0; step < 6; step++) {
+            const int mid = (lo + hi) >> 1;
+            if (__shfl(x, mid, 64) > t) hi = mid;
+            else lo = mid + 1;
+        }
+        const u64 xo = __shfl(x, lo, 64);
+        const uint32_t limo = __shfl(lim, lo, 64);
+        const uint32_t baseo = __shfl(base, lo, 64);
+        const u64 mo = __shfl(m, lo, 64);
+        if (t >= tot) continue;
+        const uint32_t pos = (uint32_t)(t - (xo - limo));
+        const int otid = wbase + lo;
+        for (int v = 0; v < Q.nvars; v++) sc.var(v) = ln.v[v * blockDim.x + otid];
+        for (int a = 0; a < Q.natoms; a++) sc.hdl(a) = ln.h[a * blockDim.x + otid];
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t p = baseo + pos;
+        if (!BCK(pos < limo && p < N.npos)) continue;
+        const uint32_t rw = N.offs[p];
+        if (!BCK(rw < N.nrows)) continue;
+        for (int c = 0; c < N.nk; c++) sc.var(N.kslot[c]) = N.kcol[c][rw];
+        u64 mm = mo;
+        if (!probe_node(N, sc, mm, status)) continue;
+        dfs<2>(Q, sc, mm, total, status);
+    }
+}
+
+__global__ void __launch_bounds__(512) k_batch_dfs(const BQuery *__restrict__ qs, const BItem *__restrict__ items,
+                                                   uint32_t nitems, u64 *counts, StatusDev *status, int lv,
+                                                   int la) {
     extern __shared__ uint32_t lds[];
     __shared__ u64 red[16];
-    const Lane ln{(int32_t *)lds, lds + kBMaxVars * blockDim.x};
+    // two lane states per thread, each lv variables and la handles (the
+    // batch's largest counts): its own (node 0) and a scratch one (node 1
+    // pairs dealt to it by expand_node1)
+    const uint32_t per = (uint32_t)(lv + la) * blockDim.x;
+    const Lane ln{(int32_t *)lds, lds + lv * blockDim.x};
+    const Lane sc{(int32_t *)(lds + per), lds + per + lv * blockDim.x};
     for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const BItem item = items[it];
         const BQuery &Q = qs[item.q];
         u64 total = 0;
-        for (uint32_t r = item.r0 + threadIdx.x; r < item.r1; r += blockDim.x) {
+        // the same number of rounds for every lane, so that node 1 can be
+        // expanded by the whole wave
+        for (uint32_t rb = item.r0; rb < item.r1; rb += blockDim.x) {
+            const uint32_t r = rb + threadIdx.x;
             // node 0: the cover is a base table (or its selection)
             const BNode &N0 = Q.node[0];
-            const uint32_t row = N0.offs ? N0.offs[r] : r;
-            if (!BCK(row < N0.nrows)) continue;
-            for (int c = 0; c < N0.nk; c++) ln.var(N0.kslot[c]) = N0.kcol[c][row];
+            bool ok = r < item.r1;
             u64 m = 1;
-            if (!probe_node(N0, ln, m, status)) continue;
-            dfs<1>(Q, ln, m, total, status);
+            if (ok) {
+                const uint32_t row = N0.offs ? N0.offs[r] : r;
+                ok = BCK(row < N0.nrows);
+                if (ok) {
+                    for (int c = 0; c < N0.nk; c++) ln.var(N0.kslot[c]) = N0.kcol[c][row];
+                    ok = probe_node(N0, ln, m, status);
+                }
+            }
+            if (Q.nexec == 1) {
+                if (ok) dfs<1>(Q, ln, m, total, status);
+                continue;
+            }
+            uint32_t base = 0, lim = 0;
+            if (ok) {
+                const BNode &N1 = Q.node[1];
+                base = ln.hdl(N1.catom);
+                if (BCK(base < N1.npos)) lim = N1.len[base];
+            }
+            expand_node1(Q, ln, sc, base, lim, m, total, status);
         }
         // one atomic per work item
         for (int o = 32; o > 0; o >>= 1) total += __shfl_xor(total, o, 64);
@@ -156,11 +229,11 @@ __global__ void k_zero_u64(u64 *p, uint32_t n) {
 }
 
 hipError_t launch_batch_dfs(const BQuery *qs, const BItem *items, uint32_t nitems, u64 *counts, StatusDev *status,
-                            int block, int grid, hipStream_t s) {
+                            int block, int grid, int lv, int la, hipStream_t s) {
     if (nitems == 0) return hipSuccess;
-    if (block > 512) return hipErrorInvalidValue;   // LDS: 128 bytes per thread
-    const size_t lds = sizeof(uint32_t) * (size_t)(kBMaxVars + FJ_MAX_ATOMS) * block;
-    hipLaunchKernelGGL(k_batch_dfs, dim3(grid), dim3(block), lds, s, qs, items, nitems, counts, status);
+    if (block > 512 || lv < 1 || lv > kBMaxVars || la < 1 || la > FJ_MAX_ATOMS) return hipErrorInvalidValue;
+    const size_t lds = 2 * sizeof(uint32_t) * (size_t)(lv + la) * block;
+    hipLaunchKernelGGL(k_batch_dfs, dim3(grid), dim3(block), lds, s, qs, items, nitems, counts, status, lv, la);
     return hipGetLastError();
 }
 

@@ -156,6 +156,7 @@ struct BNode {
 struct BQuery {
     int nexec;                // nodes run tuple by tuple; the rest are products
     int ntail;
+    int nvars, natoms;
     uint32_t n0;              // rows of the first node's cover
     BNode node[kBMaxNodes];
     int tail_atom[kBMaxNodes];

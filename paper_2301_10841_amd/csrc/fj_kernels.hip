@@ -147,13 +147,10 @@ __device__ __forceinline__ u64 table_insert(const LevelDev &L, const int32_t *co
         }
         u64 i = bucket_start<Slot32>(mix32(key), mask);
         for (u64 n = 0; n <= mask; n++) {
-            uint32_t c = T[i].key;   // may be stale-empty; the CAS settles it
-            if (c == key) return i;
-            if (c == kEmpty32) {
-                uint32_t old = atomicCAS(&T[i].key, kEmpty32, key);
-                if (old == kEmpty32) { claimed = true; return i; }
-                if (old == key) return i;
-            }
+            // the compare-and-swap returns the occupant: no separate read
+            const uint32_t old = atomicCAS(&T[i].key, kEmpty32, key);
+            if (old == kEmpty32) { claimed = true; return i; }
+            if (old == key) return i;
             i = (i + 1) & mask;
         }
     } else if (L.mode == KM_K64) {
@@ -165,13 +162,9 @@ __device__ __forceinline__ u64 table_insert(const LevelDev &L, const int32_t *co
         }
         u64 i = bucket_start<Slot64>(mix64(key), mask);
         for (u64 n = 0; n <= mask; n++) {
-            u64 c = T[i].key;        // may be stale-empty; the CAS settles it
-            if (c == key) return i;
-            if (c == kEmpty64) {
-                u64 old = atomicCAS(&T[i].key, kEmpty64, key);
-                if (old == kEmpty64) { claimed = true; return i; }
-                if (old == key) return i;
-            }
+            const u64 old = atomicCAS(&T[i].key, kEmpty64, key);
+            if (old == kEmpty64) { claimed = true; return i; }
+            if (old == key) return i;
             i = (i + 1) & mask;
         }
     } else {
@@ -260,7 +253,8 @@ __global__ void k_fill_list(const FillList *__restrict__ fl, LevelDev root, uint
     const u64 tid = (u64)blockIdx.x * blockDim.x + threadIdx.x;
     for (int k = 0; k < fl->n; k++) {
         const FillRegion &r = fl->r[k];
-        for (u64 i = tid; i < r.nwords; i += stride) r.p[i] = r.pat[i % (u64)r.period];
+        const u64 m = (u64)r.period - 1;   // periods are 1, 2 or 4
+        for (u64 i = tid; i < r.nwords; i += stride) r.p[i] = r.pat[i & m];
     }
     if (tid == 0 && root.len) {
         root.len[0] = nroot;
@@ -562,13 +556,17 @@ __global__ void __launch_bounds__(256) k_group_force(const ForceArgs *__restrict
     else force_scatter_item(a, w);
 }
 
-// One block per FillBlock: a chunk of one region set to its periodic pattern.
+// One block per FillBlock: a chunk of one region set to its periodic
+// pattern (period 1, 2 or 4 words), in 16-byte stores from a 16-byte
+// aligned chunk start.
 __global__ void __launch_bounds__(256) k_group_fill(const FillBlock *__restrict__ fb) {
     const FillBlock &b = fb[blockIdx.x];
-    for (u64 i = threadIdx.x; i < b.n; i += 256) {
-        const u64 word = b.start + i;
-        b.p[word] = b.pat[word % (u64)b.period];
-    }
+    const u64 m = (u64)b.period - 1;
+    uint32_t *p = b.p + b.start;
+    const u64 n4 = b.n >> 2;
+    const uint4 v = make_uint4(b.pat[0], b.pat[1 & m], b.pat[2 & m], b.pat[3 & m]);
+    for (u64 i = threadIdx.x; i < n4; i += 256) ((uint4 *)p)[i] = v;
+    for (u64 i = (n4 << 2) + threadIdx.x; i < b.n; i += 256) p[i] = b.pat[(b.start + i) & m];
 }
 
 // Per COLT: the root handle spans every root row; a built root with no rows
@@ -817,6 +815,10 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
 #define FJ_SCAN_ROWS 1
 #endif
 constexpr int kScanRows = FJ_SCAN_ROWS;
+#ifndef FJ_SCAN_SPEC
+#define FJ_SCAN_SPEC 1
+#endif
+constexpr int kScanSpec = FJ_SCAN_SPEC;   // lookups whose bucket loads are in flight together
 constexpr int kScanMaxLookups = 8;
 
 // Streaming loads of cover columns (read once).
@@ -965,6 +967,59 @@ __device__ __forceinline__ void scan_round(const ScanArgs &a, const ScanLookup &
     }
 }
 
+// One row, one lookup, in two steps: issue() computes the bucket and starts
+// its load; resolve() scans it (and walks on in the rare full bucket).  A
+// thread issues the loads of two lookups before resolving the first, since
+// a bucket's address depends only on the row's key columns.
+struct RowProbe {
+    Bucket bk;
+    u64 idx;
+    u64 key;     // K32: the 32-bit key; K64: the packed pair
+    bool empty;  // the key equals the empty marker (reserved slot)
+};
+
+__device__ __forceinline__ void probe_issue(const ScanLookup &L, uint32_t k0, uint32_t k1, bool alive,
+                                            RowProbe &rp) {
+#pragma unroll
+    for (int q = 0; q < kBucketVec; q++) rp.bk.q[q] = make_uint4(0, 0, 0, 0);
+    if (L.mode == KM_K32) {
+        rp.key = k0;
+        rp.empty = k0 == kEmpty32;
+        rp.idx = bucket_start<Slot32>(mix32(k0), L.mask);
+        if (alive && !rp.empty) load_bucket(L.table, rp.idx * sizeof(Slot32), rp.bk);
+    } else {
+        rp.key = ((u64)k0 << 32) | k1;
+        rp.empty = rp.key == kEmpty64;
+        rp.idx = bucket_start<Slot64>(mix64(rp.key), L.mask);
+        if (alive && !rp.empty) load_bucket(L.table, rp.idx * sizeof(Slot64), rp.bk);
+    }
+}
+
+__device__ __forceinline__ bool probe_resolve(const ScanLookup &L, RowProbe &rp, uint32_t &val) {
+    if (L.mode == KM_K32) {
+        const Slot32 *T = (const Slot32 *)L.table;
+        if (rp.empty) { const Slot32 rs = T[L.mask + 1]; val = rs.val; return rs.key != 0; }
+        constexpr u64 B = kBucketBytes / sizeof(Slot32);
+        int st = scan_bucket32(rp.bk, (uint32_t)rp.key, val);
+        for (u64 n = B; st == 0 && n <= L.mask; n += B) {
+            rp.idx = (rp.idx + B) & L.mask;
+            load_bucket(T, rp.idx * sizeof(Slot32), rp.bk);
+            st = scan_bucket32(rp.bk, (uint32_t)rp.key, val);
+        }
+        return st == 1;
+    }
+    const Slot64 *T = (const Slot64 *)L.table;
+    if (rp.empty) { const Slot64 rs = T[L.mask + 1]; val = rs.val; return rs.key != 0; }
+    constexpr u64 B = kBucketBytes / sizeof(Slot64);
+    int st = scan_bucket64(rp.bk, rp.key, val);
+    for (u64 n = B; st == 0 && n <= L.mask; n += B) {
+        rp.idx = (rp.idx + B) & L.mask;
+        load_bucket(T, rp.idx * sizeof(Slot64), rp.bk);
+        st = scan_bucket64(rp.bk, rp.key, val);
+    }
+    return st == 1;
+}
+
 template <bool STATS>
 __global__ void __launch_bounds__(256) k_scan_probe(ScanArgs a) {
     StatusDev *status = a.status;
@@ -989,8 +1044,46 @@ __global__ void __launch_bounds__(256) k_scan_probe(ScanArgs a) {
     }
 #pragma unroll
     for (int r = 0; r < kScanRows; r++) alive[r] = alive[r] && CK(row[r] < a.nrows);
+    if constexpr (kScanRows == 1) {
+        // every lookup's key columns first (independent loads), then the
+        // lookups in order, kScanSpec bucket loads in flight at a time
+        uint32_t k0[kScanMaxLookups], k1[kScanMaxLookups];
+#pragma unroll
+        for (int j = 0; j < kScanMaxLookups; j++) {
+            k0[j] = 0;
+            k1[j] = 0;
+            if (j < a.nl && alive[0]) {
+                const ScanLookup &L = a.lk[j];
+                k0[j] = (uint32_t)a.cols[L.kc[0]][row[0]];
+                if (L.mode != KM_K32) k1[j] = (uint32_t)a.cols[L.kc[1]][row[0]];
+            }
+        }
+#pragma unroll
+        for (int j0 = 0; j0 < kScanMaxLookups; j0 += kScanSpec) {
+            if (j0 >= a.nl || !__any(alive[0])) break;
+            const bool two = kScanSpec == 2 && j0 + 1 < a.nl;
+            RowProbe p0, p1;
+            probe_issue(a.lk[j0], k0[j0], k1[j0], alive[0], p0);
+            if (two) probe_issue(a.lk[j0 + 1], k0[j0 + 1], k1[j0 + 1], alive[0], p1);
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const int j = j0 + h;
+                if (h == 1 && !two) break;
+                const ScanLookup &L = a.lk[j];
+                if (!alive[0]) continue;
+                if (STATS) nprobe++;
+                uint32_t v = 0;
+                alive[0] = probe_resolve(L, h == 0 ? p0 : p1, v);
+                if (!alive[0]) continue;
+                if (!CK(v < L.cnpos)) { alive[0] = false; continue; }
+                if (STATS) nhit++;
+                hs[j][threadIdx.x] = v;
+                if (L.child_leaf) mult[0] *= L.clen[v];
+            }
+        }
+    }
     // trie by trie over this thread's rows (Section 4.3's vectorized order)
-    for (int j = 0; j < a.nl; j++) {
+    for (int j = 0; j < a.nl && kScanRows > 1; j++) {
         const ScanLookup &L = a.lk[j];
         uint32_t val[kScanRows];
         if (STATS) {

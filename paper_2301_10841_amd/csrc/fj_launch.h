@@ -69,7 +69,7 @@ struct ScanLaunch {
 hipError_t launch_scan_probe(const ScanLaunch &l, hipStream_t s);
 int scan_max_lookups();
 hipError_t launch_batch_dfs(const BQuery *qs, const BItem *items, uint32_t nitems, unsigned long long *counts,
-                            StatusDev *status, int block, int grid, hipStream_t s);
+                            StatusDev *status, int block, int grid, int lv, int la, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, uint32_t n, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, unsigned long long n, uint32_t v, hipStream_t s);
 hipError_t launch_table_init(void *table, unsigned long long nslots, int mode, hipStream_t s);
