@@ -105,6 +105,7 @@ struct fj_ctx {
     DevBuf scanb;                   // block sums for scans
     DevBuf desc;                    // node + emit descriptors
     DevBuf emitbuf;                 // emit counts and starts
+    DevBuf chunkb;                  // per-block binding bounds of a probe launch
     DevBuf sketch;                  // column sketch table and results
     struct ColtGroup *group = nullptr;  // fj_colt_rebuild_many's descriptors and scratch
     unsigned long long *sketch_h = nullptr;  // pinned sketch results
@@ -657,6 +658,7 @@ void fj_ctx_destroy(fj_ctx *c) {
     c->scanb.release();
     c->desc.release();
     c->emitbuf.release();
+    c->chunkb.release();
     c->sketch.release();
     if (c->sketch_h) hipHostFree(c->sketch_h);
     destroy_group(c->group);
@@ -1102,6 +1104,12 @@ fj_status exec_node(Exec &x, int k, uint32_t E) {
         pl.dcap = (uint32_t)x.C;
         pl.surv_base = surv_base;
         pl.def_base = def_base;
+        {
+            const u64 need = (u64)n / 64 + 2;   // blocks of at least 64 threads, plus the sentinel
+            FJ_TRY(c->chunkb.ensure(need * sizeof(uint32_t), c->stream));
+            pl.chunk_buf = c->chunkb.as<uint32_t>();
+            pl.chunk_cap = c->chunkb.bytes / sizeof(uint32_t);
+        }
         {
             Timer t(c, k == 0 ? FJ_T_PROBE0 : FJ_T_PROBE);
             FJ_HIP(fj::launch_probe(pl, c->stream));

@@ -676,7 +676,19 @@ struct ProbeArgs {
     u64 def_base;
     StatusDev *status;
     int count_stats;
+    const uint32_t *chunk_e;  // per block: the binding of its first tuple (+1 sentinel), or null
 };
+
+// The binding of the first tuple of every block-sized chunk of a tile (and
+// of the tile's last tuple, as a sentinel), so that a probe thread searches
+// only between its block's two bounds instead of over every binding.
+__global__ void k_chunk_entries(const u64 *__restrict__ starts, uint32_t E, u64 t0, uint32_t n, uint32_t bs,
+                                uint32_t nchunks, uint32_t *out) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > nchunks) return;
+    const u64 off = std::min<u64>((u64)c * bs, (u64)n - 1);
+    out[c] = E == 1 ? 0u : upper_entry(starts, 0, E, t0 + off);
+}
 
 __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
     const NodeDev &nd = *a.nd;
@@ -694,8 +706,14 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
     if (ok) {
         if (a.din) { t = a.din[idx]; resume = a.din_j[idx]; } else { t = idx; }
         const u64 g = a.t0 + t;
-        e = a.E == 1 ? 0u : upper_entry(a.starts, 0, a.E, g);
-        ok = CK(e < a.E && e < nd.in.cap && g >= a.starts[e] && g < a.starts[e + 1]);
+        uint32_t lo = 0, hi = a.E;
+        if (!a.din && a.chunk_e) {
+            lo = a.chunk_e[blockIdx.x];
+            hi = a.chunk_e[blockIdx.x + 1] + 1;
+            ok = CK(lo < hi && hi <= a.E);
+        }
+        e = (!ok || a.E == 1) ? 0u : upper_entry(a.starts, lo, hi, g);
+        ok = ok && CK(e < a.E && e < nd.in.cap && g >= a.starts[e] && g < a.starts[e + 1]);
     }
     if (ok) {
         const u64 i = a.t0 + t - a.starts[e];
@@ -1345,9 +1363,16 @@ hipError_t launch_probe(const ProbeLaunch &p, hipStream_t s) {
     a.din = p.din; a.din_j = p.din_j; a.dout = p.dout; a.dout_j = p.dout_j;
     a.status = p.status; a.count_stats = p.count_stats; a.dcap = p.dcap;
     a.surv_base = p.surv_base; a.def_base = p.def_base;
+    a.chunk_e = nullptr;
     if (p.n == 0) return hipSuccess;
     int bs = p.block > 0 ? p.block : 256;
-    hipLaunchKernelGGL(k_probe, dim3(blocks_for(p.n, bs)), dim3(bs), 0, s, a);
+    const uint32_t nb = blocks_for(p.n, bs);
+    if (!p.din && p.chunk_buf && p.chunk_cap >= (u64)nb + 1) {
+        hipLaunchKernelGGL(k_chunk_entries, dim3((nb + 1 + 255) / 256), dim3(256), 0, s, p.starts, p.E, p.t0, p.n,
+                           (uint32_t)bs, nb, p.chunk_buf);
+        a.chunk_e = p.chunk_buf;
+    }
+    hipLaunchKernelGGL(k_probe, dim3(nb), dim3(bs), 0, s, a);
     return hipGetLastError();
 }
 

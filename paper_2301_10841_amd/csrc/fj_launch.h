@@ -40,6 +40,8 @@ struct ProbeLaunch {
     int block;
     uint32_t dcap;         // capacity of the deferral lists
     unsigned long long surv_base, def_base;  // counter values before the launch
+    uint32_t *chunk_buf;   // scratch for the per-block binding bounds (chunk_cap entries), or null
+    unsigned long long chunk_cap;
 };
 
 struct ScanLaunch {
