@@ -248,6 +248,9 @@ fj_status colt_allocate(fj_colt *t) {
         if (l > 0) FJ_TRY(colt_alloc(t, &L.offs, n));
         FJ_TRY(colt_alloc(t, &L.len, n));
         if (leaf) continue;
+        // a level below the root keyed by one variable keeps that key beside
+        // each offset (written when its parent is forced)
+        if (l > 0 && t->lev_nk[l] == 1) FJ_TRY(colt_alloc(t, &L.kv, n));
         FJ_TRY(colt_alloc(t, &L.st, n));
         if (l == 0 && !t->root_built && t->nlev == 1) {
             // a base table iterated directly is never forced: no map, no scratch
@@ -256,6 +259,11 @@ fj_status colt_allocate(fj_colt *t) {
             continue;
         }
         FJ_TRY(colt_alloc(t, &L.kl, n));
+        if (t->lev_nk[l] == 1) {
+            // forced handles list their keys and each key's offset count
+            FJ_TRY(colt_alloc(t, &L.kk, n));
+            FJ_TRY(colt_alloc(t, &L.kn, n));
+        }
         FJ_TRY(colt_alloc(t, &L.rank_ctr, n));
         FJ_TRY(colt_alloc(t, &L.cnt, n));
         FJ_TRY(colt_alloc(t, &L.fq, n));
@@ -1506,6 +1514,7 @@ fj_status batch_query(const fj_query *q, const fj_plan *p, fj_colt *const *colts
                 return fail(FJ_ERR_UNSUPPORTED, "batched plans iterate the last level reached by a probe");
             N.offs = ct->lev[cl].offs;
             N.len = ct->lev[cl].len;
+            N.kv = node[ci].nv == 1 ? ct->lev[cl].kv : nullptr;
         }
         N.npos = ct->lev[cl].npos;
         N.nrows = (uint32_t)ct->nrows;

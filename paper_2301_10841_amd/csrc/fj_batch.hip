@@ -41,7 +41,9 @@ struct Lane {
     __device__ __forceinline__ uint32_t &hdl(int a) const { return h[a * blockDim.x + threadIdx.x]; }
 };
 
-__device__ __forceinline__ uint32_t root_get(const BLookup &L, const Lane &ln) {
+// get() on a root map: the child start (and, for 16-byte slots, the child's
+// length in *clen), or ~0u.
+__device__ __forceinline__ uint32_t root_get(const BLookup &L, const Lane &ln, uint32_t *clen) {
     if (L.mode == KM_K32) {
         const Slot32 *T = (const Slot32 *)L.table;
         const uint32_t key = (uint32_t)ln.var(L.kslot[0]);
@@ -56,11 +58,14 @@ __device__ __forceinline__ uint32_t root_get(const BLookup &L, const Lane &ln) {
     } else {
         const Slot64 *T = (const Slot64 *)L.table;
         const u64 key = ((u64)(uint32_t)ln.var(L.kslot[0]) << 32) | (uint32_t)ln.var(L.kslot[1]);
-        if (key == kEmpty64) return T[L.mask + 1].key ? T[L.mask + 1].val : ~0u;
+        if (key == kEmpty64) {
+            *clen = T[L.mask + 1].pad;
+            return T[L.mask + 1].key ? T[L.mask + 1].val : ~0u;
+        }
         u64 i = (bmix64(key) & L.mask) & ~1ull;   // 2 slots of 16 bytes
         for (u64 n = 0; n <= L.mask; n++) {
             const Slot64 sl = T[i];
-            if (sl.key == key) return sl.val;
+            if (sl.key == key) { *clen = sl.pad; return sl.val; }
             if (sl.key == kEmpty64) return ~0u;
             i = (i + 1) & L.mask;
         }
@@ -72,10 +77,11 @@ __device__ __forceinline__ uint32_t root_get(const BLookup &L, const Lane &ln) {
 __device__ __forceinline__ bool probe_node(const BNode &N, const Lane &ln, u64 &mult, StatusDev *status) {
     for (int j = 0; j < N.nl; j++) {
         const BLookup &L = N.lk[j];
-        const uint32_t s = root_get(L, ln);
+        uint32_t clen = 0;
+        const uint32_t s = root_get(L, ln, &clen);
         if (s == ~0u) return false;
         if (!BCK(s < L.cnpos)) return false;
-        if (L.child_leaf) mult *= L.clen[s];
+        if (L.child_leaf) mult *= L.mode == KM_K64 ? clen : L.clen[s];
         else ln.hdl(L.atom) = s;
     }
     return true;
@@ -108,9 +114,13 @@ __device__ __forceinline__ void dfs(const BQuery &Q, const Lane &ln, u64 mult, u
         for (uint32_t pos = 0; pos < lim; pos++) {
             const uint32_t p = base + pos;
             if (!BCK(p < N.npos)) return;
-            const uint32_t rw = N.offs[p];
-            if (!BCK(rw < N.nrows)) return;
-            for (int c = 0; c < N.nk; c++) ln.var(N.kslot[c]) = N.kcol[c][rw];
+            if (N.kv) {
+                ln.var(N.kslot[0]) = N.kv[p];
+            } else {
+                const uint32_t rw = N.offs[p];
+                if (!BCK(rw < N.nrows)) return;
+                for (int c = 0; c < N.nk; c++) ln.var(N.kslot[c]) = N.kcol[c][rw];
+            }
             u64 mm = mult;
             if (!probe_node(N, ln, mm, status)) continue;
             dfs<K + 1>(Q, ln, mm, total, status);
@@ -158,9 +168,13 @@ __device__ __forceinline__ void expand_node1(const BQuery &Q, const Lane &ln, co
         __builtin_amdgcn_wave_barrier();
         const uint32_t p = baseo + pos;
         if (!BCK(pos < limo && p < N.npos)) continue;
-        const uint32_t rw = N.offs[p];
-        if (!BCK(rw < N.nrows)) continue;
-        for (int c = 0; c < N.nk; c++) sc.var(N.kslot[c]) = N.kcol[c][rw];
+        if (N.kv) {
+            sc.var(N.kslot[0]) = N.kv[p];
+        } else {
+            const uint32_t rw = N.offs[p];
+            if (!BCK(rw < N.nrows)) continue;
+            for (int c = 0; c < N.nk; c++) sc.var(N.kslot[c]) = N.kcol[c][rw];
+        }
         u64 mm = mo;
         if (!probe_node(N, sc, mm, status)) continue;
         dfs<2>(Q, sc, mm, total, status);

@@ -45,6 +45,10 @@ struct LevelDev {
     uint32_t *rank_ctr;  // per handle: distinct keys seen while forcing
     uint32_t *cnt;       // per child rank position: offsets while forcing (returns to 0)
     uint32_t *fq;        // force queue: handle starts
+    // Keys kept beside the offsets (levels keyed by one variable only):
+    int32_t *kv;         // kv[p]: the level's key value of the row at offs[p] (below the root)
+    int32_t *kk;         // kk[p + r]: the key of rank r of the forced handle at p
+    uint32_t *kn;        // kn[p + r]: the number of offsets under that key
     int mode;
     int nk;
     int kcol[FJ_MAX_COLS];
@@ -146,6 +150,7 @@ struct BNode {
     int kslot[FJ_MAX_COLS];   // variables the cover binds
     const int32_t *kcol[FJ_MAX_COLS];  // their columns
     const uint32_t *offs;     // offsets of the cover's level (node 0: selection or null)
+    const int32_t *kv;        // the cover's key values beside its offsets (one key variable), or null
     const uint32_t *len;      // lengths of the cover's level (unused at node 0)
     uint32_t npos;
     uint32_t nrows;

@@ -495,9 +495,16 @@ __device__ __forceinline__ void force_children_item(const ForceArgs &a, uint32_t
     const uint32_t cnt = (uint32_t)a.cntv[w];
     if (!CK((u64)p + rank < a.L.npos && s < a.C.npos && cnt > 0)) return;
     a.L.kl[p + rank] = s;
+    if (a.L.kk) {
+        a.L.kk[p + rank] = a.cols[a.L.kcol[0]][row];
+        a.L.kn[p + rank] = cnt;
+    }
     a.C.len[s] = cnt;
     a.L.cnt[s] = cnt;
     if (a.L.mode != KM_ZERO) *slot_val_ptr(a.L, ws & ~kClaim) = s;
+    // 16-byte slots also carry the child's length: a lookup that reaches an
+    // offset vector reads its multiplicity from the slot it found
+    if (a.L.mode == KM_K64) ((Slot64 *)a.L.table)[ws & ~kClaim].pad = cnt;
 }
 
 __global__ void __launch_bounds__(256) k_force_children(ForceArgs a) {
@@ -517,6 +524,7 @@ __device__ __forceinline__ void force_scatter_item(const ForceArgs &a, uint32_t 
     const uint32_t pos = s + atomicSub(&a.L.cnt[s], 1u) - 1u;
     if (!CK(pos >= s && pos < p + a.L.len[p])) return;
     a.C.offs[pos] = row;
+    if (a.C.kv) a.C.kv[pos] = a.cols[a.C.kcol[0]][row];
 }
 
 __global__ void __launch_bounds__(256) k_force_scatter(ForceArgs a) {
@@ -730,20 +738,31 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
             ok = CK(p + i < S.L.npos);
             const uint32_t s = ok ? S.L.kl[p + (uint32_t)i] : 0u;
             ok = ok && CK(s < S.C.npos);
-            const uint32_t row = ok ? S.C.offs[s] : 0u;
-            ok = ok && CK(row < S.L.nrows);
-            if (ok) {
-                for (int c = 0; c < S.nk; c++) v[S.kslot[c]] = S.cols[S.kcol[c]][row];
-                if (S.child_leaf) mult *= S.C.len[s];
+            if (ok && S.L.kk && S.nk == 1) {
+                // the key list holds the key and its offset count
+                v[S.kslot[0]] = S.L.kk[p + (uint32_t)i];
+                if (S.child_leaf) mult *= S.L.kn[p + (uint32_t)i];
                 else h[S.atom] = s;
+            } else {
+                const uint32_t row = ok ? S.C.offs[s] : 0u;
+                ok = ok && CK(row < S.L.nrows);
+                if (ok) {
+                    for (int c = 0; c < S.nk; c++) v[S.kslot[c]] = S.cols[S.kcol[c]][row];
+                    if (S.child_leaf) mult *= S.C.len[s];
+                    else h[S.atom] = s;
+                }
             }
         } else {
             const u64 pos = p + i;
             ok = CK(p < S.L.npos) && CK(pos < S.L.npos && i < trie_len(S, p));
-            const uint32_t row = ok ? (S.L.offs ? S.L.offs[pos] : (uint32_t)pos) : 0u;
-            ok = ok && CK(row < S.L.nrows);
-            if (ok)
-                for (int c = 0; c < S.nk; c++) v[S.kslot[c]] = S.cols[S.kcol[c]][row];
+            if (ok && S.L.kv && S.nk == 1) {
+                v[S.kslot[0]] = S.L.kv[pos];   // the key beside the offset
+            } else {
+                const uint32_t row = ok ? (S.L.offs ? S.L.offs[pos] : (uint32_t)pos) : 0u;
+                ok = ok && CK(row < S.L.nrows);
+                if (ok)
+                    for (int c = 0; c < S.nk; c++) v[S.kslot[c]] = S.cols[S.kcol[c]][row];
+            }
         }
         // lookups in node order
         survive = ok;
@@ -762,7 +781,8 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
                 defer = true; defer_j = j; survive = false;
                 break;
             }
-            uint32_t s;
+            uint32_t s, clen = 0;
+            bool have_len = false;
             if (j >= resume) nprobe++;
             if (P.L.mode == KM_ZERO) {
                 // a map with no variables has one key, or none when empty
@@ -776,10 +796,14 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
                 if (slot == ~0ull) { survive = false; break; }
                 if (!CK(slot < P.L.nslots)) { survive = false; break; }
                 s = slot_val(P.L, slot);
+                if (P.L.mode == KM_K64) {
+                    clen = ((const Slot64 *)P.L.table)[slot].pad;   // the line just read
+                    have_len = true;
+                }
             }
             if (!CK(s < P.C.npos)) { survive = false; break; }
             if (j >= resume) nhit++;
-            if (P.child_leaf) mult *= P.C.len[s];
+            if (P.child_leaf) mult *= have_len ? clen : P.C.len[s];
             else h[P.atom] = s;
         }
         if (survive && nd.emit) {
