@@ -1446,7 +1446,9 @@ extern "C" fj_status fj_execute(fj_ctx *c, const fj_query *q, const fj_plan *p, 
     }
     if (st != FJ_OK) return st;
     FJ_TRY(sync_status(c));
-    *count = c->status_h->count;
+    u64 total = c->status_h->count;
+    for (int q = 0; q < fj::kCountParts; q++) total += c->status_h->count_part[q * fj::kPartStride];
+    *count = total;
     if (written) *written = x.written;
     if (stats) {
         for (int k = 0; k < x.tail_from; k++) {

@@ -220,6 +220,12 @@ struct GroupRoot {
     int built;
 };
 
+// Result counts are added to kCountParts partial counters, each on its own
+// 128-byte line, so that many workgroups adding at once do not queue on one
+// address; the host sums them.
+constexpr int kCountParts = 16;
+constexpr int kPartStride = 16;   // 64-bit words between partial counters
+
 // Host <-> device status block, one per context.
 struct StatusDev {
     unsigned long long count;      // result tuples so far
@@ -232,6 +238,7 @@ struct StatusDev {
     uint32_t pending;              // entries whose cover had to be forced first
     uint32_t total32;              // 32-bit scan totals
     uint32_t ftotal[FJ_MAX_ATOMS];  // counts of a batch of selections
+    alignas(128) unsigned long long count_part[kCountParts * kPartStride];  // more result tuples
     uint32_t err_line;             // first failed device bounds check (source line)
     uint32_t err_count;            // failed device bounds checks
 };

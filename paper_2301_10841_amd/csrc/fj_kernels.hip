@@ -193,6 +193,42 @@ __device__ __forceinline__ u64 wave_sum_u64(u64 v) {
 }
 
 // Wave-aggregated reservation: returns this lane's slot for `pred` lanes.
+// Block-wide forms (every thread of the block calls them; blocks of at most
+// 1024 threads; lds holds 17 words): one atomic per block instead of one per
+// wave.
+__device__ __forceinline__ void block_add_count(u64 v, StatusDev *st, u64 *lds) {
+    v = wave_sum_u64(v);
+    const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (__lane_id() == 0) lds[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u64 t = 0;
+        for (int w = 0; w < nw; w++) t += lds[w];
+        if (t) atomicAdd(&st->count_part[(blockIdx.x % kCountParts) * kPartStride], t);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ u64 block_reserve(bool pred, u64 *counter, u64 *lds) {
+    const u64 mask = __ballot(pred);
+    const int lane = __lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane == 0) lds[wid] = (u64)__popcll(mask);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u64 off = 0;
+        for (int w = 0; w < nw; w++) {
+            const u64 t = lds[w];
+            lds[w] = off;
+            off += t;
+        }
+        lds[16] = off ? atomicAdd(counter, off) : 0ull;
+    }
+    __syncthreads();
+    const u64 base = lds[16] + lds[wid] + (u64)__popcll(mask & ((1ull << lane) - 1ull));
+    __syncthreads();
+    return base;
+}
+
 __device__ __forceinline__ u64 wave_reserve(bool pred, u64 *counter) {
     const u64 mask = __ballot(pred);
     const int lane = __lane_id();
@@ -699,6 +735,7 @@ __global__ void k_chunk_entries(const u64 *__restrict__ starts, uint32_t E, u64 
 }
 
 __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
+    __shared__ u64 red[17];
     const NodeDev &nd = *a.nd;
     StatusDev *status = a.status;
     const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -824,19 +861,17 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
             atomicAdd(&a.status->hit[nd.k], nh);
         }
     }
-    if (nd.emit) {
-        u64 c = wave_sum_u64(emitv);
-        if (__lane_id() == 0 && c) atomicAdd(&a.status->count, c);
-    }
+    if (nd.emit) block_add_count(emitv, status, red);
     // deferred tuples
     // the counters only grow; this launch's entries start at its base
-    {
-        u64 pos = wave_reserve(defer, &a.status->deferred) - a.def_base;
+    if (__syncthreads_or(defer)) {
+        u64 pos = block_reserve(defer, &a.status->deferred, red) - a.def_base;
         if (defer && CK(pos < a.dcap)) { a.dout[pos] = t; a.dout_j[pos] = (uint8_t)defer_j; }
     }
     // survivors to the output frontier
     const bool write = survive && (!nd.emit || nd.materialize);
-    u64 pos = wave_reserve(write, &a.status->survivors) - a.surv_base;
+    if (!__syncthreads_or(write)) return;
+    u64 pos = block_reserve(write, &a.status->survivors, red) - a.surv_base;
     if (write && CK(pos < nd.out.cap)) {
         const FrontierDev &O = nd.out;
         for (int j = 0; j < nd.nout; j++) O.vals[(u64)j * O.cap + pos] = v[nd.out_slot[j]];
@@ -1168,8 +1203,12 @@ __global__ void __launch_bounds__(256) k_scan_probe(ScanArgs a) {
             }
             tot += e;
         }
+        // one atomic per wave, spread over the partial counters
         tot = wave_sum_u64(tot);
-        if (__lane_id() == 0 && tot) atomicAdd(&a.status->count, tot);
+        if (__lane_id() == 0 && tot)
+            atomicAdd(&status->count_part[((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % kCountParts) *
+                                          kPartStride],
+                      tot);
     }
     if (!a.emit || a.materialize) {
 #pragma unroll
