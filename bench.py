@@ -50,6 +50,8 @@ def main():
     ap.add_argument("--cycle4-scale", type=int, default=16, help="rmat workload: scale of the 4-cycle run")
     ap.add_argument("--queries", type=int, default=256, help="batch workload: number of queries")
     ap.add_argument("--tune-queries", type=int, default=48, help="batch workload: calibration batch size")
+    ap.add_argument("--chooser-queries", type=int, default=48,
+                    help="star workload: held-out queries for the learned-vs-plain leg (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -168,14 +170,39 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes,
                      "traffic_note": traffic_note,
                      "kernel": "k_scan_probe (node 0)", "avg_launch_ms": avg_probe0_ms,
-                     "alg_bytes_per_launch": alg_bytes},
+                     "alg_bytes_per_launch": alg_bytes,
+                     "useful_byte_efficiency": alg_bytes / traffic_bytes if traffic_bytes else None,
+                     "l2_hit_rate": tr["tcc_hit_rate"] if tr else None},
         "phases": phases,
         "cpu_baseline": cpu,
     }
     for c in colts:
         c.free()
+    if args.chooser_queries > 0:
+        res["learned_vs_plain"] = chooser_leg(ctx, args.chooser_queries)
     ctx.close()
     print(json.dumps(res), flush=True)
+
+
+def chooser_leg(ctx, n):
+    """Learned vs plain plan time on n held-out queries of the batched
+    generator (a seed disjoint from the chooser's training and held-out
+    sets): every candidate timed (root builds + join, median of 5) and both
+    choices' overheads timed live; end-to-end = choice + chosen plan."""
+    import datagen
+    from paper_2301_10841_amd import learn
+    t0 = time.time()
+    m, info = learn.load(ctx)
+    rows = learn.evaluate(ctx, m, learn.QuerySupply(0), datagen.seed_for(5, 3), n, reps=5)
+    s = learn.summarize(rows)
+    m.free()
+    log(f"chooser leg: {n} queries in {time.time() - t0:.1f}s")
+    return {"queries": n, "learned_over_plain_total": s["learned_over_plain_total"],
+            "learned_over_plain_geomean": s["learned_over_plain_geomean"],
+            "learned_mean_regret": s["learned_mean_regret_vs_best"],
+            "plain_mean_regret": s["plain_mean_regret_vs_best"],
+            "choose_learned_ms": s["choose_learned_ms_mean"], "choose_plain_ms": s["choose_plain_ms_mean"],
+            "weights": "paper_2301_10841_amd/weights/chooser.npz"}
 
 
 def sampled_triangles(src, dst, xs):

@@ -462,17 +462,58 @@ __global__ void __launch_bounds__(256) k_fq_lens(LevelDev L, const uint32_t *fq,
 
 // Pass 1: insert each offset's key (handle, key values) and count the
 // offsets per key in the slot's value word; the inserting item is marked.
+// Called by every active lane of a wave (wave-wide rounds below).
 __device__ __forceinline__ void force_insert_item(const ForceArgs &a, uint32_t w) {
     StatusDev *status = a.status;
     uint32_t j, p, i, row;
-    if (!force_item(a, w, j, p, i, row)) { a.wslot[w] = 0; return; }
-    if (a.L.mode == KM_ZERO) {             // one key: the first offset claims it
+    bool todo = force_item(a, w, j, p, i, row);
+    if (!todo) a.wslot[w] = 0;
+    if (todo && a.L.mode == KM_ZERO) {     // one key: the first offset claims it
         a.wslot[w] = i == 0 ? kClaim : 0u;
-        return;
+        todo = false;
     }
     Key k;
     k.h = p;
-    for (int c = 0; c < a.L.nk; c++) k.v[c] = a.cols[a.L.kcol[c]][row];
+    k.v[0] = k.v[1] = 0;
+    if (todo)
+        for (int c = 0; c < a.L.nk; c++) k.v[c] = a.cols[a.L.kcol[c]][row];
+    // Up to two rounds: the lanes holding the same key (same map, handle and
+    // key of at most two columns) as the wave's first remaining lane insert
+    // it once and add their number at once, which keeps a heavy key under
+    // skew from serializing many atomics on one slot.
+    const int lane = __lane_id();
+    for (int round = 0; round < 2; round++) {
+        const u64 act = __ballot(todo);
+        if (act == 0) break;
+        const int leader = __ffsll((long long)act) - 1;
+        const u64 tb = (u64)(uintptr_t)a.L.table;
+        const u64 ltb = __shfl(tb, leader, 64);
+        const uint32_t lh = __shfl(k.h, leader, 64);
+        const int32_t l0 = __shfl(k.v[0], leader, 64), l1 = __shfl(k.v[1], leader, 64);
+        const bool same = todo && a.L.mode != KM_REP && tb == ltb && k.h == lh && k.v[0] == l0 &&
+                          (a.L.nk < 2 || k.v[1] == l1);
+        const u64 grp = __ballot(same);
+        const int m = __popcll(grp);
+        if (m < 2) break;
+        uint32_t ws = 0;
+        int good = 0;
+        if (lane == leader) {
+            bool claimed;
+            const u64 sl = table_insert(a.L, a.cols, k, row, claimed);
+            if (CK(sl < a.L.nslots && sl < kClaim)) {
+                atomicAdd(slot_val_ptr(a.L, sl), (uint32_t)(claimed ? m - 1 : m));
+                ws = (uint32_t)sl | (claimed ? kClaim : 0u);
+                good = 1;
+            }
+        }
+        ws = __shfl(ws, leader, 64);
+        good = __shfl(good, leader, 64);
+        if (same) {
+            a.wslot[w] = !good ? 0u : (lane == leader ? ws : (ws & ~kClaim));
+            todo = false;
+        }
+    }
+    if (!todo) return;
     bool claimed;
     const u64 sl = table_insert(a.L, a.cols, k, row, claimed);
     if (!CK(sl < a.L.nslots && sl < kClaim)) { a.wslot[w] = 0; return; }
@@ -550,13 +591,46 @@ __global__ void __launch_bounds__(256) k_force_children(ForceArgs a) {
 
 // Pass 4: every offset moves into its key's child segment.  The cursor
 // counts down to zero, leaving the counter array clean for the next force.
+// Called by every active lane of a wave (wave-wide rounds below).
 __device__ __forceinline__ void force_scatter_item(const ForceArgs &a, uint32_t w) {
     StatusDev *status = a.status;
     uint32_t j, p, i, row;
-    if (!force_item(a, w, j, p, i, row)) return;
-    const uint32_t ws = a.wslot[w];
-    const uint32_t s = a.L.mode == KM_ZERO ? p : *slot_val_ptr(a.L, ws & ~kClaim);
-    if (!CK(s >= p && s < a.C.npos)) return;
+    bool todo = force_item(a, w, j, p, i, row);
+    uint32_t s = 0;
+    if (todo) {
+        const uint32_t ws = a.wslot[w];
+        s = a.L.mode == KM_ZERO ? p : *slot_val_ptr(a.L, ws & ~kClaim);
+        todo = CK(s >= p && s < a.C.npos);
+    }
+    // Up to two rounds: the lanes moving into the same child segment as the
+    // wave's first remaining lane take consecutive positions with one
+    // subtraction from its cursor.
+    const int lane = __lane_id();
+    for (int round = 0; round < 2; round++) {
+        const u64 act = __ballot(todo);
+        if (act == 0) break;
+        const int leader = __ffsll((long long)act) - 1;
+        const u64 cp = (u64)(uintptr_t)a.L.cnt;
+        const u64 lcp = __shfl(cp, leader, 64);
+        const uint32_t ls = __shfl(s, leader, 64);
+        const bool same = todo && cp == lcp && s == ls;
+        const u64 grp = __ballot(same);
+        const int m = __popcll(grp);
+        if (m < 2) break;
+        uint32_t old = 0;
+        if (lane == leader) old = atomicSub(&a.L.cnt[s], (uint32_t)m);
+        old = __shfl(old, leader, 64);
+        if (same) {
+            todo = false;
+            const uint32_t r = (uint32_t)__popcll(grp & ((1ull << lane) - 1ull));
+            const uint32_t pos = s + old - 1u - r;
+            if (CK(old >= (uint32_t)m && pos >= s && pos < p + a.L.len[p])) {
+                a.C.offs[pos] = row;
+                if (a.C.kv) a.C.kv[pos] = a.cols[a.C.kcol[0]][row];
+            }
+        }
+    }
+    if (!todo) return;
     const uint32_t pos = s + atomicSub(&a.L.cnt[s], 1u) - 1u;
     if (!CK(pos >= s && pos < p + a.L.len[p])) return;
     a.C.offs[pos] = row;
@@ -586,18 +660,33 @@ __device__ __forceinline__ int group_member(const u64 *__restrict__ wpre, int n,
 }
 
 template <int PHASE>
-__global__ void __launch_bounds__(256) k_group_force(const ForceArgs *__restrict__ descs, const u64 *__restrict__ wpre,
-                                                     int n, u64 wtot) {
-    const u64 g = (u64)blockIdx.x * 256 + threadIdx.x;
-    if (g >= wtot) return;
-    const int k = group_member(wpre, n, g);
-    const ForceArgs &a = descs[k];
-    const uint32_t w = (uint32_t)(g - wpre[k]);
-    if (w >= a.W) return;
+__device__ __forceinline__ void group_item(const ForceArgs &a, uint32_t w) {
     if (PHASE == 0) force_insert_item(a, w);
     else if (PHASE == 1) force_pack_item(a, w);
     else if (PHASE == 2) force_children_item(a, w);
     else force_scatter_item(a, w);
+}
+
+template <int PHASE>
+__global__ void __launch_bounds__(256) k_group_force(const ForceArgs *__restrict__ descs, const u64 *__restrict__ wpre,
+                                                     int n, u64 wtot) {
+    // the block's first member by one search; lanes step on at boundaries
+    const u64 gb = (u64)blockIdx.x * 256;
+    if (gb >= wtot) return;
+    const int kb = group_member(wpre, n, gb);
+    const u64 g = gb + threadIdx.x;
+    if (g >= wtot) return;
+    int k = kb;
+    while (k + 1 < n && wpre[k + 1] <= g) k++;
+    const uint32_t w = (uint32_t)(g - wpre[k]);
+    if (__all(k == kb)) {
+        // the whole wave works for one member: its descriptor at a uniform address
+        const ForceArgs &a = descs[kb];
+        if (w < a.W) group_item<PHASE>(a, w);
+    } else {
+        const ForceArgs &a = descs[k];
+        if (w < a.W) group_item<PHASE>(a, w);
+    }
 }
 
 // One block per FillBlock: a chunk of one region set to its periodic
