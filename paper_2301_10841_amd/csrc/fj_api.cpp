@@ -111,6 +111,7 @@ struct fj_ctx {
     unsigned long long *sketch_h = nullptr;  // pinned sketch results
     void *desc_h = nullptr;         // pinned staging for descriptors
     size_t desc_h_bytes = 0;
+    hipEvent_t desc_done = nullptr; // the last copy out of desc_h has finished
     // timing
     struct Pending { int cls; hipEvent_t a, b; };
     std::vector<hipEvent_t> pool;
@@ -671,6 +672,7 @@ void fj_ctx_destroy(fj_ctx *c) {
     if (c->sketch_h) hipHostFree(c->sketch_h);
     destroy_group(c->group);
     if (c->desc_h) hipHostFree(c->desc_h);
+    if (c->desc_done) hipEventDestroy(c->desc_done);
     for (auto &p : c->pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
     for (auto e : c->pool) hipEventDestroy(e);
     if (c->status_d) hipFree(c->status_d);
@@ -1355,17 +1357,20 @@ extern "C" fj_status fj_execute(fj_ctx *c, const fj_query *q, const fj_plan *p, 
     size_t nd_bytes = align256(sizeof(NodeDev) * std::max(x.tail_from, 1));
     size_t em_bytes = align256(fj::emit_dev_size());
     FJ_TRY(c->desc.ensure(nd_bytes + em_bytes, c->stream));
-    if (c->desc_h_bytes < std::max(nd_bytes, em_bytes)) {
-        FJ_HIP(hipStreamSynchronize(c->stream));
+    // the staging buffer mirrors the device layout (node descriptors, then
+    // the emit descriptor) and goes over in one copy; only that copy of the
+    // previous call must have finished before it is rewritten
+    if (!c->desc_done) FJ_HIP(hipEventCreateWithFlags(&c->desc_done, hipEventDisableTiming));
+    else FJ_HIP(hipEventSynchronize(c->desc_done));
+    if (c->desc_h_bytes < nd_bytes + em_bytes) {
         if (c->desc_h) hipHostFree(c->desc_h);
         c->desc_h = nullptr;
         c->desc_h_bytes = 0;
-        FJ_HIP(hipHostMalloc(&c->desc_h, std::max(nd_bytes, em_bytes), hipHostMallocDefault));
-        c->desc_h_bytes = std::max(nd_bytes, em_bytes);
+        FJ_HIP(hipHostMalloc(&c->desc_h, nd_bytes + em_bytes, hipHostMallocDefault));
+        c->desc_h_bytes = nd_bytes + em_bytes;
     }
     x.nd_d = c->desc.as<NodeDev>(0);
     x.emit_d = c->desc.as<char>(nd_bytes);
-    FJ_HIP(hipStreamSynchronize(c->stream));  // desc_h may still feed an earlier copy
     NodeDev *ndh = (NodeDev *)c->desc_h;
     for (int k = 0; k < x.tail_from; k++) {
         NodeDev &nd = ndh[k];
@@ -1414,19 +1419,17 @@ extern "C" fj_status fj_execute(fj_ctx *c, const fj_query *q, const fj_plan *p, 
         nd.in = x.F[k];
         nd.out = x.F[k + 1];
     }
-    if (x.tail_from > 0)
-        FJ_HIP(hipMemcpyAsync(x.nd_d, ndh, sizeof(NodeDev) * x.tail_from, hipMemcpyHostToDevice, c->stream));
     if (x.out) {
-        // the emit descriptor follows the node descriptors in the staging buffer
-        FJ_HIP(hipStreamSynchronize(c->stream));
         const fj::NodeLayout &LT0 = p->layout[x.tail_from];
-        fj::emit_dev_fill(c->desc_h, x.F[x.tail_from], LT0.in_var.data(), LT0.in_var.size(), LT0.in_hatom.data(),
-                          LT0.in_hatom.size(),
-                          x.tails.data(), (int)x.tails.size(), x.head_src.data(), (int)x.head_src.size(), x.out,
-                          x.cap);
-        FJ_HIP(hipMemcpyAsync(x.emit_d, c->desc_h, fj::emit_dev_size(), hipMemcpyHostToDevice, c->stream));
-        FJ_HIP(hipStreamSynchronize(c->stream));
+        fj::emit_dev_fill((char *)c->desc_h + nd_bytes, x.F[x.tail_from], LT0.in_var.data(), LT0.in_var.size(),
+                          LT0.in_hatom.data(), LT0.in_hatom.size(), x.tails.data(), (int)x.tails.size(),
+                          x.head_src.data(), (int)x.head_src.size(), x.out, x.cap);
     }
+    if (x.tail_from > 0 || x.out) {
+        const size_t bytes = x.out ? nd_bytes + fj::emit_dev_size() : sizeof(NodeDev) * x.tail_from;
+        FJ_HIP(hipMemcpyAsync(c->desc.p, c->desc_h, bytes, hipMemcpyHostToDevice, c->stream));
+    }
+    FJ_HIP(hipEventRecord(c->desc_done, c->stream));
 
     // clear the counters but keep any error a build left for the next check;
     // the host copy mirrors the cleared counters (they are read as bases)
