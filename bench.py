@@ -324,13 +324,20 @@ def bench_rmat(args):
     for c in r["colts"]:
         c.free()
     assert r["count"] == tri, (r["count"], tri)
-    # sampled parity: triangles through 64 random x vertices
+    # sampled parity: the triangles through 2048 random x vertices.  The
+    # sampled query keeps the R rows with x in the sample, the S rows whose
+    # y such an R row reaches and the T rows that close back to the sample:
+    # exactly the rows those triangles use.
     rng = np.random.default_rng(12345)
-    xs = np.sort(rng.choice(np.unique(src), size=64, replace=False))
+    xs = np.sort(rng.choice(np.unique(src), size=2048, replace=False))
     want = sampled_triangles(src, dst, xs)
     keep = np.isin(src, xs)
-    es = synth.Relation("Es", [src[keep], dst[keep]])
-    sq = synth.make_query(["x", "y", "z"], [es, dq.relations[0]], [(0, (0, 1)), (1, (1, 2)), (1, (2, 0))])
+    keep_s = np.isin(src, np.unique(dst[keep]))
+    keep_t = np.isin(dst, xs)
+    es = synth.Relation("Rs", [src[keep], dst[keep]])
+    ss = synth.Relation("Ss", [src[keep_s], dst[keep_s]])
+    ts = synth.Relation("Ts", [src[keep_t], dst[keep_t]])
+    sq = synth.make_query(["x", "y", "z"], [es, ss, ts], [(0, (0, 1)), (1, (1, 2)), (2, (2, 0))])
     ds = runner.DeviceQuery(ctx, sq)
     rs = ds.run(ds.plan_binary([0, 1, 2], True), materialize=False, stats=True)
     rs_probe = sum(n_["cover"] for n_ in rs["stats"].per_node())
@@ -340,7 +347,7 @@ def bench_rmat(args):
     for c in colts:
         c.free()
     del d, ds
-    # CPU baseline: the C oracle on the sampled query (64 x vertices)
+    # CPU baseline: the C oracle on the sampled query
     cpu = None
     if not args.no_cpu:
         from oracle import cfj
@@ -352,8 +359,9 @@ def bench_rmat(args):
             raise SystemExit(f"sampled triangles: GPU {rs['count']} vs CPU oracle {r_cpu['count']}")
         cpu = {"value": rs_probe / t_cpu if rs_probe else None, "unit": "probe tuples/s", "cores": 1,
                "kind": "oracle",
-               "sample": f"the triangle query restricted to {xs.size} sampled x vertices ({int(keep.sum())} R rows, "
-                         f"full S and T), converted plan, count only, one run including its COLT builds",
+               "sample": f"the triangle query restricted to {xs.size} sampled x vertices ({int(keep.sum())} R, "
+                         f"{int(keep_s.sum())} S and {int(keep_t.sum())} T rows), converted plan, count only, "
+                         f"one run including its COLT builds",
                "s_per_run": t_cpu, "host_cpus": os.cpu_count()}
     # 4-cycle at a reduced scale against trace(A^4)
     s4, d4 = datagen.rmat_edges(datagen.seed_for(3, 1 + args.seed_rep), args.cycle4_scale,

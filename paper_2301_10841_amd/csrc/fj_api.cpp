@@ -1119,6 +1119,8 @@ fj_status exec_node(Exec &x, int k, uint32_t E) {
             FJ_TRY(c->chunkb.ensure(need * sizeof(uint32_t), c->stream));
             pl.chunk_buf = c->chunkb.as<uint32_t>();
             pl.chunk_cap = c->chunkb.bytes / sizeof(uint32_t);
+            pl.max_slots = p->q.nvars;
+            pl.max_atoms = p->q.natoms;
         }
         {
             Timer t(c, k == 0 ? FJ_T_PROBE0 : FJ_T_PROBE);

@@ -823,6 +823,10 @@ __global__ void k_chunk_entries(const u64 *__restrict__ starts, uint32_t E, u64 
     out[c] = E == 1 ? 0u : upper_entry(starts, 0, E, t0 + off);
 }
 
+// MV and MA bound the binding's variable slots and atoms (powers of two; the
+// host picks the smallest that fits the query, and every index is masked so
+// that no plan can index past them).
+template <int MV, int MA>
 __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
     __shared__ u64 red[17];
     const NodeDev &nd = *a.nd;
@@ -833,8 +837,8 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
     int resume = 0, defer_j = 0;
     u64 mult = 1, emitv = 0;
     uint32_t nprobe = 0, nhit = 0;
-    int32_t v[FJ_MAX_VARS];
-    uint32_t h[FJ_MAX_ATOMS];
+    int32_t v[MV];
+    uint32_t h[MA];
     uint32_t e = 0;
     bool ok = idx < a.n;
     if (ok) {
@@ -852,42 +856,42 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
     if (ok) {
         const u64 i = a.t0 + t - a.starts[e];
         const FrontierDev &F = nd.in;
-        for (int j = 0; j < nd.nin; j++) v[j] = F.vals[(u64)j * F.cap + e];
-        for (int j = 0; j < nd.nin_h; j++) h[nd.in_h_atom[j]] = F.hdl[(u64)j * F.cap + e];
+        for (int j = 0; j < nd.nin; j++) v[(j) & (MV - 1)] = F.vals[(u64)j * F.cap + e];
+        for (int j = 0; j < nd.nin_h; j++) h[(nd.in_h_atom[j]) & (MA - 1)] = F.hdl[(u64)j * F.cap + e];
         mult = F.mult ? F.mult[e] : 1ull;
         // bind the cover tuple
         const uint8_t cb = a.cov[e];
         const int ci = cb & 0x7F;
         const SubDev &S = nd.sub[ci];
-        const uint32_t p = S.level == 0 ? 0u : h[S.atom];
+        const uint32_t p = S.level == 0 ? 0u : h[(S.atom) & (MA - 1)];
         if (cb & 0x80) {
             ok = CK(p + i < S.L.npos);
             const uint32_t s = ok ? S.L.kl[p + (uint32_t)i] : 0u;
             ok = ok && CK(s < S.C.npos);
             if (ok && S.L.kk && S.nk == 1) {
                 // the key list holds the key and its offset count
-                v[S.kslot[0]] = S.L.kk[p + (uint32_t)i];
+                v[(S.kslot[0]) & (MV - 1)] = S.L.kk[p + (uint32_t)i];
                 if (S.child_leaf) mult *= S.L.kn[p + (uint32_t)i];
-                else h[S.atom] = s;
+                else h[(S.atom) & (MA - 1)] = s;
             } else {
                 const uint32_t row = ok ? S.C.offs[s] : 0u;
                 ok = ok && CK(row < S.L.nrows);
                 if (ok) {
-                    for (int c = 0; c < S.nk; c++) v[S.kslot[c]] = S.cols[S.kcol[c]][row];
+                    for (int c = 0; c < S.nk; c++) v[(S.kslot[c]) & (MV - 1)] = S.cols[S.kcol[c]][row];
                     if (S.child_leaf) mult *= S.C.len[s];
-                    else h[S.atom] = s;
+                    else h[(S.atom) & (MA - 1)] = s;
                 }
             }
         } else {
             const u64 pos = p + i;
             ok = CK(p < S.L.npos) && CK(pos < S.L.npos && i < trie_len(S, p));
             if (ok && S.L.kv && S.nk == 1) {
-                v[S.kslot[0]] = S.L.kv[pos];   // the key beside the offset
+                v[(S.kslot[0]) & (MV - 1)] = S.L.kv[pos];   // the key beside the offset
             } else {
                 const uint32_t row = ok ? (S.L.offs ? S.L.offs[pos] : (uint32_t)pos) : 0u;
                 ok = ok && CK(row < S.L.nrows);
                 if (ok)
-                    for (int c = 0; c < S.nk; c++) v[S.kslot[c]] = S.cols[S.kcol[c]][row];
+                    for (int c = 0; c < S.nk; c++) v[(S.kslot[c]) & (MV - 1)] = S.cols[S.kcol[c]][row];
             }
         }
         // lookups in node order
@@ -895,7 +899,7 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
         for (int j = 0; j < nd.nsub && survive; j++) {
             if (j == ci) continue;
             const SubDev &P = nd.sub[j];
-            const uint32_t ph = P.level == 0 ? 0u : h[P.atom];
+            const uint32_t ph = P.level == 0 ? 0u : h[(P.atom) & (MA - 1)];
             if (!CK(ph < P.L.npos)) { survive = false; break; }
             const uint32_t st = P.L.st[ph];
             if (st == 0 || st == kQueued) {
@@ -917,7 +921,7 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
             } else {
                 Key k;
                 k.h = ph;
-                for (int c = 0; c < P.nk; c++) k.v[c] = v[P.kslot[c]];
+                for (int c = 0; c < P.nk; c++) k.v[c] = v[(P.kslot[c]) & (MV - 1)];
                 const u64 slot = table_find(P.L, P.cols, k);
                 if (slot == ~0ull) { survive = false; break; }
                 if (!CK(slot < P.L.nslots)) { survive = false; break; }
@@ -930,14 +934,14 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
             if (!CK(s < P.C.npos)) { survive = false; break; }
             if (j >= resume) nhit++;
             if (P.child_leaf) mult *= have_len ? clen : P.C.len[s];
-            else h[P.atom] = s;
+            else h[(P.atom) & (MA - 1)] = s;
         }
         if (survive && nd.emit) {
             emitv = mult;
             for (int q = 0; q < nd.ntail; q++) {
                 const TailDev &T = nd.tail[q];
                 if (T.level == 0) { emitv *= (u64)T.root_len; continue; }
-                const uint32_t th = h[T.atom];
+                const uint32_t th = h[(T.atom) & (MA - 1)];
                 if (!CK(th < T.L.npos)) { survive = false; emitv = 0; break; }
                 emitv *= (u64)T.L.len[th];
             }
@@ -963,8 +967,8 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
     u64 pos = block_reserve(write, &a.status->survivors, red) - a.surv_base;
     if (write && CK(pos < nd.out.cap)) {
         const FrontierDev &O = nd.out;
-        for (int j = 0; j < nd.nout; j++) O.vals[(u64)j * O.cap + pos] = v[nd.out_slot[j]];
-        for (int j = 0; j < nd.nout_h; j++) O.hdl[(u64)j * O.cap + pos] = h[nd.out_h_atom[j]];
+        for (int j = 0; j < nd.nout; j++) O.vals[(u64)j * O.cap + pos] = v[(nd.out_slot[j]) & (MV - 1)];
+        for (int j = 0; j < nd.nout_h; j++) O.hdl[(u64)j * O.cap + pos] = h[(nd.out_h_atom[j]) & (MA - 1)];
         if (O.mult) O.mult[pos] = mult;
     }
 }
@@ -1524,7 +1528,10 @@ hipError_t launch_probe(const ProbeLaunch &p, hipStream_t s) {
                            (uint32_t)bs, nb, p.chunk_buf);
         a.chunk_e = p.chunk_buf;
     }
-    hipLaunchKernelGGL(k_probe, dim3(nb), dim3(bs), 0, s, a);
+    // the smallest instantiation whose bounds hold the query's slots and atoms
+    if (p.max_slots <= 8 && p.max_atoms <= 8) hipLaunchKernelGGL((k_probe<8, 8>), dim3(nb), dim3(bs), 0, s, a);
+    else if (p.max_slots <= 16 && p.max_atoms <= 16) hipLaunchKernelGGL((k_probe<16, 16>), dim3(nb), dim3(bs), 0, s, a);
+    else hipLaunchKernelGGL((k_probe<FJ_MAX_VARS, FJ_MAX_ATOMS>), dim3(nb), dim3(bs), 0, s, a);
     return hipGetLastError();
 }
 

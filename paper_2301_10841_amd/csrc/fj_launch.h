@@ -42,6 +42,8 @@ struct ProbeLaunch {
     unsigned long long surv_base, def_base;  // counter values before the launch
     uint32_t *chunk_buf;   // scratch for the per-block binding bounds (chunk_cap entries), or null
     unsigned long long chunk_cap;
+    int max_slots;         // variable slots of a binding (<= FJ_MAX_VARS)
+    int max_atoms;         // atoms of the query (<= FJ_MAX_ATOMS)
 };
 
 struct ScanLaunch {
