@@ -50,6 +50,8 @@ def main():
     ap.add_argument("--cycle4-scale", type=int, default=16, help="rmat workload: scale of the 4-cycle run")
     ap.add_argument("--queries", type=int, default=256, help="batch workload: number of queries")
     ap.add_argument("--tune-queries", type=int, default=48, help="batch workload: calibration batch size")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="star workload: skip the one-filter variant and the learned-vs-plain leg (profiling)")
     ap.add_argument("--chooser-queries", type=int, default=48,
                     help="star workload: held-out queries for the learned-vs-plain leg (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -172,8 +174,9 @@ def main():
     }
     for c in colts:
         c.free()
-    res["one_filter_variant"] = star_one_filter(ctx, args)
-    if args.chooser_queries > 0:
+    if not args.no_extras:
+        res["one_filter_variant"] = star_one_filter(ctx, args)
+    if args.chooser_queries > 0 and not args.no_extras:
         res["learned_vs_plain"] = chooser_leg(ctx, args.chooser_queries)
     ctx.close()
     print(json.dumps(res), flush=True)
