@@ -1,0 +1,82 @@
+"""Parity at the workloads' full sizes, where the oracle cannot run the whole
+query: R-MAT with 2^22 vertices and 50M edges (plan invariance, and the
+triangles through sampled vertices against the oracle and the closed form),
+and batched-mix queries at full relation sizes (counts against the oracle)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import datagen
+from datagen import synth
+from oracle import cfj, closed
+from oracle import plans as P
+from tests.gpu_util import gj_nodes
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2301_10841_amd import fj, runner
+    ctx = fj.Context(0)
+    yield fj, runner, ctx
+    ctx.close()
+
+
+def _count(runner, ctx, dq, order=None, nodes=None):
+    d = runner.DeviceQuery(ctx, dq)
+    plan = d.plan_nodes(nodes) if nodes is not None else d.plan_binary(order, True)
+    r = d.run(plan, materialize=False)
+    for c in r["colts"]:
+        c.free()
+    return r["count"]
+
+
+def test_rmat_full_scale_triangles(env):
+    fj, runner, ctx = env
+    src, dst = datagen.rmat_edges(datagen.seed_for(3, 1), 22, 50_000_000)
+    _say("R-MAT edges", src.size)
+    assert src.size == 50_000_000
+    tq = synth.triangle_query((src, dst))
+    gj = _count(runner, ctx, tq, nodes=gj_nodes(tq, [0, 1, 2]))
+    conv = _count(runner, ctx, tq, order=[0, 1, 2])
+    _say("triangles", gj, conv)
+    assert gj == conv
+    # the triangles through 256 sampled x vertices use exactly the R rows
+    # leaving the sample, the S rows those reach and the T rows closing back
+    rng = np.random.default_rng(99)
+    xs = rng.choice(np.unique(src), size=256, replace=False)
+    kr = np.isin(src, xs)
+    ks = np.isin(src, np.unique(dst[kr]))
+    kt = np.isin(dst, xs)
+    rels = [synth.Relation("R", [src[kr], dst[kr]]), synth.Relation("S", [src[ks], dst[ks]]),
+            synth.Relation("T", [src[kt], dst[kt]])]
+    sq = synth.make_query(["x", "y", "z"], rels, [(0, (0, 1)), (1, (1, 2)), (2, (2, 0))])
+    got = _count(runner, ctx, sq, order=[0, 1, 2])
+    want = cfj.run(sq, P.factor(P.binary2fj(sq, [0, 1, 2])), materialize=False, counters=False)["count"]
+    tr = closed.triangle_count((src[kr], dst[kr]), (src[ks], dst[ks]), (src[kt], dst[kt]))
+    _say("sampled triangles", got, want, tr)
+    assert got == want == tr
+    assert 0 < got < gj
+
+
+def test_batch_queries_at_full_size(env):
+    fj, runner, ctx = env
+    seed = datagen.seed_for(4, 0)
+    for i in range(16):
+        dq, _ = datagen.batch_query(seed, i)
+        order = list(range(len(dq.atoms)))
+        got = _count(runner, ctx, dq, order=order)
+        want = cfj.run(dq, P.factor(P.binary2fj(dq, order)), materialize=False, counters=False)["count"]
+        _say(i, dq.kind, [r.nrows for r in dq.relations], got)
+        assert got == want, (i, dq.kind)
