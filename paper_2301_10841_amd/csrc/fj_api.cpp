@@ -227,7 +227,7 @@ int key_mode(int level, int nk) {
 }
 
 size_t slot_bytes(int mode) {
-    return mode == fj::KM_K32 ? sizeof(fj::Slot32) : (mode == fj::KM_K64 ? sizeof(fj::Slot64) : sizeof(fj::SlotRep));
+    return mode == fj::KM_K32 ? 2 * sizeof(uint32_t) : (mode == fj::KM_K64 ? sizeof(fj::Slot64) : sizeof(fj::SlotRep));
 }
 
 template <typename T>
@@ -277,7 +277,8 @@ fj_status colt_allocate(fj_colt *t) {
             L.nslots = cap + 1;
             t->table_slots[l] = cap + 1;
             char *tb = nullptr;
-            FJ_TRY(colt_alloc(t, &tb, (cap + 1) * slot_bytes(L.mode)));
+            FJ_TRY(colt_alloc(t, &tb, L.mode == fj::KM_K32 ? fj::k32_table_words(cap) * sizeof(uint32_t)
+                                                           : (cap + 1) * slot_bytes(L.mode)));
             L.table = tb;
         }
     }
@@ -365,8 +366,8 @@ static fj_status colt_fill_list(fj_colt *t) {
     bool overflow = false;
     auto add = [&](fj::FillList &fl, u64 &total, uint32_t *p, u64 nwords, std::initializer_list<uint32_t> pat) {
         if (!p || !nwords) return;
-        if (fl.n >= fj::kMaxFill || (pat.size() != 1 && pat.size() != 2 && pat.size() != 4)) {
-            overflow = true;   // the fill kernels take periods of 1, 2 or 4 words
+        if (fl.n >= fj::kMaxFill || (pat.size() != 1 && pat.size() != 2 && pat.size() != 4 && pat.size() != 8)) {
+            overflow = true;   // the fill kernels take periods of 1, 2, 4 or 8 words
             return;
         }
         fj::FillRegion &r = fl.r[fl.n++];
@@ -395,8 +396,11 @@ static fj_status colt_fill_list(fj_colt *t) {
         const u64 ns = t->table_slots[l];
         uint32_t *T = (uint32_t *)L.table;
         if (L.mode == fj::KM_K32) {
-            add(fl, words, T, 2 * (ns - 1), {fj::kEmpty32, 0u});
-            add(fl, words, T + 2 * (ns - 1), 2, {0u});
+            // buckets of four empty keys and four zero values (the insert
+            // counts a key's rows in its value); the reserved slot unclaimed
+            const u64 kw = fj::k32_key_word(ns - 1);
+            add(fl, words, T, kw, {fj::kEmpty32, fj::kEmpty32, fj::kEmpty32, fj::kEmpty32, 0u, 0u, 0u, 0u});
+            add(fl, words, T + kw, fj::k32_table_words(ns - 1) - kw, {0u});
         } else if (L.mode == fj::KM_K64) {
             add(fl, words, T, 4 * (ns - 1), {fj::kEmpty32, fj::kEmpty32, 0u, 0u});
             add(fl, words, T + 4 * (ns - 1), 4, {0u});
@@ -513,7 +517,7 @@ fj_status group_prepare(fj_ctx *c, ColtGroup &G, fj_colt *const *colts, int n, u
                 b.p = fl.r[r].p;
                 b.start = off;
                 b.n = std::min<u64>(kFillChunk, fl.r[r].nwords - off);
-                for (int q = 0; q < 4; q++) b.pat[q] = fl.r[r].pat[q];
+                for (int q = 0; q < 8; q++) b.pat[q] = fl.r[r].pat[q];
                 b.period = fl.r[r].period;
                 fb.push_back(b);
             }

@@ -45,15 +45,24 @@ struct Lane {
 // length in *clen), or ~0u.
 __device__ __forceinline__ uint32_t root_get(const BLookup &L, const Lane &ln, uint32_t *clen) {
     if (L.mode == KM_K32) {
-        const Slot32 *T = (const Slot32 *)L.table;
+        // buckets of four keys, then their four values
+        const uint32_t *T = (const uint32_t *)L.table;
         const uint32_t key = (uint32_t)ln.var(L.kslot[0]);
-        if (key == kEmpty32) return T[L.mask + 1].key ? T[L.mask + 1].val : ~0u;
-        u64 i = (bmix32(key) & L.mask) & ~3ull;   // 4 slots of 8 bytes
-        for (u64 n = 0; n <= L.mask; n++) {
-            const Slot32 sl = T[i];
-            if (sl.key == key) return sl.val;
-            if (sl.key == kEmpty32) return ~0u;
-            i = (i + 1) & L.mask;
+        if (key == kEmpty32) {
+            const u64 w = k32_key_word(L.mask + 1);
+            return T[w] ? T[w + 4] : ~0u;
+        }
+        u64 i = (bmix32(key) & L.mask) & ~(u64)(kK32Bucket - 1);
+        for (u64 n = 0; n <= L.mask; n += kK32Bucket) {
+            const u64 w = k32_key_word(i);
+            const uint4 q = *(const uint4 *)(T + w);
+            const uint32_t ks[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int s = 0; s < 4; s++) {
+                if (ks[s] == key) return T[w + 4 + s];
+                if (ks[s] == kEmpty32) return ~0u;
+            }
+            i = (i + kK32Bucket) & L.mask;
         }
     } else {
         const Slot64 *T = (const Slot64 *)L.table;

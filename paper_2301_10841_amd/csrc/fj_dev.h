@@ -22,7 +22,8 @@ constexpr unsigned long long kEmpty64 = ~0ull;
 
 // Hash-map layouts of one level, chosen by key width.
 enum KeyMode : int {
-    KM_K32 = 0,   // root level, one key column:  slot {u32 key, u32 val}
+    KM_K32 = 0,   // root level, one key column: u32 key and u32 val per
+                  // slot, in split buckets (below)
     KM_K64 = 1,   // packed 64-bit key (root with two key columns, or
                   // (handle, value) below the root): slot {u64 key, u32 val, pad}
     KM_REP = 2,   // wider keys: slot {u32 handle, u32 representative row, u32 val, pad},
@@ -30,7 +31,16 @@ enum KeyMode : int {
     KM_ZERO = 3   // a level with no variables: one key, no table
 };
 
-struct Slot32 { uint32_t key; uint32_t val; };
+// KM_K32 maps hold buckets of four slots as four keys followed by their four
+// values (32 bytes), so one 16-byte load compares a probe against a whole
+// bucket and the value is read only on a hit.  Slot i's key is 32-bit word
+// k32_key_word(i) of the table and its value the word four after it; the
+// reserved slot (index capacity) starts a bucket of its own.
+constexpr int kK32Bucket = 4;
+__host__ __device__ inline unsigned long long k32_key_word(unsigned long long i) {
+    return ((i >> 2) << 3) + (i & 3);
+}
+__host__ __device__ inline unsigned long long k32_table_words(unsigned long long cap) { return 2 * cap + 8; }
 struct alignas(16) Slot64 { unsigned long long key; uint32_t val; uint32_t pad; };
 struct alignas(16) SlotRep { unsigned long long hr; uint32_t val; uint32_t pad; };  // hr = row << 32 | handle
 
@@ -180,8 +190,8 @@ struct BItem {
 struct FillRegion {
     uint32_t *p;
     unsigned long long nwords;
-    uint32_t pat[4];
-    int period;
+    uint32_t pat[8];
+    int period;   // 1, 2, 4 or 8 words
 };
 constexpr int kMaxFill = 6 * kMaxLevels + 4;
 struct FillList {
@@ -210,8 +220,8 @@ struct ForceArgs {
 // Grouped root builds: a chunk of a fill region, and a COLT's root words.
 struct FillBlock {
     uint32_t *p;
-    unsigned long long start, n;   // words [start, start + n) of the region at p
-    uint32_t pat[4];
+    unsigned long long start, n;   // words [start, start + n) of the region at p (start % 8 == 0)
+    uint32_t pat[8];
     int period;
 };
 struct GroupRoot {

@@ -45,16 +45,15 @@ struct Key {
     int32_t v[FJ_MAX_COLS];
 };
 
-// Probing walks forward from the start of a 32-byte bucket (4 slots of 8 B,
-// or 2 of 16 B), so that one pair of 16-byte loads usually settles a lookup.
+// Probing walks forward slot by slot from the start of a 32-byte bucket:
+// four KM_K32 slots (keys first, then values), or two 16-byte slots, so one
+// 16-byte key load (KM_K32) or one pair of them usually settles a lookup.
 // Insert and find use the same sequence.
-#ifndef FJ_BUCKET_BYTES
-#define FJ_BUCKET_BYTES 32
-#endif
-constexpr int kBucketBytes = FJ_BUCKET_BYTES;
+constexpr int kBucketBytes = 32;
 template <typename SlotT> __device__ __forceinline__ u64 bucket_start(u64 h, u64 mask) {
     return (h & mask) & ~(u64)(kBucketBytes / sizeof(SlotT) - 1);
 }
+__device__ __forceinline__ u64 k32_bucket(uint32_t h, u64 mask) { return (h & mask) & ~(u64)(kK32Bucket - 1); }
 
 __device__ __forceinline__ u64 pack64(const LevelDev &L, const Key &k) {
     // root with two key columns: (v0, v1); below the root: (handle, v0)
@@ -80,12 +79,12 @@ __device__ __forceinline__ bool rep_equal(const LevelDev &L, const int32_t *cons
 __device__ __forceinline__ u64 table_find(const LevelDev &L, const int32_t *const *cols, const Key &k) {
     const u64 mask = L.mask;
     if (L.mode == KM_K32) {
-        const Slot32 *T = (const Slot32 *)L.table;
+        const uint32_t *T = (const uint32_t *)L.table;
         uint32_t key = (uint32_t)k.v[0];
-        if (key == kEmpty32) return T[mask + 1].key ? mask + 1 : ~0ull;
-        u64 i = bucket_start<Slot32>(mix32(key), mask);
+        if (key == kEmpty32) return T[k32_key_word(mask + 1)] ? mask + 1 : ~0ull;
+        u64 i = k32_bucket(mix32(key), mask);
         for (u64 n = 0; n <= mask; n++) {
-            uint32_t c = T[i].key;
+            uint32_t c = T[k32_key_word(i)];
             if (c == key) return i;
             if (c == kEmpty32) return ~0ull;
             i = (i + 1) & mask;
@@ -116,19 +115,19 @@ __device__ __forceinline__ u64 table_find(const LevelDev &L, const int32_t *cons
 }
 
 __device__ __forceinline__ uint32_t slot_val(const LevelDev &L, u64 i) {
-    if (L.mode == KM_K32) return ((const Slot32 *)L.table)[i].val;
+    if (L.mode == KM_K32) return ((const uint32_t *)L.table)[k32_key_word(i) + 4];
     if (L.mode == KM_K64) return ((const Slot64 *)L.table)[i].val;
     return ((const SlotRep *)L.table)[i].val;
 }
 
 __device__ __forceinline__ void set_slot_val(const LevelDev &L, u64 i, uint32_t v) {
-    if (L.mode == KM_K32) ((Slot32 *)L.table)[i].val = v;
+    if (L.mode == KM_K32) ((uint32_t *)L.table)[k32_key_word(i) + 4] = v;
     else if (L.mode == KM_K64) ((Slot64 *)L.table)[i].val = v;
     else ((SlotRep *)L.table)[i].val = v;
 }
 
 __device__ __forceinline__ uint32_t *slot_val_ptr(const LevelDev &L, u64 i) {
-    if (L.mode == KM_K32) return &((Slot32 *)L.table)[i].val;
+    if (L.mode == KM_K32) return (uint32_t *)L.table + k32_key_word(i) + 4;
     if (L.mode == KM_K64) return &((Slot64 *)L.table)[i].val;
     return &((SlotRep *)L.table)[i].val;
 }
@@ -139,16 +138,16 @@ __device__ __forceinline__ u64 table_insert(const LevelDev &L, const int32_t *co
     const u64 mask = L.mask;
     claimed = false;
     if (L.mode == KM_K32) {
-        Slot32 *T = (Slot32 *)L.table;
+        uint32_t *T = (uint32_t *)L.table;
         uint32_t key = (uint32_t)k.v[0];
         if (key == kEmpty32) {
-            claimed = atomicCAS(&T[mask + 1].key, 0u, 1u) == 0u;
+            claimed = atomicCAS(&T[k32_key_word(mask + 1)], 0u, 1u) == 0u;
             return mask + 1;
         }
-        u64 i = bucket_start<Slot32>(mix32(key), mask);
+        u64 i = k32_bucket(mix32(key), mask);
         for (u64 n = 0; n <= mask; n++) {
             // the compare-and-swap returns the occupant: no separate read
-            const uint32_t old = atomicCAS(&T[i].key, kEmpty32, key);
+            const uint32_t old = atomicCAS(&T[k32_key_word(i)], kEmpty32, key);
             if (old == kEmpty32) { claimed = true; return i; }
             if (old == key) return i;
             i = (i + 1) & mask;
@@ -265,22 +264,6 @@ __global__ void k_fill(T *p, u64 n, T v) {
     for (; i < n; i += stride) p[i] = v;
 }
 
-__global__ void k_table_init(void *table, u64 nslots, int mode) {
-    // all slots empty; the reserved last slot starts at 0 (unclaimed)
-    u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    u64 stride = (u64)gridDim.x * blockDim.x;
-    for (; i < nslots; i += stride) {
-        bool last = (i + 1 == nslots);
-        if (mode == KM_K32) {
-            Slot32 s; s.key = last ? 0u : kEmpty32; s.val = 0; ((Slot32 *)table)[i] = s;
-        } else if (mode == KM_K64) {
-            Slot64 s; s.key = last ? 0ull : kEmpty64; s.val = 0; s.pad = 0; ((Slot64 *)table)[i] = s;
-        } else {
-            SlotRep s; s.hr = kEmpty64; s.val = 0; s.pad = 0; ((SlotRep *)table)[i] = s;
-        }
-    }
-}
-
 // Fill a list of regions with periodic 32-bit patterns (table slots, zeroed
 // state arrays) in one launch; also set the root handle and the one-handle
 // force queue of the root.
@@ -289,7 +272,7 @@ __global__ void k_fill_list(const FillList *__restrict__ fl, LevelDev root, uint
     const u64 tid = (u64)blockIdx.x * blockDim.x + threadIdx.x;
     for (int k = 0; k < fl->n; k++) {
         const FillRegion &r = fl->r[k];
-        const u64 m = (u64)r.period - 1;   // periods are 1, 2 or 4
+        const u64 m = (u64)r.period - 1;   // periods are 1, 2, 4 or 8
         for (u64 i = tid; i < r.nwords; i += stride) r.p[i] = r.pat[i & m];
     }
     if (tid == 0 && root.len) {
@@ -694,12 +677,13 @@ __global__ void __launch_bounds__(256) k_group_force(const ForceArgs *__restrict
 // aligned chunk start.
 __global__ void __launch_bounds__(256) k_group_fill(const FillBlock *__restrict__ fb) {
     const FillBlock &b = fb[blockIdx.x];
-    const u64 m = (u64)b.period - 1;
+    const u64 m = (u64)b.period - 1;   // 1, 2, 4 or 8 words; b.start % 8 == 0
     uint32_t *p = b.p + b.start;
     const u64 n4 = b.n >> 2;
-    const uint4 v = make_uint4(b.pat[0], b.pat[1 & m], b.pat[2 & m], b.pat[3 & m]);
-    for (u64 i = threadIdx.x; i < n4; i += 256) ((uint4 *)p)[i] = v;
-    for (u64 i = (n4 << 2) + threadIdx.x; i < b.n; i += 256) p[i] = b.pat[(b.start + i) & m];
+    const uint4 v0 = make_uint4(b.pat[0], b.pat[1 & m], b.pat[2 & m], b.pat[3 & m]);
+    const uint4 v1 = make_uint4(b.pat[4 & m], b.pat[5 & m], b.pat[6 & m], b.pat[7 & m]);
+    for (u64 i = threadIdx.x; i < n4; i += 256) ((uint4 *)p)[i] = (i & 1) ? v1 : v0;
+    for (u64 i = (n4 << 2) + threadIdx.x; i < b.n; i += 256) p[i] = b.pat[i & m];
 }
 
 // Per COLT: the root handle spans every root row; a built root with no rows
@@ -976,35 +960,38 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
 // ------------------------------------------------------------ scan probe
 // Specialised first node: the cover is a base table (or its selection)
 // iterated directly and every other subatom is a probe of a root map keyed
-// by cover columns.  Each thread takes kScanRows rows of a contiguous tile
-// (coalesced, non-temporal column loads) and probes trie by trie across its
-// rows, so the rows' independent probes are in flight together: the
-// vectorized execution of Section 4.3 mapped onto one thread's registers.
+// by cover columns.  The node's lookups run as rounds over a batch of cover
+// rows (Section 4.3's batch, one lookup at a time over the whole batch).
+// Round 0 probes every row of a tile of kTile positions, kTileRows per
+// thread with their loads in flight together; the rows that hit join an LDS
+// batch.  Once the batch could not take another tile, round j probes only
+// the entries left by round j - 1, reading lookup j's key columns for those
+// rows alone: every round's lanes are dense, the later rounds shrink with
+// the selectivity, and key columns past the first are read only where a row
+// is still alive.  A hit is kept per (lookup, batch entry) in LDS: its slot
+// for a KM_K32 map, whose value is read only for the rows that pass every
+// lookup, or its value for a KM_K64 map.
 
-#ifndef FJ_SCAN_ROWS
-#define FJ_SCAN_ROWS 1
+#ifndef FJ_TILE_ROWS
+#define FJ_TILE_ROWS 2
 #endif
-constexpr int kScanRows = FJ_SCAN_ROWS;
-#ifndef FJ_SCAN_SPEC
-#define FJ_SCAN_SPEC 1
+constexpr int kTileRows = FJ_TILE_ROWS;
+constexpr int kTile = 256 * kTileRows;
+constexpr int kBatch = 2 * kTile;   // batch entries: room for another whole tile at every check
+#ifndef FJ_ROUND_ROWS
+#define FJ_ROUND_ROWS 2
 #endif
-constexpr int kScanSpec = FJ_SCAN_SPEC;   // lookups whose bucket loads are in flight together
+constexpr int kRoundRows = FJ_ROUND_ROWS;   // batch entries per thread in flight in the later rounds
+#ifndef FJ_SCAN_WAVES
+#define FJ_SCAN_WAVES 1
+#endif
+static_assert(kBatch <= 65536, "batch entries are 16-bit");
 constexpr int kScanMaxLookups = 8;
-
-// Streaming loads of cover columns (read once).
-__device__ __forceinline__ int32_t stream_load(const int32_t *p) {
-#ifdef FJ_NT_LOADS
-    return __builtin_nontemporal_load(p);
-#else
-    return *p;
-#endif
-}
 
 struct ScanArgs {
     const int32_t *cols[FJ_MAX_COLS];
     int ncols;
-    int vec;                  // cover columns are 16-byte aligned: load 4 rows at once
-    int keycol[FJ_MAX_COLS];  // nonzero for columns some lookup keys on
+    int vec;                  // no selection, rows in bounds, 16-byte aligned columns, r0 % 4 == 0
     const uint32_t *sel;      // selection of the cover relation, or null
     uint32_t nrows;           // rows of the cover relation's columns
     uint32_t r0;              // first cover position of this launch
@@ -1026,251 +1013,404 @@ struct ScanArgs {
     u64 surv_base;            // survivor counter before this launch
 };
 
-// Bucket of a root map, held as 16-byte vector registers.
-constexpr int kBucketVec = kBucketBytes / 16;
-struct Bucket { uint4 q[kBucketVec]; };
-
-__device__ __forceinline__ void load_bucket(const void *T, u64 byte_off, Bucket &out) {
-    const uint4 *src = (const uint4 *)((const char *)T + byte_off);
-#pragma unroll
-    for (int q = 0; q < kBucketVec; q++) out.q[q] = src[q];
-}
-
-// Scan a loaded bucket in slot order: 1 = hit, 2 = miss (empty slot), 0 = go
-// on.  Branch-free: walking the slots backwards, the earliest slot that holds
-// the key or is empty decides.
-__device__ __forceinline__ int scan_bucket32(const Bucket &bk, uint32_t key, uint32_t &val) {
-    int st = 0;
-    uint32_t v = 0;
-#pragma unroll
-    for (int q = kBucketVec - 1; q >= 0; q--) {
-        const uint32_t kz = bk.q[q].z, kx = bk.q[q].x;
-        st = kz == key ? 1 : (kz == kEmpty32 ? 2 : st);
-        v = kz == key ? bk.q[q].w : v;
-        st = kx == key ? 1 : (kx == kEmpty32 ? 2 : st);
-        v = kx == key ? bk.q[q].y : v;
-    }
-    val = v;
-    return st;
-}
-
-__device__ __forceinline__ int scan_bucket64(const Bucket &bk, u64 key, uint32_t &val) {
-    int st = 0;
-    uint32_t v = 0;
-#pragma unroll
-    for (int q = kBucketVec - 1; q >= 0; q--) {
-        const u64 k = ((u64)bk.q[q].y << 32) | bk.q[q].x;
-        st = k == key ? 1 : (k == kEmpty64 ? 2 : st);
-        v = k == key ? bk.q[q].z : v;
-    }
-    val = v;
-    return st;
-}
-
-// One round of root-map probes for kScanRows rows: every row's bucket load
-// is issued before any is examined.  Keys equal to the empty marker live in
-// the reserved slot (mask + 1), whose key word is 1 once claimed.
-template <int MODE>
-__device__ __forceinline__ void scan_round(const ScanArgs &a, const ScanLookup &L, const uint32_t *row,
-                                           bool *alive, bool vec, uint32_t *val) {
-    typedef typename std::conditional<MODE == KM_K32, Slot32, Slot64>::type SlotT;
-    typedef typename std::conditional<MODE == KM_K32, uint32_t, u64>::type KeyT;
-    constexpr u64 B = kBucketBytes / sizeof(SlotT);
-    const SlotT *T = (const SlotT *)L.table;
-    const KeyT empty = MODE == KM_K32 ? (KeyT)kEmpty32 : (KeyT)kEmpty64;
-    const int32_t *c0 = a.cols[L.kc[0]];
-    const int32_t *c1 = a.cols[MODE == KM_K32 ? L.kc[0] : L.kc[1]];
-    int32_t k0[kScanRows], k1[kScanRows];
-    // keys: one 16-byte load per column when the thread's rows are
-    // consecutive and all alive, else one load per live row
-    bool all = vec;
-#pragma unroll
-    for (int r = 0; r < kScanRows; r++) all = all && alive[r];
-    if constexpr (kScanRows == 4) {
-        if (all) {
-            const int4 x = *(const int4 *)(c0 + row[0]);
-            k0[0] = x.x; k0[1] = x.y; k0[2] = x.z; k0[3] = x.w;
-            if (MODE != KM_K32) {
-                const int4 y = *(const int4 *)(c1 + row[0]);
-                k1[0] = y.x; k1[1] = y.y; k1[2] = y.z; k1[3] = y.w;
-            }
-        }
-    }
-    if (!all || kScanRows != 4) {
-#pragma unroll
-        for (int r = 0; r < kScanRows; r++) {
-            k0[r] = alive[r] ? c0[row[r]] : 0;
-            if (MODE != KM_K32) k1[r] = alive[r] ? c1[row[r]] : 0;
-        }
-    }
-    KeyT key[kScanRows];
-    u64 idx[kScanRows];
-    Bucket bk[kScanRows];
-#pragma unroll
-    for (int r = 0; r < kScanRows; r++) {
-#pragma unroll
-        for (int q = 0; q < kBucketVec; q++) bk[r].q[q] = make_uint4(0, 0, 0, 0);
-        key[r] = MODE == KM_K32 ? (KeyT)(uint32_t)k0[r]
-                                : (KeyT)((((u64)(uint32_t)k0[r]) << 32) | (uint32_t)k1[r]);
-        const u64 h = MODE == KM_K32 ? (u64)mix32((uint32_t)key[r]) : mix64((u64)key[r]);
-        idx[r] = bucket_start<SlotT>(h, L.mask);
-        if (alive[r] && key[r] != empty) load_bucket(T, idx[r] * sizeof(SlotT), bk[r]);
-    }
-#pragma unroll
-    for (int r = 0; r < kScanRows; r++) {
-        if (!alive[r]) continue;
-        if (key[r] == empty) {
-            const SlotT rs = T[L.mask + 1];
-            alive[r] = rs.key != 0;
-            val[r] = rs.val;
-            continue;
-        }
-        int st = MODE == KM_K32 ? scan_bucket32(bk[r], (uint32_t)key[r], val[r])
-                                : scan_bucket64(bk[r], (u64)key[r], val[r]);
-        for (u64 n = B; st == 0 && n <= L.mask; n += B) {   // a full bucket: go on (rare)
-            idx[r] = (idx[r] + B) & L.mask;
-            load_bucket(T, idx[r] * sizeof(SlotT), bk[r]);
-            st = MODE == KM_K32 ? scan_bucket32(bk[r], (uint32_t)key[r], val[r])
-                                : scan_bucket64(bk[r], (u64)key[r], val[r]);
-        }
-        alive[r] = st == 1;
-    }
-}
-
-// One row, one lookup, in two steps: issue() computes the bucket and starts
-// its load; resolve() scans it (and walks on in the rare full bucket).  A
-// thread issues the loads of two lookups before resolving the first, since
-// a bucket's address depends only on the row's key columns.
+// One row's probe of a root map in two steps, so that several rows' loads
+// are in flight together: issue() hashes the key and loads its first bucket
+// (KM_K32: the bucket's four keys, one 16-byte load; KM_K64: its two
+// slots), resolve() scans it and walks on past full buckets.
 struct RowProbe {
-    Bucket bk;
-    u64 idx;
-    u64 key;     // K32: the 32-bit key; K64: the packed pair
+    uint4 q0, q1;
+    u64 idx;     // first slot of the loaded bucket
+    u64 key;     // KM_K32: the 32-bit key; KM_K64: the packed pair
     bool empty;  // the key equals the empty marker (reserved slot)
 };
 
+template <int MODE>
 __device__ __forceinline__ void probe_issue(const ScanLookup &L, uint32_t k0, uint32_t k1, bool alive,
                                             RowProbe &rp) {
-#pragma unroll
-    for (int q = 0; q < kBucketVec; q++) rp.bk.q[q] = make_uint4(0, 0, 0, 0);
-    if (L.mode == KM_K32) {
+    rp.q1 = make_uint4(0, 0, 0, 0);
+    // the load is not branched around: rows that need no bucket read
+    // bucket 0, so the compiler keeps every row's load in flight
+    if constexpr (MODE == KM_K32) {
         rp.key = k0;
         rp.empty = k0 == kEmpty32;
-        rp.idx = bucket_start<Slot32>(mix32(k0), L.mask);
-        if (alive && !rp.empty) load_bucket(L.table, rp.idx * sizeof(Slot32), rp.bk);
+        rp.idx = k32_bucket(mix32(k0), L.mask);
+        const u64 b = (alive && !rp.empty) ? rp.idx : 0;
+        rp.q0 = *(const uint4 *)((const uint32_t *)L.table + k32_key_word(b));
     } else {
         rp.key = ((u64)k0 << 32) | k1;
         rp.empty = rp.key == kEmpty64;
         rp.idx = bucket_start<Slot64>(mix64(rp.key), L.mask);
-        if (alive && !rp.empty) load_bucket(L.table, rp.idx * sizeof(Slot64), rp.bk);
+        const uint4 *b = (const uint4 *)((const Slot64 *)L.table + ((alive && !rp.empty) ? rp.idx : 0));
+        rp.q0 = b[0];
+        rp.q1 = b[1];
     }
 }
 
-__device__ __forceinline__ bool probe_resolve(const ScanLookup &L, RowProbe &rp, uint32_t &val) {
-    if (L.mode == KM_K32) {
-        const Slot32 *T = (const Slot32 *)L.table;
-        if (rp.empty) { const Slot32 rs = T[L.mask + 1]; val = rs.val; return rs.key != 0; }
-        constexpr u64 B = kBucketBytes / sizeof(Slot32);
-        int st = scan_bucket32(rp.bk, (uint32_t)rp.key, val);
-        for (u64 n = B; st == 0 && n <= L.mask; n += B) {
-            rp.idx = (rp.idx + B) & L.mask;
-            load_bucket(T, rp.idx * sizeof(Slot32), rp.bk);
-            st = scan_bucket32(rp.bk, (uint32_t)rp.key, val);
+// Four KM_K32 keys in slot order: 1 = hit (its slot in s), 2 = miss (an
+// empty slot comes first), 0 = full of other keys.  Branch-free: walking
+// backwards, the earliest deciding slot wins.
+__device__ __forceinline__ int scan_keys32(const uint4 &q, uint32_t key, int &s) {
+    int st = 0, at = 0;
+    st = q.w == key ? 1 : (q.w == kEmpty32 ? 2 : st);
+    at = q.w == key ? 3 : at;
+    st = q.z == key ? 1 : (q.z == kEmpty32 ? 2 : st);
+    at = q.z == key ? 2 : at;
+    st = q.y == key ? 1 : (q.y == kEmpty32 ? 2 : st);
+    at = q.y == key ? 1 : at;
+    st = q.x == key ? 1 : (q.x == kEmpty32 ? 2 : st);
+    at = q.x == key ? 0 : at;
+    s = at;
+    return st;
+}
+
+// Two KM_K64 slots {key lo, key hi, val, pad}: as above, the value in val.
+__device__ __forceinline__ int scan_slots64(const uint4 &a, const uint4 &b, u64 key, uint32_t &val) {
+    int st = 0;
+    uint32_t v = 0;
+    const u64 kb = ((u64)b.y << 32) | b.x, ka = ((u64)a.y << 32) | a.x;
+    st = kb == key ? 1 : (kb == kEmpty64 ? 2 : st);
+    v = kb == key ? b.z : v;
+    st = ka == key ? 1 : (ka == kEmpty64 ? 2 : st);
+    v = ka == key ? a.z : v;
+    val = v;
+    return st;
+}
+
+// true on a hit; out = the slot (KM_K32) or the value (KM_K64)
+template <int MODE>
+__device__ __forceinline__ bool probe_resolve(const ScanLookup &L, RowProbe &rp, uint32_t &out) {
+    if constexpr (MODE == KM_K32) {
+        const uint32_t *T = (const uint32_t *)L.table;
+        out = (uint32_t)(L.mask + 1);
+        if (rp.empty) return T[k32_key_word(L.mask + 1)] != 0u;
+        int s = 0;
+        int st = scan_keys32(rp.q0, (uint32_t)rp.key, s);
+        for (u64 n = kK32Bucket; st == 0 && n <= L.mask; n += kK32Bucket) {   // a full bucket (rare)
+            rp.idx = (rp.idx + kK32Bucket) & L.mask;
+            rp.q0 = *(const uint4 *)(T + k32_key_word(rp.idx));
+            st = scan_keys32(rp.q0, (uint32_t)rp.key, s);
+        }
+        out = (uint32_t)(rp.idx + s);
+        return st == 1;
+    } else {
+        const Slot64 *T = (const Slot64 *)L.table;
+        if (rp.empty) {
+            const Slot64 rs = T[L.mask + 1];
+            out = rs.val;
+            return rs.key != 0;
+        }
+        int st = scan_slots64(rp.q0, rp.q1, rp.key, out);
+        for (u64 n = 2; st == 0 && n <= L.mask; n += 2) {
+            rp.idx = (rp.idx + 2) & L.mask;
+            const uint4 *b = (const uint4 *)(T + rp.idx);
+            rp.q0 = b[0];
+            rp.q1 = b[1];
+            st = scan_slots64(rp.q0, rp.q1, rp.key, out);
         }
         return st == 1;
     }
-    const Slot64 *T = (const Slot64 *)L.table;
-    if (rp.empty) { const Slot64 rs = T[L.mask + 1]; val = rs.val; return rs.key != 0; }
-    constexpr u64 B = kBucketBytes / sizeof(Slot64);
-    int st = scan_bucket64(rp.bk, rp.key, val);
-    for (u64 n = B; st == 0 && n <= L.mask; n += B) {
-        rp.idx = (rp.idx + B) & L.mask;
-        load_bucket(T, rp.idx * sizeof(Slot64), rp.bk);
-        st = scan_bucket64(rp.bk, rp.key, val);
+}
+
+__device__ __forceinline__ uint32_t tile_row(const ScanArgs &a, uint32_t tile0, uint32_t p) {
+    const uint32_t pos = a.r0 + tile0 + p;
+    return a.sel ? a.sel[pos] : pos;
+}
+
+// A slot in an LDS list for each lane with pred, one LDS atomic per wave.
+__device__ __forceinline__ uint32_t list_slot(bool pred, uint32_t *cnt) {
+    const u64 mask = __ballot(pred);
+    if (!mask) return 0;
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)mask) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(cnt, (uint32_t)__popcll(mask));
+    base = __shfl(base, leader, 64);
+    return base + __popcll(mask & ((1ull << lane) - 1ull));
+}
+
+// Rows of a tile taken with positions strided by the workgroup size (a
+// ragged tile, or a selection), and which are live; dead ones read row 0
+// (the launch has nrows >= 1).
+__device__ __forceinline__ void round0_rows(const ScanArgs &a, uint32_t tile0, uint32_t tn, uint32_t *row,
+                                            bool *alive) {
+    StatusDev *status = a.status;
+#pragma unroll
+    for (int r = 0; r < kTileRows; r++) {
+        const uint32_t p = r * 256 + threadIdx.x;
+        alive[r] = p < tn;
+        row[r] = tile_row(a, tile0, alive[r] ? p : 0u);   // position 0 of the tile exists
+        alive[r] = alive[r] && CK(row[r] < a.nrows);
+        row[r] = alive[r] ? row[r] : 0u;
     }
-    return st == 1;
+}
+
+// LDS state of one workgroup: the batch of rows that passed round 0 (their
+// rows and, per lookup, their hits) and the lists of batch entries that
+// passed each later round.
+struct ScanLds {
+    uint32_t *bh;       // bh[j * kBatch + b]: lookup j's hit for batch entry b (dynamic LDS)
+    uint32_t *brow;     // brow[b]: the entry's row of the cover relation
+    uint16_t *lists;    // two lists of kBatch: entries alive after rounds 1, 2, ... (alternating)
+    uint32_t *cnt;      // cnt[0]: batch entries; cnt[j]: entries alive after round j
+};
+
+// Round 0, second half: scan the issued probes of the thread's rows; rows
+// that hit join the batch.
+template <int MODE, bool STATS>
+__device__ __forceinline__ void round0_finish(const ScanArgs &a, const ScanLookup &L, const uint32_t *row,
+                                              const bool *alive, RowProbe *pr, const ScanLds &S,
+                                              uint32_t &nprobe, uint32_t &nhit) {
+    StatusDev *status = a.status;
+#pragma unroll
+    for (int r = 0; r < kTileRows; r++) {
+        bool hit = false;
+        uint32_t v = 0;
+        if (alive[r]) {
+            if (STATS) nprobe++;
+            hit = probe_resolve<MODE>(L, pr[r], v) && (MODE == KM_K32 || CK(v < L.cnpos));
+            if (STATS && hit) nhit++;
+        }
+        const uint32_t b = list_slot(hit, &S.cnt[0]);
+        if (hit) {
+            S.brow[b] = row[r];
+            S.bh[b] = v;
+        }
+    }
+}
+
+// Keys of one column for the thread's rows of a whole tile (VEC layout).
+__device__ __forceinline__ void tile_keys(const int32_t *c, uint32_t row0, uint32_t *k) {
+    if constexpr (kTileRows % 4 == 0) {
+#pragma unroll
+        for (int r = 0; r < kTileRows; r += 4) {
+            const int4 x = *(const int4 *)(c + row0 + r);
+            k[r] = x.x; k[r + 1] = x.y; k[r + 2] = x.z; k[r + 3] = x.w;
+        }
+    } else if constexpr (kTileRows == 2) {
+        const int2 x = *(const int2 *)(c + row0);
+        k[0] = x.x; k[1] = x.y;
+    } else {
+#pragma unroll
+        for (int r = 0; r < kTileRows; r++) k[r] = (uint32_t)c[row0 + r];
+    }
+}
+
+// Round j >= 1: lookup L over the n batch entries the previous round left
+// (round 1: the whole batch), kRoundRows entries per thread in flight.
+template <int MODE, bool STATS>
+__device__ __forceinline__ void scan_round(const ScanArgs &a, const ScanLookup &L, int j, uint32_t n,
+                                           const ScanLds &S, uint32_t &nprobe, uint32_t &nhit) {
+    StatusDev *status = a.status;
+    const uint16_t *in = j == 1 ? nullptr : S.lists + ((j - 1) & 1) * kBatch;
+    uint16_t *out = S.lists + (j & 1) * kBatch;
+    const int32_t *c0 = a.cols[L.kc[0]];
+    const int32_t *c1 = a.cols[MODE != KM_K32 ? L.kc[1] : L.kc[0]];
+    for (uint32_t i0 = 0; i0 < n; i0 += 256 * kRoundRows) {
+        uint32_t b[kRoundRows], k0[kRoundRows], k1[kRoundRows];
+        bool live[kRoundRows];
+#pragma unroll
+        for (int r = 0; r < kRoundRows; r++) {
+            const uint32_t i = i0 + r * 256 + threadIdx.x;
+            live[r] = i < n;
+            b[r] = live[r] ? (in ? in[i] : i) : 0u;   // entry 0 exists (n > 0)
+            const uint32_t row = S.brow[b[r]];
+            k0[r] = (uint32_t)c0[row];
+            k1[r] = MODE != KM_K32 ? (uint32_t)c1[row] : 0u;
+        }
+        RowProbe pr[kRoundRows];
+#pragma unroll
+        for (int r = 0; r < kRoundRows; r++) probe_issue<MODE>(L, k0[r], k1[r], live[r], pr[r]);
+#pragma unroll
+        for (int r = 0; r < kRoundRows; r++) {
+            bool hit = false;
+            if (live[r]) {
+                if (STATS) nprobe++;
+                uint32_t v = 0;
+                hit = probe_resolve<MODE>(L, pr[r], v) && (MODE == KM_K32 || CK(v < L.cnpos));
+                if (hit) {
+                    if (STATS) nhit++;
+                    S.bh[j * kBatch + b[r]] = v;
+                }
+            }
+            const uint32_t o = list_slot(hit, &S.cnt[j]);
+            if (hit) out[o] = (uint16_t)b[r];
+        }
+    }
+}
+
+// Rounds 1..nl-1 over the batch, then the batch's results: counts (emit)
+// and/or frontier rows (materialize, or a node that is not the last).  Every
+// thread of the workgroup calls it; it leaves the batch empty.
+template <bool STATS>
+__device__ __forceinline__ void scan_flush(const ScanArgs &a, const ScanLds &S, uint32_t nb, u64 &tot,
+                                           uint32_t &nprobe, uint32_t &nhit, u64 *red) {
+    StatusDev *status = a.status;
+    uint32_t nf = nb;
+    int last = 0;
+    for (int j = 1; j < a.nl && nf > 0; j++) {
+        if (a.lk[j].mode == KM_K32) scan_round<KM_K32, STATS>(a, a.lk[j], j, nf, S, nprobe, nhit);
+        else scan_round<KM_K64, STATS>(a, a.lk[j], j, nf, S, nprobe, nhit);
+        __syncthreads();
+        nf = S.cnt[j];
+        last = j;
+    }
+    if (nf > 0) {
+        const uint16_t *fin = last == 0 ? nullptr : S.lists + (last & 1) * kBatch;
+        const bool write = !a.emit || a.materialize;
+        if (write) {
+            if (threadIdx.x == 0) red[16] = atomicAdd(&a.status->survivors, (u64)nf);
+            __syncthreads();
+        }
+        const u64 base = write ? red[16] - a.surv_base : 0;
+        for (uint32_t i = threadIdx.x; i < nf; i += 256) {
+            const uint32_t b = fin ? fin[i] : i;
+            // slots of KM_K32 maps become their values (the child handles)
+            bool ok = true;
+            for (int j = 0; j < a.nl; j++) {
+                const ScanLookup &L = a.lk[j];
+                if (L.mode != KM_K32) continue;
+                const uint32_t v = ((const uint32_t *)L.table)[k32_key_word(S.bh[j * kBatch + b]) + 4];
+                ok = ok && CK(v < L.cnpos);
+                S.bh[j * kBatch + b] = v;
+            }
+            if (!ok) continue;
+            u64 m = 1;
+            for (int j = 0; j < a.nl; j++)
+                if (a.lk[j].child_leaf) m *= a.lk[j].clen[S.bh[j * kBatch + b]];
+            if (a.emit) {
+                u64 e = m;
+                for (int q = 0; q < a.ntail; q++) {
+                    if (a.tail_lk[q] < 0) { e *= a.tail_root_len[q]; continue; }
+                    const uint32_t th = S.bh[a.tail_lk[q] * kBatch + b];
+                    if (!CK(th < a.tail_npos[q])) { e = 0; break; }
+                    e *= a.tail_len[q][th];
+                }
+                tot += e;
+            }
+            if (write) {
+                const u64 pos = base + i;
+                const FrontierDev &O = a.out;
+                if (!CK(pos < O.cap)) continue;
+                const uint32_t row = S.brow[b];
+                for (int j = 0; j < a.nout; j++) O.vals[(u64)j * O.cap + pos] = a.cols[a.out_col[j]][row];
+                for (int j = 0; j < a.nl; j++)
+                    if (a.lk[j].hcol >= 0) O.hdl[(u64)a.lk[j].hcol * O.cap + pos] = S.bh[j * kBatch + b];
+                if (O.mult) O.mult[pos] = m;
+            }
+        }
+    }
+    __syncthreads();   // every entry of the batch is read: empty it
+    if (threadIdx.x <= kScanMaxLookups) S.cnt[threadIdx.x] = 0;
+    __syncthreads();
+}
+
+// Persistent workgroups: workgroup g takes tiles g, g + G, g + 2G, ... and
+// runs round 0 over each; when the batch could not take another whole tile
+// (or the tiles run out) the later rounds run over the batch.  So the
+// dependent latencies of the later rounds are paid once per batch, not once
+// per tile.  A whole tile's keys (VEC layout) are loaded one tile ahead, so
+// their latency hides behind the current tile's probes.
+template <int MODE, bool STATS>
+__device__ __forceinline__ void scan_tiles(const ScanArgs &a, const ScanLds &S, u64 &tot, uint32_t &nprobe,
+                                           uint32_t &nhit, u64 *red) {
+    StatusDev *status = a.status;
+    const ScanLookup &L = a.lk[0];
+    const int32_t *c0 = a.cols[L.kc[0]];
+    const int32_t *c1 = a.cols[MODE == KM_K32 ? L.kc[0] : L.kc[1]];
+    const uint32_t ntiles = (a.n + kTile - 1) / kTile;
+    const uint32_t nfull = a.vec ? a.n / kTile : 0;   // tiles read with the VEC layout
+    // keys of whole tiles, in two register sets used in turn (the loop is
+    // unrolled by two), so that no loaded key is ever copied: a copy would
+    // wait for its load
+    uint32_t ka0[kTileRows], ka1[kTileRows], kb0[kTileRows], kb1[kTileRows];
+    auto prefetch = [&](uint32_t t, uint32_t *k0, uint32_t *k1) {
+        if (t < nfull) {
+            const uint32_t row0 = a.r0 + t * kTile + threadIdx.x * kTileRows;
+            tile_keys(c0, row0, k0);
+            if constexpr (MODE != KM_K32) tile_keys(c1, row0, k1);
+        }
+    };
+    // tile t with its keys in (k0, k1) if it is whole; prefetch the keys of
+    // the workgroup's next tile into (n0, n1)
+    auto tile = [&](uint32_t t, const uint32_t *k0, const uint32_t *k1, uint32_t *n0, uint32_t *n1) {
+        const uint32_t tile0 = t * (uint32_t)kTile;
+        const uint32_t tn = min((uint32_t)kTile, a.n - tile0);
+        uint32_t row[kTileRows];
+        bool alive[kTileRows];
+        RowProbe pr[kTileRows];
+        if (t < nfull) {
+#pragma unroll
+            for (int r = 0; r < kTileRows; r++) {
+                row[r] = a.r0 + tile0 + threadIdx.x * kTileRows + r;
+                alive[r] = true;
+            }
+#pragma unroll
+            for (int r = 0; r < kTileRows; r++)
+                probe_issue<MODE>(L, k0[r], MODE != KM_K32 ? k1[r] : 0u, true, pr[r]);
+            prefetch(t + gridDim.x, n0, n1);
+        } else {
+            round0_rows(a, tile0, tn, row, alive);
+            uint32_t s0[kTileRows], s1[kTileRows];
+#pragma unroll
+            for (int r = 0; r < kTileRows; r++) {
+                s0[r] = (uint32_t)c0[row[r]];
+                s1[r] = MODE != KM_K32 ? (uint32_t)c1[row[r]] : 0u;
+            }
+#pragma unroll
+            for (int r = 0; r < kTileRows; r++) probe_issue<MODE>(L, s0[r], s1[r], alive[r], pr[r]);
+        }
+        round0_finish<MODE, STATS>(a, L, row, alive, pr, S, nprobe, nhit);
+        __syncthreads();
+        const uint32_t nb = S.cnt[0];   // block-uniform
+        if (nb > 0 && (nb > (uint32_t)(kBatch - kTile) || t + gridDim.x >= ntiles))
+            scan_flush<STATS>(a, S, nb, tot, nprobe, nhit, red);
+    };
+    prefetch(blockIdx.x, ka0, ka1);
+    for (uint32_t t = blockIdx.x; t < ntiles; t += 2 * gridDim.x) {
+        tile(t, ka0, ka1, kb0, kb1);
+        if (t + gridDim.x < ntiles) tile(t + gridDim.x, kb0, kb1, ka0, ka1);
+    }
+}
+
+// A node with no lookups: every live cover row is a result.
+template <bool STATS>
+__device__ __forceinline__ void scan_all(const ScanArgs &a, const ScanLds &S, u64 &tot, uint32_t &nprobe,
+                                         uint32_t &nhit, u64 *red) {
+    const uint32_t ntiles = (a.n + kTile - 1) / kTile;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint32_t tile0 = t * (uint32_t)kTile;
+        const uint32_t tn = min((uint32_t)kTile, a.n - tile0);
+        uint32_t row[kTileRows];
+        bool alive[kTileRows];
+        round0_rows(a, tile0, tn, row, alive);
+#pragma unroll
+        for (int r = 0; r < kTileRows; r++) {
+            const uint32_t b = list_slot(alive[r], &S.cnt[0]);
+            if (alive[r]) S.brow[b] = row[r];
+        }
+        __syncthreads();
+        const uint32_t nb = S.cnt[0];
+        if (nb > 0 && (nb > (uint32_t)(kBatch - kTile) || t + gridDim.x >= ntiles))
+            scan_flush<STATS>(a, S, nb, tot, nprobe, nhit, red);
+    }
 }
 
 template <bool STATS>
-__global__ void __launch_bounds__(256) k_scan_probe(ScanArgs a) {
+__global__ void __launch_bounds__(256, FJ_SCAN_WAVES) k_scan_probe(ScanArgs a) {
     StatusDev *status = a.status;
-    // child handles of the thread's live rows, per lookup
-    __shared__ uint32_t hs[kScanMaxLookups][256 * kScanRows];
-    const uint32_t first = (blockIdx.x * 256u + threadIdx.x) * kScanRows;
-    uint32_t row[kScanRows];
-    bool alive[kScanRows];
-    u64 mult[kScanRows];
+    extern __shared__ uint32_t bh[];
+    __shared__ uint32_t brow[kBatch];
+    __shared__ uint16_t lists[2 * kBatch];
+    __shared__ uint32_t cnt[kScanMaxLookups + 1];
+    __shared__ u64 red[17];
+    const ScanLds S{bh, brow, lists, cnt};
+    if (threadIdx.x <= kScanMaxLookups) cnt[threadIdx.x] = 0;
+    __syncthreads();
     uint32_t nprobe = 0, nhit = 0;
-#pragma unroll
-    for (int r = 0; r < kScanRows; r++) {
-        alive[r] = first + r < a.n;
-        mult[r] = 1;
-        row[r] = alive[r] ? a.r0 + first + r : 0u;
-    }
-    bool vec = a.vec;
-    if (a.sel) {
-#pragma unroll
-        for (int r = 0; r < kScanRows; r++) row[r] = alive[r] ? a.sel[row[r]] : 0u;
-        vec = false;
-    }
-#pragma unroll
-    for (int r = 0; r < kScanRows; r++) alive[r] = alive[r] && CK(row[r] < a.nrows);
-    if constexpr (kScanRows == 1) {
-        // every lookup's key columns first (independent loads), then the
-        // lookups in order, kScanSpec bucket loads in flight at a time
-        uint32_t k0[kScanMaxLookups], k1[kScanMaxLookups];
-#pragma unroll
-        for (int j = 0; j < kScanMaxLookups; j++) {
-            k0[j] = 0;
-            k1[j] = 0;
-            if (j < a.nl && alive[0]) {
-                const ScanLookup &L = a.lk[j];
-                k0[j] = (uint32_t)a.cols[L.kc[0]][row[0]];
-                if (L.mode != KM_K32) k1[j] = (uint32_t)a.cols[L.kc[1]][row[0]];
-            }
-        }
-#pragma unroll
-        for (int j0 = 0; j0 < kScanMaxLookups; j0 += kScanSpec) {
-            if (j0 >= a.nl || !__any(alive[0])) break;
-            const bool two = kScanSpec == 2 && j0 + 1 < a.nl;
-            RowProbe p0, p1;
-            probe_issue(a.lk[j0], k0[j0], k1[j0], alive[0], p0);
-            if (two) probe_issue(a.lk[j0 + 1], k0[j0 + 1], k1[j0 + 1], alive[0], p1);
-#pragma unroll
-            for (int h = 0; h < 2; h++) {
-                const int j = j0 + h;
-                if (h == 1 && !two) break;
-                const ScanLookup &L = a.lk[j];
-                if (!alive[0]) continue;
-                if (STATS) nprobe++;
-                uint32_t v = 0;
-                alive[0] = probe_resolve(L, h == 0 ? p0 : p1, v);
-                if (!alive[0]) continue;
-                if (!CK(v < L.cnpos)) { alive[0] = false; continue; }
-                if (STATS) nhit++;
-                hs[j][threadIdx.x] = v;
-                if (L.child_leaf) mult[0] *= L.clen[v];
-            }
-        }
-    }
-    // trie by trie over this thread's rows (Section 4.3's vectorized order)
-    for (int j = 0; j < a.nl && kScanRows > 1; j++) {
-        const ScanLookup &L = a.lk[j];
-        uint32_t val[kScanRows];
-        if (STATS) {
-#pragma unroll
-            for (int r = 0; r < kScanRows; r++) nprobe += alive[r];
-        }
-        if (L.mode == KM_K32) scan_round<KM_K32>(a, L, row, alive, vec, val);
-        else scan_round<KM_K64>(a, L, row, alive, vec, val);
-#pragma unroll
-        for (int r = 0; r < kScanRows; r++) {
-            if (!alive[r]) continue;
-            if (!CK(val[r] < L.cnpos)) { alive[r] = false; continue; }
-            if (STATS) nhit++;
-            hs[j][threadIdx.x * kScanRows + r] = val[r];
-            if (L.child_leaf) mult[r] *= L.clen[val[r]];
-        }
-    }
+    u64 tot = 0;
+    if (a.nl == 0) scan_all<STATS>(a, S, tot, nprobe, nhit, red);
+    else if (a.lk[0].mode == KM_K32) scan_tiles<KM_K32, STATS>(a, S, tot, nprobe, nhit, red);
+    else scan_tiles<KM_K64, STATS>(a, S, tot, nprobe, nhit, red);
     if (STATS) {
         u64 np = wave_sum_u64(nprobe), nh = wave_sum_u64(nhit);
         if (__lane_id() == 0 && (np | nh)) {
@@ -1278,43 +1418,7 @@ __global__ void __launch_bounds__(256) k_scan_probe(ScanArgs a) {
             atomicAdd(&a.status->hit[a.node], nh);
         }
     }
-    bool any = false;
-#pragma unroll
-    for (int r = 0; r < kScanRows; r++) any |= alive[r];
-    if (!__any(any)) return;   // the common case: no survivor in the whole wave
-    if (a.emit) {
-        u64 tot = 0;
-#pragma unroll
-        for (int r = 0; r < kScanRows; r++) {
-            if (!alive[r]) continue;
-            u64 e = mult[r];
-            for (int q = 0; q < a.ntail; q++) {
-                if (a.tail_lk[q] < 0) { e *= a.tail_root_len[q]; continue; }
-                const uint32_t th = hs[a.tail_lk[q]][threadIdx.x * kScanRows + r];
-                if (!CK(th < a.tail_npos[q])) { e = 0; break; }
-                e *= a.tail_len[q][th];
-            }
-            tot += e;
-        }
-        // one atomic per wave, spread over the partial counters
-        tot = wave_sum_u64(tot);
-        if (__lane_id() == 0 && tot)
-            atomicAdd(&status->count_part[((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % kCountParts) *
-                                          kPartStride],
-                      tot);
-    }
-    if (!a.emit || a.materialize) {
-#pragma unroll
-        for (int r = 0; r < kScanRows; r++) {
-            const u64 pos = wave_reserve(alive[r], &a.status->survivors) - a.surv_base;
-            if (!alive[r] || !CK(pos < a.out.cap)) continue;
-            const FrontierDev &O = a.out;
-            for (int j = 0; j < a.nout; j++) O.vals[(u64)j * O.cap + pos] = a.cols[a.out_col[j]][row[r]];
-            for (int j = 0; j < a.nl; j++)
-                if (a.lk[j].hcol >= 0) O.hdl[(u64)a.lk[j].hcol * O.cap + pos] = hs[j][threadIdx.x * kScanRows + r];
-            if (O.mult) O.mult[pos] = mult[r];
-        }
-    }
+    if (a.emit) block_add_count(tot, status, red);
 }
 
 // ------------------------------------------------------------------- emit
@@ -1406,12 +1510,6 @@ hipError_t launch_fill_u32(uint32_t *p, u64 n, uint32_t v, hipStream_t s) {
     if (!n) return hipSuccess;
     unsigned b = (unsigned)std::min<u64>(blocks_for(n, 256), 65535);
     hipLaunchKernelGGL(k_fill<uint32_t>, dim3(b), dim3(256), 0, s, p, n, v);
-    return hipGetLastError();
-}
-
-hipError_t launch_table_init(void *table, u64 nslots, int mode, hipStream_t s) {
-    unsigned b = (unsigned)std::min<u64>(blocks_for(nslots, 256), 65535);
-    hipLaunchKernelGGL(k_table_init, dim3(b), dim3(256), 0, s, table, nslots, mode);
     return hipGetLastError();
 }
 
@@ -1552,18 +1650,22 @@ hipError_t launch_emit_rows(const void *emit_dev, uint32_t E, const u64 *starts,
 hipError_t launch_scan_probe(const ScanLaunch &l, hipStream_t s) {
     if (l.nl > kScanMaxLookups) return hipErrorInvalidValue;
     if (l.n == 0) return hipSuccess;
+    if (l.nrows == 0) return hipErrorInvalidValue;   // positions into an empty relation
     ScanArgs a;
     memset(&a, 0, sizeof(a));
     for (int c = 0; c < FJ_MAX_COLS; c++) a.cols[c] = l.cols[c];
     a.ncols = l.ncols; a.sel = l.sel; a.nrows = l.nrows; a.r0 = l.r0; a.n = l.n;
-    // 4-row vector loads need 16-byte aligned columns and a 4-aligned start
-    a.vec = kScanRows == 4 && (l.r0 % 4) == 0;
+    // without a selection, positions are rows: they must exist
+    if (!l.sel && (u64)l.r0 + l.n > l.nrows) return hipErrorInvalidValue;
+    // 4-row vector loads: rows in bounds (no selection), 16-byte aligned
+    // columns and a 4-aligned start
+    a.vec = !l.sel && (l.r0 % 4) == 0;
     for (int c = 0; c < l.ncols; c++) a.vec = a.vec && ((uintptr_t)l.cols[c] % 16) == 0;
     a.nl = l.nl;
     for (int j = 0; j < l.nl; j++) {
+        // KM_K32 hits are kept as 32-bit slot numbers
+        if (l.lk[j].mode == KM_K32 && l.lk[j].mask >= 0xFFFFFFFFull) return hipErrorInvalidValue;
         a.lk[j] = l.lk[j];
-        a.keycol[l.lk[j].kc[0]] = 1;
-        if (l.lk[j].mode == KM_K64) a.keycol[l.lk[j].kc[1]] = 1;
     }
     a.nout = l.nout;
     for (int j = 0; j < l.nout; j++) a.out_col[j] = l.out_col[j];
@@ -1574,10 +1676,30 @@ hipError_t launch_scan_probe(const ScanLaunch &l, hipStream_t s) {
         a.tail_npos[q] = l.tail_npos[q]; a.tail_root_len[q] = l.tail_root_len[q];
     }
     a.status = l.status; a.count_stats = l.count_stats; a.node = l.node; a.surv_base = l.surv_base;
+    // persistent workgroups: as many as are resident at once, at most one
+    // per tile
+    constexpr int kMaxDevices = 64;
+    const size_t lds = (size_t)l.nl * kBatch * sizeof(uint32_t);
+    const void *fn = l.count_stats ? (const void *)k_scan_probe<true> : (const void *)k_scan_probe<false>;
+    static int resident[2][kScanMaxLookups + 1][kMaxDevices];   // 0: not known yet
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    int &res = resident[l.count_stats ? 1 : 0][l.nl][dev];
+    if (res == 0) {
+        int per_cu = 0, cus = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        res = std::max(1, per_cu) * std::max(1, cus);
+    }
+    const unsigned grid = (unsigned)std::min<u64>(blocks_for(l.n, kTile), (u64)res);
     if (l.count_stats)
-        hipLaunchKernelGGL(k_scan_probe<true>, dim3(blocks_for(l.n, 256 * kScanRows)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_scan_probe<true>, dim3(grid), dim3(256), lds, s, a);
     else
-        hipLaunchKernelGGL(k_scan_probe<false>, dim3(blocks_for(l.n, 256 * kScanRows)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_scan_probe<false>, dim3(grid), dim3(256), lds, s, a);
     return hipGetLastError();
 }
 

@@ -76,7 +76,6 @@ hipError_t launch_batch_dfs(const BQuery *qs, const BItem *items, uint32_t nitem
                             StatusDev *status, int block, int grid, int lv, int la, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, uint32_t n, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, unsigned long long n, uint32_t v, hipStream_t s);
-hipError_t launch_table_init(void *table, unsigned long long nslots, int mode, hipStream_t s);
 hipError_t launch_fill_list(const FillList *fl_dev, unsigned long long total_words, const LevelDev &root,
                             uint32_t nroot, uint32_t *pre, hipStream_t s);
 hipError_t launch_scan_u64(const unsigned long long *in, unsigned long long *out, unsigned long long n,
