@@ -203,7 +203,8 @@ struct fj_colt {
     int lev_nk[fj::kMaxLevels] = {0};
     int lev_var[fj::kMaxLevels][FJ_MAX_COLS] = {{0}};
     LevelDev lev[fj::kMaxLevels + 1];
-    u64 table_slots[fj::kMaxLevels] = {0};
+    u64 table_slots[fj::kMaxLevels] = {0};   // slots of each level's map in use (reserved slot included)
+    u64 table_cap[fj::kMaxLevels] = {0};     // slots each level's map was allocated for
     // Regions a (re)build initialises: the root level's counters and map and
     // every level's state words.  An inner level's counters and map are
     // initialised before its first force after a rebuild (lev_ready).
@@ -214,6 +215,7 @@ struct fj_colt {
     fj::FillList *fill_lev_dev[fj::kMaxLevels] = {nullptr};
     u64 fill_lev_words[fj::kMaxLevels] = {0};
     bool lev_ready[fj::kMaxLevels] = {false};
+    bool fill_stale = true;   // the device copies of the fill lists are out of date
     std::vector<void *> allocs;
 };
 
@@ -224,6 +226,14 @@ int key_mode(int level, int nk) {
     if (level == 0 && nk == 1) return fj::KM_K32;
     if ((level == 0 && nk == 2) || (level > 0 && nk == 1)) return fj::KM_K64;
     return fj::KM_REP;
+}
+
+// Map capacity for at most `rows` keys: a power of two of at least twice the
+// rows, so linear probing always ends at an empty slot.
+u64 map_cap(u64 rows) {
+    u64 cap = 16;
+    while (cap < 2 * rows) cap <<= 1;
+    return cap;
 }
 
 size_t slot_bytes(int mode) {
@@ -271,11 +281,12 @@ fj_status colt_allocate(fj_colt *t) {
         L.nk = t->lev_nk[l];
         L.mode = key_mode(l, L.nk);
         if (L.mode != fj::KM_ZERO) {
-            u64 cap = 16;
-            while (cap < 2 * (u64)n) cap <<= 1;
+            // sized for the capacity; each (re)build uses the part its rows need
+            const u64 cap = map_cap(n);
             L.mask = cap - 1;
             L.nslots = cap + 1;
             t->table_slots[l] = cap + 1;
+            t->table_cap[l] = cap;
             char *tb = nullptr;
             FJ_TRY(colt_alloc(t, &tb, L.mode == fj::KM_K32 ? fj::k32_table_words(cap) * sizeof(uint32_t)
                                                            : (cap + 1) * slot_bytes(L.mode)));
@@ -360,9 +371,10 @@ static fj_status force_queue(fj_ctx *c, fj_colt *t, int l, uint32_t nh, u64 W_kn
 
 // The regions a (re)build initialises (the root level's counters and map,
 // every level's state words) and, per inner level, the counters and map its
-// first force initialises.  Map slots start empty, the reserved slot
-// unclaimed.
-static fj_status colt_fill_list(fj_colt *t) {
+// first force initialises, for a root over `rows` rows: positions past them
+// are never touched.  Map slots start empty, the reserved slot unclaimed.
+// Host lists only (colt_fill_upload copies them to the device).
+static fj_status colt_fill_list(fj_colt *t, u64 rows) {
     bool overflow = false;
     auto add = [&](fj::FillList &fl, u64 &total, uint32_t *p, u64 nwords, std::initializer_list<uint32_t> pat) {
         if (!p || !nwords) return;
@@ -378,7 +390,7 @@ static fj_status colt_fill_list(fj_colt *t) {
         for (uint32_t v : pat) r.pat[i++] = v;
         total += nwords;
     };
-    const u64 n = std::max<uint32_t>(t->cap_rows, 1);
+    const u64 n = std::max<u64>(std::min<u64>(rows, t->cap_rows), 1);
     memset(&t->fill_h, 0, sizeof(t->fill_h));
     t->fill_words = 0;
     for (int l = 0; l < t->nlev; l++) {
@@ -409,15 +421,43 @@ static fj_status colt_fill_list(fj_colt *t) {
         }
     }
     if (overflow) return fail(FJ_ERR_UNSUPPORTED, "too many COLT levels");
-    fj::FillList *d = nullptr;
-    FJ_TRY(colt_alloc(t, &d, 1));
-    FJ_HIP(hipMemcpy(d, &t->fill_h, sizeof(t->fill_h), hipMemcpyHostToDevice));
-    t->fill_dev = d;
+    return FJ_OK;
+}
+
+// Size every level's map for the rows the root now ranges over (within the
+// capacity it was allocated for) and recompute the fill lists; the device
+// copies are marked stale when they change.
+static fj_status colt_size(fj_colt *t) {
+    const u64 rows = std::max<uint32_t>(t->nroot, 1);
+    for (int l = 0; l < t->nlev; l++) {
+        LevelDev &L = t->lev[l];
+        if (!L.table) continue;
+        const u64 cap = std::min(map_cap(rows), t->table_cap[l]);
+        L.mask = cap - 1;
+        L.nslots = cap + 1;
+        t->table_slots[l] = cap + 1;
+    }
+    const fj::FillList old = t->fill_h;
+    std::vector<fj::FillList> old_lev(t->fill_lev_h, t->fill_lev_h + fj::kMaxLevels);
+    FJ_TRY(colt_fill_list(t, rows));
+    if (memcmp(&old, &t->fill_h, sizeof(old)) != 0 ||
+        memcmp(old_lev.data(), t->fill_lev_h, sizeof(fj::FillList) * fj::kMaxLevels) != 0)
+        t->fill_stale = true;
+    return FJ_OK;
+}
+
+// Device copies of the fill lists, (re)written when stale.  Rare (the rows
+// changed): waits for the work queued so far, which may still read them.
+static fj_status colt_fill_upload(fj_ctx *c, fj_colt *t) {
+    if (!t->fill_stale) return FJ_OK;
+    FJ_HIP(hipStreamSynchronize(c->stream));
+    if (!t->fill_dev) FJ_TRY(colt_alloc(t, &t->fill_dev, 1));
+    FJ_HIP(hipMemcpy(t->fill_dev, &t->fill_h, sizeof(t->fill_h), hipMemcpyHostToDevice));
     for (int l = 1; l < t->nlev; l++) {
-        if (!t->fill_lev_words[l]) continue;
-        FJ_TRY(colt_alloc(t, &t->fill_lev_dev[l], 1));
+        if (!t->fill_lev_dev[l]) FJ_TRY(colt_alloc(t, &t->fill_lev_dev[l], 1));
         FJ_HIP(hipMemcpy(t->fill_lev_dev[l], &t->fill_lev_h[l], sizeof(fj::FillList), hipMemcpyHostToDevice));
     }
+    t->fill_stale = false;
     return FJ_OK;
 }
 
@@ -435,6 +475,8 @@ static fj_status colt_level_ready(fj_ctx *c, fj_colt *t, int l) {
 }
 
 static fj_status colt_reset(fj_ctx *c, fj_colt *t) {
+    FJ_TRY(colt_size(t));
+    FJ_TRY(colt_fill_upload(c, t));
     for (int l = 0; l <= t->nlev; l++) t->lev[l].nrows = (uint32_t)t->nrows;
     for (int l = 0; l < t->nlev; l++) t->lev_ready[l] = false;
     LevelDev &R = t->lev[0];
@@ -495,7 +537,7 @@ static void destroy_group(ColtGroup *g) {
 
 namespace {
 
-constexpr u64 kFillChunk = 65536;   // words per fill block
+constexpr u64 kFillChunk = 4096;   // words per fill block
 
 // Lay out and upload the group's descriptors for the COLTs' current
 // relations; wcap_min sizes the scratch (at least the current total).
@@ -807,11 +849,24 @@ fj_status fj_filter_lt_batch(fj_ctx *c, int32_t n, const int32_t *const *cols, c
     FJ_TRY(c->scanb.ensure(off[n] + 256, c->stream));
     FJ_TRY(zero_status_field(c, offsetof(StatusDev, ftotal), sizeof(c->status_h->ftotal)));
     {
+        // the non-empty selections in one grouped pass of three launches
+        const int32_t *gc[FJ_MAX_ATOMS];
+        u64 gr[FJ_MAX_ATOMS];
+        int32_t gb[FJ_MAX_ATOMS];
+        uint32_t *go[FJ_MAX_ATOMS], *gs[FJ_MAX_ATOMS], *gt[FJ_MAX_ATOMS];
+        int m = 0;
+        for (int i = 0; i < n; i++) {
+            if (nrows[i] <= 0) continue;
+            gc[m] = cols[i];
+            gr[m] = (u64)nrows[i];
+            gb[m] = bounds[i];
+            go[m] = outs[i];
+            gs[m] = c->scanb.as<uint32_t>(off[i]);
+            gt[m] = &c->status_d->ftotal[i];
+            m++;
+        }
         Timer t(c, FJ_T_FILTER);
-        for (int i = 0; i < n; i++)
-            if (nrows[i] > 0)
-                FJ_HIP(fj::launch_filter_lt(cols[i], (u64)nrows[i], bounds[i], outs[i], c->scanb.as<uint32_t>(off[i]),
-                                            &c->status_d->ftotal[i], c->stream));
+        FJ_HIP(fj::launch_filter_lt_group(m, gc, gr, gb, go, gs, gt, c->stream));
     }
     FJ_TRY(sync_status(c));
     for (int i = 0; i < n; i++) counts[i] = (int64_t)c->status_h->ftotal[i];
@@ -899,8 +954,7 @@ fj_status fj_build_colt(fj_ctx *c, const fj_query *q, const fj_plan *p, int32_t 
             for (int j = 0; j < t->lev_nk[l]; j++)
                 for (int cc = 0; cc < q->atoms[atom].arity; cc++)
                     if (q->atoms[atom].vars[cc] == t->lev_var[l][j]) t->lev[l].kcol[j] = cc;
-        st = colt_fill_list(t);
-        if (st == FJ_OK) st = colt_reset(c, t);
+        st = colt_reset(c, t);
         if (st == FJ_OK) st = sync_status(c);
     }
     if (st != FJ_OK) {
@@ -949,6 +1003,8 @@ fj_status fj_colt_rebuild_many(fj_ctx *c, int32_t n, fj_colt *const *colts, cons
         t->sel = r.sel;
         t->nrows = r.nrows;
         t->nroot = (uint32_t)(r.sel ? r.nsel : r.nrows);
+        FJ_TRY(colt_size(t));
+        FJ_TRY(colt_fill_upload(c, t));
     }
     if (!c->group) c->group = new ColtGroup();
     FJ_TRY(group_prepare(c, *c->group, colts, n, 0));
@@ -1012,7 +1068,11 @@ fj_status force_pending_queues(Exec &x, int node, const std::vector<std::pair<in
 
 fj_status emit_rows(Exec &x, uint32_t E) {
     // materialize the result rows of E final bindings in frontier F[tail_from]
+    // the emit's place in the output is decided on the device, so no wait
+    // here; the host copy of the status is as fresh as the caller's last
+    // sync, which came after every earlier emit
     fj_ctx *c = x.c;
+    x.written = c->status_h->written;
     if (!x.out || E == 0 || x.written >= x.cap) return FJ_OK;
     u64 *cnt = c->emitbuf.as<u64>();
     u64 *starts = c->emitbuf.as<u64>(align256(sizeof(u64) * x.C));
@@ -1020,15 +1080,16 @@ fj_status emit_rows(Exec &x, uint32_t E) {
         Timer t(c, FJ_T_EMIT);
         FJ_HIP(fj::launch_emit_count(x.emit_d, E, cnt, c->status_d, c->stream));
     }
-    FJ_TRY(scan_u64(c, cnt, starts, E));
-    FJ_TRY(sync_status(c));
-    u64 total = c->status_h->total;
-    u64 rows = std::min<u64>(total, x.cap - x.written);
+    {
+        size_t nb = (E + 1023) / 1024 + 1;
+        FJ_TRY(c->scanb.ensure(nb * sizeof(u64), c->stream));
+        Timer t(c, FJ_T_SCAN);
+        FJ_HIP(fj::launch_scan_u64_emit(cnt, starts, E, c->scanb.as<u64>(), c->status_d, x.cap, c->stream));
+    }
     {
         Timer t(c, FJ_T_EMIT);
-        FJ_HIP(fj::launch_emit_rows(x.emit_d, E, starts, rows, x.written, c->status_d, c->stream));
+        FJ_HIP(fj::launch_emit_rows(x.emit_d, E, starts, x.cap - x.written, c->status_d, c->stream));
     }
-    x.written += rows;
     return FJ_OK;
 }
 
@@ -1455,6 +1516,7 @@ extern "C" fj_status fj_execute(fj_ctx *c, const fj_query *q, const fj_plan *p, 
     }
     if (st != FJ_OK) return st;
     FJ_TRY(sync_status(c));
+    x.written = c->status_h->written;
     u64 total = c->status_h->count;
     for (int q = 0; q < fj::kCountParts; q++) total += c->status_h->count_part[q * fj::kPartStride];
     *count = total;

@@ -242,6 +242,9 @@ struct StatusDev {
     unsigned long long survivors;  // rows written to the output frontier by the last launch
     unsigned long long deferred;   // tuples waiting for a lazy force
     unsigned long long total;      // scan totals
+    unsigned long long written;    // result rows materialized so far
+    unsigned long long emit_base;  // the current emit's first output row
+    unsigned long long emit_rows;  // the current emit's rows (within the output capacity)
     unsigned long long probe[FJ_MAX_NODES];
     unsigned long long hit[FJ_MAX_NODES];
     uint32_t fq_n[FJ_MAX_ATOMS * kMaxLevels];  // force-queue lengths per (atom, level)

@@ -342,6 +342,32 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_blocks(T *bsum, u64 nb, T
     }
 }
 
+// The block-sum scan of an emit's per-binding row counts, which also places
+// the emit in the output: its first row follows the rows written so far and
+// its row count is cut to the output's capacity.
+__global__ void __launch_bounds__(kScanThreads) k_scan_blocks_emit(u64 *bsum, u64 nb, u64 *out_last,
+                                                                   StatusDev *st, u64 cap) {
+    __shared__ u64 lds[17];
+    u64 carry = 0;
+    for (u64 c = 0; c < nb; c += kScanThreads) {
+        u64 i = c + threadIdx.x;
+        u64 v = i < nb ? bsum[i] : 0;
+        u64 tot;
+        u64 ex = block_excl_scan<u64>(v, lds, tot);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        *out_last = carry;
+        st->total = carry;
+        const u64 base = st->written;
+        const u64 rows = base < cap ? (carry < cap - base ? carry : cap - base) : 0;
+        st->emit_base = base;
+        st->emit_rows = rows;
+        st->written = base + rows;
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const T *in, T *out, u64 n, const T *bsum) {
     __shared__ T lds[17];
@@ -400,6 +426,69 @@ __global__ void __launch_bounds__(256) k_filter_write(const int32_t *__restrict_
     const uint32_t bits = filter_bits(col, n, bound, first, vec);
     uint32_t tot;
     uint32_t pos = bsum[blockIdx.x] + block_excl_scan<uint32_t>((uint32_t)__popc(bits), lds, tot);
+    for (int r = 0; r < kFilterRows; r++)
+        if (bits & (1u << r)) out[pos++] = (uint32_t)(first + r);
+}
+
+// Many selections in three launches: block b of a grouped launch belongs to
+// selection i with bpre[i] <= b < bpre[i + 1] and is its block b - bpre[i];
+// the middle launch scans each selection's block sums in a workgroup of its
+// own.
+struct FilterGroup {
+    int n;
+    const int32_t *col[FJ_MAX_ATOMS];
+    unsigned long long rows[FJ_MAX_ATOMS];
+    int32_t bound[FJ_MAX_ATOMS];
+    int vec[FJ_MAX_ATOMS];
+    uint32_t *out[FJ_MAX_ATOMS];
+    uint32_t *bsum[FJ_MAX_ATOMS];
+    uint32_t *total[FJ_MAX_ATOMS];
+    uint32_t bpre[FJ_MAX_ATOMS + 1];
+};
+
+__device__ __forceinline__ int filter_member(const FilterGroup &g, uint32_t b) {
+    int i = 0;
+    while (i + 1 < g.n && g.bpre[i + 1] <= b) i++;
+    return i;
+}
+
+__global__ void __launch_bounds__(256) k_filter_count_group(FilterGroup g) {
+    __shared__ uint32_t lds[17];
+    const int i = filter_member(g, blockIdx.x);
+    const uint32_t b = blockIdx.x - g.bpre[i];
+    const u64 first = ((u64)b * 256 + threadIdx.x) * kFilterRows;
+    const uint32_t bits = filter_bits(g.col[i], g.rows[i], g.bound[i], first, g.vec[i]);
+    uint32_t tot;
+    block_excl_scan<uint32_t>((uint32_t)__popc(bits), lds, tot);
+    if (threadIdx.x == 0) g.bsum[i][b] = tot;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_filter_scan_group(FilterGroup g) {
+    __shared__ uint32_t lds[17];
+    const int i = blockIdx.x;
+    uint32_t *bsum = g.bsum[i];
+    const u64 nb = g.bpre[i + 1] - g.bpre[i];
+    uint32_t carry = 0;
+    for (u64 c = 0; c < nb; c += kScanThreads) {
+        const u64 k = c + threadIdx.x;
+        const uint32_t v = k < nb ? bsum[k] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<uint32_t>(v, lds, tot);
+        if (k < nb) bsum[k] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *g.total[i] = carry;
+}
+
+__global__ void __launch_bounds__(256) k_filter_write_group(FilterGroup g) {
+    __shared__ uint32_t lds[17];
+    const int i = filter_member(g, blockIdx.x);
+    const uint32_t b = blockIdx.x - g.bpre[i];
+    const u64 first = ((u64)b * 256 + threadIdx.x) * kFilterRows;
+    const uint32_t bits = filter_bits(g.col[i], g.rows[i], g.bound[i], first, g.vec[i]);
+    uint32_t tot;
+    uint32_t pos = g.bsum[i][b] + block_excl_scan<uint32_t>((uint32_t)__popc(bits), lds, tot);
+    uint32_t *out = g.out[i];
     for (int r = 0; r < kFilterRows; r++)
         if (bits & (1u << r)) out[pos++] = (uint32_t)(first + r);
 }
@@ -1467,11 +1556,8 @@ __global__ void __launch_bounds__(256) k_emit_count(const EmitDev *__restrict__ 
     cnt[e] = v;
 }
 
-__global__ void __launch_bounds__(256) k_emit_rows(const EmitDev *__restrict__ dp, uint32_t E, const u64 *starts,
-                                                   u64 nrows, u64 base, StatusDev *status) {
-    const EmitDev &d = *dp;
-    u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrows) return;
+__device__ __forceinline__ void emit_row(const EmitDev &d, uint32_t E, const u64 *starts, u64 base, u64 r,
+                                         StatusDev *status) {
     uint32_t e = E == 1 ? 0u : upper_entry(starts, 0, E, r);
     if (!CK(e < E && e < d.F.cap && r >= starts[e] && r < starts[e + 1] && base + r < d.out_rows)) return;
     u64 idx = r - starts[e];
@@ -1500,6 +1586,15 @@ __global__ void __launch_bounds__(256) k_emit_rows(const EmitDev *__restrict__ d
             o[j] = T.cols[T.kcol[c]][rows[q]];
         }
     }
+}
+
+// Rows [0, emit_rows) of the current emit, at output rows emit_base + r
+// (both set on the device by the emit's scan), grid-stride.
+__global__ void __launch_bounds__(256) k_emit_rows(const EmitDev *__restrict__ dp, uint32_t E, const u64 *starts,
+                                                   StatusDev *status) {
+    const u64 nrows = status->emit_rows, base = status->emit_base;
+    for (u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += (u64)gridDim.x * blockDim.x)
+        emit_row(*dp, E, starts, base, r, status);
 }
 
 // ------------------------------------------------------------- launchers
@@ -1553,6 +1648,34 @@ hipError_t launch_filter_lt(const int32_t *col, u64 n, int32_t bound, uint32_t *
                        (uint32_t *)nullptr);
     hipLaunchKernelGGL(k_filter_write, dim3((unsigned)nb), dim3(256), 0, s, col, n, bound, vec, (const uint32_t *)bsum,
                        out);
+    return hipGetLastError();
+}
+
+hipError_t launch_filter_lt_group(int n, const int32_t *const *cols, const u64 *rows, const int32_t *bounds,
+                                  uint32_t *const *outs, uint32_t *const *bsums, uint32_t *const *totals,
+                                  hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (n > FJ_MAX_ATOMS) return hipErrorInvalidValue;
+    FilterGroup g;
+    memset(&g, 0, sizeof(g));
+    g.n = n;
+    u64 nb = 0;
+    for (int i = 0; i < n; i++) {
+        g.col[i] = cols[i];
+        g.rows[i] = rows[i];
+        g.bound[i] = bounds[i];
+        g.vec[i] = ((uintptr_t)cols[i] % 16) == 0;
+        g.out[i] = outs[i];
+        g.bsum[i] = bsums[i];
+        g.total[i] = totals[i];
+        g.bpre[i] = (uint32_t)nb;
+        nb += std::max<u64>((rows[i] + kFilterBlock - 1) / kFilterBlock, 1);
+    }
+    if (nb > 0x7fffffffu) return hipErrorInvalidValue;
+    g.bpre[n] = (uint32_t)nb;
+    hipLaunchKernelGGL(k_filter_count_group, dim3((unsigned)nb), dim3(256), 0, s, g);
+    hipLaunchKernelGGL(k_filter_scan_group, dim3((unsigned)n), dim3(kScanThreads), 0, s, g);
+    hipLaunchKernelGGL(k_filter_write_group, dim3((unsigned)nb), dim3(256), 0, s, g);
     return hipGetLastError();
 }
 
@@ -1639,11 +1762,21 @@ hipError_t launch_emit_count(const void *emit_dev, uint32_t E, u64 *cnt, StatusD
     return hipGetLastError();
 }
 
-hipError_t launch_emit_rows(const void *emit_dev, uint32_t E, const u64 *starts, u64 nrows, u64 base,
-                            StatusDev *st, hipStream_t s) {
-    if (!nrows) return hipSuccess;
-    hipLaunchKernelGGL(k_emit_rows, dim3(blocks_for(nrows, 256)), dim3(256), 0, s, (const EmitDev *)emit_dev, E,
-                       starts, nrows, base, st);
+hipError_t launch_emit_rows(const void *emit_dev, uint32_t E, const u64 *starts, u64 max_rows, StatusDev *st,
+                            hipStream_t s) {
+    if (!max_rows) return hipSuccess;
+    const unsigned grid = (unsigned)std::min<u64>(blocks_for(max_rows, 256), 2048);
+    hipLaunchKernelGGL(k_emit_rows, dim3(grid), dim3(256), 0, s, (const EmitDev *)emit_dev, E, starts, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_u64_emit(const u64 *in, u64 *out, u64 n, u64 *bsum, StatusDev *st, u64 cap, hipStream_t s) {
+    if (n == 0) return hipErrorInvalidValue;
+    const u64 nb = (n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan_reduce<u64>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, bsum);
+    hipLaunchKernelGGL(k_scan_blocks_emit, dim3(1), dim3(kScanThreads), 0, s, bsum, nb, out + n, st, cap);
+    hipLaunchKernelGGL(k_scan_apply<u64>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n,
+                       (const u64 *)bsum);
     return hipGetLastError();
 }
 

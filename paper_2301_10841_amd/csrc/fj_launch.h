@@ -84,6 +84,12 @@ hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, unsigned long long
                            uint32_t *total, hipStream_t s);
 hipError_t launch_filter_lt(const int32_t *col, unsigned long long n, int32_t bound, uint32_t *out,
                             uint32_t *bsum, uint32_t *total, hipStream_t s);
+// Selections of n columns (each with its own bound, output and block-sum
+// scratch of rows / 1024 + 1 words) in three launches; totals[i] receives
+// selection i's row count.
+hipError_t launch_filter_lt_group(int n, const int32_t *const *cols, const unsigned long long *rows,
+                                  const int32_t *bounds, uint32_t *const *outs, uint32_t *const *bsums,
+                                  uint32_t *const *totals, hipStream_t s);
 hipError_t launch_fq_lens(const LevelDev &L, const uint32_t *fq, uint32_t nh, uint32_t *lens, StatusDev *st,
                           hipStream_t s);
 hipError_t launch_force_phase(int phase, const ForceLaunch &f, hipStream_t s);
@@ -97,8 +103,15 @@ hipError_t launch_cover_fill(const NodeDev *nd, uint32_t E, const uint8_t *cov, 
 hipError_t launch_probe(const ProbeLaunch &p, hipStream_t s);
 hipError_t launch_emit_count(const void *emit_dev, uint32_t E, unsigned long long *cnt, StatusDev *st,
                              hipStream_t s);
+// Rows of the current emit (placed on the device by launch_scan_u64_emit),
+// grid-stride over at most max_rows.
 hipError_t launch_emit_rows(const void *emit_dev, uint32_t E, const unsigned long long *starts,
-                            unsigned long long nrows, unsigned long long base, StatusDev *st, hipStream_t s);
+                            unsigned long long max_rows, StatusDev *st, hipStream_t s);
+// Exclusive scan of an emit's n > 0 row counts that also places the emit in
+// the output: st->emit_base = st->written, st->emit_rows = the total cut to
+// cap rows, st->written advanced.
+hipError_t launch_scan_u64_emit(const unsigned long long *in, unsigned long long *out, unsigned long long n,
+                                unsigned long long *bsum, StatusDev *st, unsigned long long cap, hipStream_t s);
 size_t emit_dev_size();
 void emit_dev_fill(void *host_buf, const FrontierDev &F, const int *in_var, int nin, const int *in_h_atom,
                    int nin_h, const TailDev *tails, int ntail, const int *head_src, int nhead, int32_t *out,
