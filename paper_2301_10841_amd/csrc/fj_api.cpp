@@ -1076,11 +1076,15 @@ fj_status emit_rows(Exec &x, uint32_t E) {
     if (!x.out || E == 0 || x.written >= x.cap) return FJ_OK;
     u64 *cnt = c->emitbuf.as<u64>();
     u64 *starts = c->emitbuf.as<u64>(align256(sizeof(u64) * x.C));
-    {
+    if (E <= fj::emit_small_max()) {
+        // few bindings: counts, scan and placement in one launch
         Timer t(c, FJ_T_EMIT);
-        FJ_HIP(fj::launch_emit_count(x.emit_d, E, cnt, c->status_d, c->stream));
-    }
-    {
+        FJ_HIP(fj::launch_emit_count_small(x.emit_d, E, starts, c->status_d, x.cap, c->stream));
+    } else {
+        {
+            Timer t(c, FJ_T_EMIT);
+            FJ_HIP(fj::launch_emit_count(x.emit_d, E, cnt, c->status_d, c->stream));
+        }
         size_t nb = (E + 1023) / 1024 + 1;
         FJ_TRY(c->scanb.ensure(nb * sizeof(u64), c->stream));
         Timer t(c, FJ_T_SCAN);

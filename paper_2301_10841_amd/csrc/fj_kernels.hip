@@ -82,23 +82,31 @@ __device__ __forceinline__ u64 table_find(const LevelDev &L, const int32_t *cons
         const uint32_t *T = (const uint32_t *)L.table;
         uint32_t key = (uint32_t)k.v[0];
         if (key == kEmpty32) return T[k32_key_word(mask + 1)] ? mask + 1 : ~0ull;
-        u64 i = k32_bucket(mix32(key), mask);
-        for (u64 n = 0; n <= mask; n++) {
-            uint32_t c = T[k32_key_word(i)];
-            if (c == key) return i;
-            if (c == kEmpty32) return ~0ull;
-            i = (i + 1) & mask;
+        // a bucket's four keys in one 16-byte load, then the next bucket
+        u64 b = k32_bucket(mix32(key), mask);
+        for (u64 n = 0; n <= mask; n += kK32Bucket) {
+            const uint4 q = *(const uint4 *)(T + k32_key_word(b));
+            const uint32_t ks[kK32Bucket] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int s = 0; s < kK32Bucket; s++) {
+                if (ks[s] == key) return b + s;
+                if (ks[s] == kEmpty32) return ~0ull;
+            }
+            b = (b + kK32Bucket) & mask;
         }
     } else if (L.mode == KM_K64) {
         const Slot64 *T = (const Slot64 *)L.table;
         u64 key = pack64(L, k);
         if (key == kEmpty64) return T[mask + 1].key ? mask + 1 : ~0ull;
-        u64 i = bucket_start<Slot64>(mix64(key), mask);
-        for (u64 n = 0; n <= mask; n++) {
-            u64 c = T[i].key;
-            if (c == key) return i;
-            if (c == kEmpty64) return ~0ull;
-            i = (i + 1) & mask;
+        // a bucket's two slots in one 32-byte read, then the next bucket
+        u64 b = bucket_start<Slot64>(mix64(key), mask);
+        for (u64 n = 0; n <= mask; n += 2) {
+            const u64 c0 = T[b].key, c1 = T[b + 1].key;
+            if (c0 == key) return b;
+            if (c0 == kEmpty64) return ~0ull;
+            if (c1 == key) return b + 1;
+            if (c1 == kEmpty64) return ~0ull;
+            b = (b + 2) & mask;
         }
     } else {
         const SlotRep *T = (const SlotRep *)L.table;
@@ -144,13 +152,24 @@ __device__ __forceinline__ u64 table_insert(const LevelDev &L, const int32_t *co
             claimed = atomicCAS(&T[k32_key_word(mask + 1)], 0u, 1u) == 0u;
             return mask + 1;
         }
-        u64 i = k32_bucket(mix32(key), mask);
-        for (u64 n = 0; n <= mask; n++) {
-            // the compare-and-swap returns the occupant: no separate read
-            const uint32_t old = atomicCAS(&T[k32_key_word(i)], kEmpty32, key);
-            if (old == kEmpty32) { claimed = true; return i; }
-            if (old == key) return i;
-            i = (i + 1) & mask;
+        // read a bucket's keys (one 16-byte load), then compare-and-swap
+        // only the first slot seen empty; the read may be stale, but slots
+        // only ever go from empty to a key and the swap returns the true
+        // occupant, so a lost race just moves on in slot order
+        u64 b = k32_bucket(mix32(key), mask);
+        for (u64 n = 0; n <= mask; n += kK32Bucket) {
+            const uint4 q = *(const uint4 *)(T + k32_key_word(b));
+            const uint32_t ks[kK32Bucket] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int s = 0; s < kK32Bucket; s++) {
+                uint32_t c = ks[s];
+                if (c == kEmpty32) {
+                    c = atomicCAS(&T[k32_key_word(b + s)], kEmpty32, key);
+                    if (c == kEmpty32) { claimed = true; return b + s; }
+                }
+                if (c == key) return b + s;
+            }
+            b = (b + kK32Bucket) & mask;
         }
     } else if (L.mode == KM_K64) {
         Slot64 *T = (Slot64 *)L.table;
@@ -159,12 +178,20 @@ __device__ __forceinline__ u64 table_insert(const LevelDev &L, const int32_t *co
             claimed = atomicCAS(&T[mask + 1].key, 0ull, 1ull) == 0ull;
             return mask + 1;
         }
-        u64 i = bucket_start<Slot64>(mix64(key), mask);
-        for (u64 n = 0; n <= mask; n++) {
-            const u64 old = atomicCAS(&T[i].key, kEmpty64, key);
-            if (old == kEmpty64) { claimed = true; return i; }
-            if (old == key) return i;
-            i = (i + 1) & mask;
+        // as for KM_K32: read the bucket's two keys, swap the first empty one
+        u64 b = bucket_start<Slot64>(mix64(key), mask);
+        for (u64 n = 0; n <= mask; n += 2) {
+            const u64 ks[2] = {T[b].key, T[b + 1].key};
+#pragma unroll
+            for (int s = 0; s < 2; s++) {
+                u64 c = ks[s];
+                if (c == kEmpty64) {
+                    c = atomicCAS(&T[b + s].key, kEmpty64, key);
+                    if (c == kEmpty64) { claimed = true; return b + s; }
+                }
+                if (c == key) return b + s;
+            }
+            b = (b + 2) & mask;
         }
     } else {
         SlotRep *T = (SlotRep *)L.table;
@@ -1402,7 +1429,6 @@ __device__ __forceinline__ void scan_flush(const ScanArgs &a, const ScanLds &S, 
 template <int MODE, bool STATS>
 __device__ __forceinline__ void scan_tiles(const ScanArgs &a, const ScanLds &S, u64 &tot, uint32_t &nprobe,
                                            uint32_t &nhit, u64 *red) {
-    StatusDev *status = a.status;
     const ScanLookup &L = a.lk[0];
     const int32_t *c0 = a.cols[L.kc[0]];
     const int32_t *c1 = a.cols[MODE == KM_K32 ? L.kc[0] : L.kc[1]];
@@ -1542,23 +1568,65 @@ __device__ __forceinline__ uint32_t tail_len(const EmitDev &d, const TailDev &T,
     return T.L.len[p];
 }
 
-__global__ void __launch_bounds__(256) k_emit_count(const EmitDev *__restrict__ dp, uint32_t E, u64 *cnt,
-                                                    StatusDev *status) {
-    const EmitDev &d = *dp;
-    uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= E) return;
-    if (!CK(e < d.F.cap)) { cnt[e] = 0; return; }
+// Result rows of binding e (the multiplicity times every tail's length).
+__device__ __forceinline__ u64 emit_rows_of(const EmitDev &d, uint32_t e, StatusDev *status) {
+    if (!CK(e < d.F.cap)) return 0;
     u64 v = d.F.mult ? d.F.mult[e] : 1ull;
     for (int q = 0; q < d.ntail; q++) {
         uint32_t p;
         v *= tail_len(d, d.tail[q], e, p, status);
     }
-    cnt[e] = v;
+    return v;
+}
+
+// Few bindings (E <= kEmitSmall): their counts, the scan into starts (with
+// starts[E] = total) and the emit's place in the output (as
+// k_scan_blocks_emit) in one workgroup.
+constexpr int kEmitSmallThreads = 1024;
+constexpr int kEmitSmallItems = 1;
+constexpr uint32_t kEmitSmall = kEmitSmallThreads * kEmitSmallItems;
+
+__global__ void __launch_bounds__(kEmitSmallThreads) k_emit_count_small(const EmitDev *__restrict__ dp, uint32_t E,
+                                                                        u64 *starts, StatusDev *status, u64 cap) {
+    __shared__ u64 lds[17];
+    const EmitDev &d = *dp;
+    u64 v[kEmitSmallItems];
+    u64 sum = 0;
+    const uint32_t e0 = threadIdx.x * kEmitSmallItems;
+#pragma unroll
+    for (int j = 0; j < kEmitSmallItems; j++) {
+        v[j] = e0 + j < E ? emit_rows_of(d, e0 + j, status) : 0ull;
+        sum += v[j];
+    }
+    u64 tot;
+    u64 ex = block_excl_scan<u64>(sum, lds, tot);
+#pragma unroll
+    for (int j = 0; j < kEmitSmallItems; j++) {
+        if (e0 + j < E) starts[e0 + j] = ex;
+        ex += v[j];
+    }
+    if (threadIdx.x == 0) {
+        starts[E] = tot;
+        status->total = tot;
+        const u64 base = status->written;
+        const u64 rows = base < cap ? (tot < cap - base ? tot : cap - base) : 0;
+        status->emit_base = base;
+        status->emit_rows = rows;
+        status->written = base + rows;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_emit_count(const EmitDev *__restrict__ dp, uint32_t E, u64 *cnt,
+                                                    StatusDev *status) {
+    uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < E) cnt[e] = emit_rows_of(*dp, e, status);
 }
 
 __device__ __forceinline__ void emit_row(const EmitDev &d, uint32_t E, const u64 *starts, u64 base, u64 r,
                                          StatusDev *status) {
-    uint32_t e = E == 1 ? 0u : upper_entry(starts, 0, E, r);
+    // binding r first (one row per binding is the common case), else search
+    uint32_t e = (uint32_t)(r < E ? r : E - 1);
+    if (E > 1 && !(starts[e] <= r && r < starts[e + 1])) e = upper_entry(starts, 0, E, r);
     if (!CK(e < E && e < d.F.cap && r >= starts[e] && r < starts[e + 1] && base + r < d.out_rows)) return;
     u64 idx = r - starts[e];
     uint32_t rows[FJ_MAX_NODES];
@@ -1755,6 +1823,16 @@ hipError_t launch_probe(const ProbeLaunch &p, hipStream_t s) {
     else hipLaunchKernelGGL((k_probe<FJ_MAX_VARS, FJ_MAX_ATOMS>), dim3(nb), dim3(bs), 0, s, a);
     return hipGetLastError();
 }
+
+hipError_t launch_emit_count_small(const void *emit_dev, uint32_t E, u64 *starts, StatusDev *st, u64 cap,
+                                   hipStream_t s) {
+    if (E == 0 || E > kEmitSmall) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_emit_count_small, dim3(1), dim3(kEmitSmallThreads), 0, s, (const EmitDev *)emit_dev, E,
+                       starts, st, cap);
+    return hipGetLastError();
+}
+
+uint32_t emit_small_max() { return kEmitSmall; }
 
 hipError_t launch_emit_count(const void *emit_dev, uint32_t E, u64 *cnt, StatusDev *st, hipStream_t s) {
     hipLaunchKernelGGL(k_emit_count, dim3(blocks_for(E, 256)), dim3(256), 0, s, (const EmitDev *)emit_dev, E, cnt,
