@@ -926,9 +926,23 @@ __global__ void k_chunk_entries(const u64 *__restrict__ starts, uint32_t E, u64 
 // MV and MA bound the binding's variable slots and atoms (powers of two; the
 // host picks the smallest that fits the query, and every index is masked so
 // that no plan can index past them).
+// Largest e in [lo, hi) with starts[e] <= g, searching a copy of
+// starts[lo, hi] held in LDS (sst[k] = starts[lo + k]).
+__device__ __forceinline__ uint32_t upper_entry_lds(const u64 *sst, uint32_t lo, uint32_t hi, u64 g) {
+    uint32_t a = 0, b = hi - lo;
+    while (b - a > 1) {
+        const uint32_t mid = a + ((b - a) >> 1);
+        if (sst[mid] <= g) a = mid; else b = mid;
+    }
+    return lo + a;
+}
+
+constexpr uint32_t kProbeStartsLds = 1024;   // scanned cover counts a block caches for its search
+
 template <int MV, int MA>
 __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
     __shared__ u64 red[17];
+    __shared__ u64 sst[kProbeStartsLds];
     const NodeDev &nd = *a.nd;
     StatusDev *status = a.status;
     const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -940,21 +954,33 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
     int32_t v[MV];
     uint32_t h[MA];
     uint32_t e = 0;
-    bool ok = idx < a.n;
+    // a block of a tile's tuples needs only the bindings between its first
+    // and last tuple's: their scanned counts go to LDS in one coalesced
+    // read, so each thread's search costs no dependent HBM reads
+    uint32_t lo = 0, hi = a.E;
+    bool in_lds = false, range_ok = true;
+    if (!a.din && a.chunk_e) {
+        lo = a.chunk_e[blockIdx.x];
+        hi = a.chunk_e[blockIdx.x + 1] + 1;
+        range_ok = CK(lo < hi && hi <= a.E);
+        in_lds = range_ok && hi - lo + 1 <= kProbeStartsLds;   // block-uniform
+        if (in_lds) {
+            for (uint32_t k = threadIdx.x; k <= hi - lo; k += blockDim.x) sst[k] = a.starts[lo + k];
+            __syncthreads();
+        }
+    }
+    bool ok = idx < a.n && range_ok;
     if (ok) {
         if (a.din) { t = a.din[idx]; resume = a.din_j[idx]; } else { t = idx; }
         const u64 g = a.t0 + t;
-        uint32_t lo = 0, hi = a.E;
-        if (!a.din && a.chunk_e) {
-            lo = a.chunk_e[blockIdx.x];
-            hi = a.chunk_e[blockIdx.x + 1] + 1;
-            ok = CK(lo < hi && hi <= a.E);
-        }
-        e = (!ok || a.E == 1) ? 0u : upper_entry(a.starts, lo, hi, g);
-        ok = ok && CK(e < a.E && e < nd.in.cap && g >= a.starts[e] && g < a.starts[e + 1]);
+        if (a.E == 1) e = 0;
+        else if (in_lds) e = upper_entry_lds(sst, lo, hi, g);
+        else e = upper_entry(a.starts, lo, hi, g);
+        if (in_lds) ok = CK(e < a.E && e < nd.in.cap && g >= sst[e - lo] && g < sst[e - lo + 1]);
+        else ok = CK(e < a.E && e < nd.in.cap && g >= a.starts[e] && g < a.starts[e + 1]);
     }
     if (ok) {
-        const u64 i = a.t0 + t - a.starts[e];
+        const u64 i = a.t0 + t - (in_lds ? sst[e - lo] : a.starts[e]);
         const FrontierDev &F = nd.in;
         for (int j = 0; j < nd.nin; j++) v[(j) & (MV - 1)] = F.vals[(u64)j * F.cap + e];
         for (int j = 0; j < nd.nin_h; j++) h[(nd.in_h_atom[j]) & (MA - 1)] = F.hdl[(u64)j * F.cap + e];
