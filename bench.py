@@ -44,7 +44,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-reps", type=int, default=5)
     ap.add_argument("--seed-rep", type=int, default=0)
-    ap.add_argument("--workload", choices=("star", "batch", "rmat"), default="star")
+    ap.add_argument("--workload", choices=("star", "batch", "rmat", "bushy"), default="star")
     ap.add_argument("--rmat-scale", type=int, default=22)
     ap.add_argument("--rmat-edges", type=int, default=50_000_000)
     ap.add_argument("--cycle4-scale", type=int, default=16, help="rmat workload: scale of the 4-cycle run")
@@ -64,6 +64,8 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "bushy":
+        return bench_bushy(args)
     if args.workload == "rmat":
         return bench_rmat(args)
 
@@ -271,6 +273,92 @@ def sampled_triangles(src, dst, xs):
         zs = np.concatenate([d_by_src[out_ptr[y]:out_ptr[y + 1]] for y in ys])
         total += int(np.isin(zs, ins).sum())
     return total
+
+
+def bench_bushy(args):
+    """A bushy plan against the left-deep one on a 4-chain of 1M-row
+    relations (primary-key/foreign-key joins with Zipf skew, the batched
+    generator's chain recipe): ((R0 R1) (R2 R3)) runs [R2, R3] first, its
+    result materialized on the device as a relation, then [R0, R1, P1]
+    (Section 2.2).  Count only; a step includes every plan's COLT builds."""
+    import torch
+
+    import datagen
+    from paper_2301_10841_amd import fj, runner
+    seed = datagen.seed_for(6, args.seed_rep)
+    qi = 0
+    while True:
+        dq, _ = datagen.batch_query(seed, qi, min_rows=1_000_000, max_rows=1_000_000,
+                                    frac_chain=1.0, frac_star=0.0)
+        if len(dq.atoms) == 4:
+            break
+        qi += 1
+    tree = ((0, 1), (2, 3))
+    ctx = fj.Context(0)
+    d = runner.DeviceQuery(ctx, dq)
+
+    def bushy_step():
+        return d.run_bushy(tree, materialize=False)["count"]
+
+    plan = d.plan_binary([0, 1, 2, 3], True)
+
+    def left_deep_step():
+        colts = d.build(plan)
+        c = ctx.execute(d.q, plan, colts)[0]
+        for t in colts:
+            t.free()
+        return c
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            c = fn()
+        torch.cuda.synchronize()
+        return c, (time.perf_counter() - t0) / args.steps
+
+    count, t_bushy = timed(bushy_step)
+    count_ld, t_ld = timed(left_deep_step)
+    if count_ld != count:
+        raise SystemExit(f"bushy count {count} != left-deep count {count_ld}")
+    # the materialized intermediate's size: the first plan of the decomposition
+    sub = fj.bushy_decompose(tree)
+    inter = runner.DeviceQuery(ctx, datagen.synth.make_query(
+        [dq.var_names[v] for v in (2, 3, 4)], [dq.relations[dq.atoms[2][0]], dq.relations[dq.atoms[3][0]]],
+        [(0, (0, 1)), (1, (1, 2))]))
+    p1 = inter.plan_binary([0, 1], True)
+    c1 = inter.build(p1)
+    inter_rows = ctx.execute(inter.q, p1, c1)[0]
+    for t in c1:
+        t.free()
+    cpu = None
+    if not args.no_cpu:
+        from oracle import bushy as B
+        t0 = time.perf_counter()
+        want = B.evaluate(dq, tree)
+        tc = time.perf_counter() - t0
+        if want["count"] != count:
+            raise SystemExit(f"count mismatch: GPU {count} vs CPU oracle {want['count']}")
+        cpu = {"value": want["count"] / tc, "unit": "output tuples/s", "cores": 1, "kind": "oracle",
+               "sample": "the full workload (both plans of the decomposition, intermediate materialized, "
+                         "final rows materialized), one run, single-threaded C oracle",
+               "s_per_run": tc}
+    res = {
+        "metric": "output tuples/s of a bushy plan (intermediate materialized on the device), count only",
+        "value": count / t_bushy, "unit": "output tuples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_bushy * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic (seeded Zipf PK-FK chain)",
+        "config": {"workload": "4-chain R0(x0,x1)..R3(x3,x4), 1M rows each, PK-FK with Zipf skew; "
+                               "bushy ((R0 R1) (R2 R3)) vs left-deep [R0, R1, R2, R3]",
+                   "rows": [int(dq.relations[r].nrows) for r, _ in dq.atoms]},
+        "count": count, "decomposition": sub, "intermediate_rows": inter_rows,
+        "left_deep_ms_per_step": t_ld * 1e3, "bushy_over_left_deep": t_bushy / t_ld,
+        "cpu_baseline": cpu,
+    }
+    ctx.close()
+    print(json.dumps(res), flush=True)
 
 
 def bench_rmat(args):

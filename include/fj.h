@@ -211,6 +211,47 @@ fj_status fj_execute(fj_ctx *ctx, const fj_query *q, const fj_plan *p, fj_colt *
                      uint64_t *count, int32_t *out, uint64_t cap, uint64_t *written,
                      fj_stats *stats);
 
+/* ------------------------------------------------------------- bushy plans */
+
+#define FJ_MAX_BUSHY (2 * FJ_MAX_ATOMS - 1)   /* nodes of a binary join tree */
+
+/* A binary join plan over a query's atoms (Section 2.2), bushy or not.
+   Node i is a leaf when atom[i] >= 0 (that atom of the query) and otherwise
+   the join of nodes left[i] and right[i], both below i.  root is the whole
+   plan.  Every node but the root is the child of exactly one join and
+   every atom of the query is exactly one leaf. */
+typedef struct {
+    int32_t n;
+    int32_t root;
+    int32_t atom[FJ_MAX_BUSHY];
+    int32_t left[FJ_MAX_BUSHY];
+    int32_t right[FJ_MAX_BUSHY];
+} fj_bushy;
+
+/* Decompose a binary plan into left-deep plans (Section 2.2): every join
+   node that is a right child becomes the root of its own plan, which is
+   evaluated first and its result materialized; the tree's left spines give
+   each plan's order.  Writes the plans in evaluation order (the whole plan
+   last) to *nplans (host) and, for plan k, its inputs in left-deep order to
+   inputs[k * FJ_MAX_ATOMS + i] (host, FJ_MAX_BUSHY * FJ_MAX_ATOMS entries)
+   with their number in ninputs[k] (host, FJ_MAX_BUSHY entries): an input
+   is an atom index (>= 0) or -(j + 1) for the result of plan j < k.
+   Returns FJ_ERR_ARG when b is not a tree of the form above.  Host only. */
+fj_status fj_bushy_decompose(const fj_bushy *b, int32_t *nplans, int32_t *ninputs, int32_t *inputs);
+
+/* Run a binary plan by its decomposition.  Every plan is converted (and
+   factored when flags has FJ_FACTOR) as by fj_plan_from_binary, its COLTs
+   are built, and it is executed; each plan but the last has its result
+   materialized on the device as a relation over all its variables (columns
+   in increasing variable order, as the paper keeps every attribute of an
+   intermediate), which the later plans join as an atom.  The last plan's
+   result is the query's: count, out, cap and written as for fj_execute.
+   rels: host array of q->natoms relations (device columns).  Intermediates
+   are allocated and freed inside the call.  FJ_ERR_UNSUPPORTED when an
+   intermediate has more than FJ_MAX_COLS variables or 2^31 rows or more. */
+fj_status fj_execute_bushy(fj_ctx *ctx, const fj_query *q, const fj_bushy *b, const fj_relation *rels,
+                           uint32_t flags, uint64_t *count, int32_t *out, uint64_t cap, uint64_t *written);
+
 /* ------------------------------------------------------------------ batches */
 
 typedef struct fj_batch fj_batch;

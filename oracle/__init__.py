@@ -20,6 +20,10 @@ Tiers
 * ``fj_oracle.c`` (via ``cfj``) -- a plain C Free Join following Section 3.3
   (figure "fj-algo"), COLT (Section 4.2 figure "colt-impl"), vectorized
   batches (Section 4.3) and dynamic covers (Section 4.4), with work counters.
+* ``bushy``   -- bushy binary plans run as a series of left-deep plans with
+  materialized intermediates (Section 2.2), each plan through ``plans`` and
+  ``cfj``; pinned by the paper's decomposition example and by nested-loop
+  enumeration of the query result.
 
 Pins: see ``tests/test_oracle_*.py``.  Parity unpinned: nothing in the
 join-result tiers; the MLP reference in ``mlp`` is pinned by finite

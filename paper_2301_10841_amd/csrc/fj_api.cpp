@@ -7,7 +7,10 @@
 #include <algorithm>
 #include <cstddef>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "fj.h"
@@ -216,7 +219,7 @@ struct fj_colt {
     u64 fill_lev_words[fj::kMaxLevels] = {0};
     bool lev_ready[fj::kMaxLevels] = {false};
     bool fill_stale = true;   // the device copies of the fill lists are out of date
-    std::vector<void *> allocs;
+    std::vector<std::pair<void *, size_t>> allocs;   // pooled device buffers and their sizes
 };
 
 namespace {
@@ -242,8 +245,11 @@ size_t slot_bytes(int mode) {
 
 template <typename T>
 fj_status colt_alloc(fj_colt *t, T **p, size_t n) {
-    FJ_TRY(dalloc(p, n));
-    t->allocs.push_back((void *)*p);
+    const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    void *q = nullptr;
+    FJ_TRY(fj::pool_alloc(t->device, bytes, &q));
+    *p = (T *)q;
+    t->allocs.push_back({q, bytes});
     return FJ_OK;
 }
 
@@ -296,8 +302,9 @@ fj_status colt_allocate(fj_colt *t) {
     return FJ_OK;
 }
 
+// Callers make sure no queued work still uses the buffers.
 void colt_free_all(fj_colt *t) {
-    for (void *p : t->allocs) hipFree(p);
+    for (const auto &a : t->allocs) fj::pool_free(t->device, a.first, a.second);
     t->allocs.clear();
 }
 
@@ -661,6 +668,50 @@ static fj_status check_relation(const fj_relation *r, int arity) {
 }
 
 namespace fj {
+// Device buffers of freed COLTs and intermediates, kept per (device, size)
+// for later allocations of the same size: a query's COLTs are allocated when
+// built and freed after the run, and rebuilding the same query's COLTs then
+// costs no hipMalloc.  At most kPoolMaxBytes are held; the rest is freed.
+namespace {
+constexpr size_t kPoolMaxBytes = size_t(4) << 30;
+std::mutex g_pool_mu;
+std::multimap<std::pair<int, size_t>, void *> g_pool;
+size_t g_pool_held = 0;
+}  // namespace
+
+fj_status pool_alloc(int device, size_t bytes, void **out) {
+    *out = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        auto it = g_pool.find({device, bytes});
+        if (it != g_pool.end()) {
+            *out = it->second;
+            g_pool.erase(it);
+            g_pool_held -= bytes;
+            return FJ_OK;
+        }
+    }
+    hipError_t e = hipMalloc(out, bytes);
+    if (e != hipSuccess) {
+        *out = nullptr;
+        return fail(FJ_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    return FJ_OK;
+}
+
+void pool_free(int device, void *p, size_t bytes) {
+    if (!p) return;
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        if (g_pool_held + bytes <= kPoolMaxBytes) {
+            g_pool.insert({{device, bytes}, p});
+            g_pool_held += bytes;
+            return;
+        }
+    }
+    hipFree(p);
+}
+
 hipStream_t ctx_stream(const fj_ctx *c) { return c->stream; }
 int ctx_device(const fj_ctx *c) { return c->device; }
 fj_status set_error(fj_status st, const std::string &msg) { return fail(st, msg); }

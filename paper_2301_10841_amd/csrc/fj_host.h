@@ -14,4 +14,11 @@ int ctx_device(const fj_ctx *c);
 // Records msg as this thread's fj_last_error() text and returns st.
 fj_status set_error(fj_status st, const std::string &msg);
 
+// Device memory that outlives a call but is freed often (COLT arrays,
+// materialized intermediates): pool_free keeps a buffer for the next
+// pool_alloc of the same size on the same device.  The caller of pool_free
+// makes sure no queued work still uses the buffer.
+fj_status pool_alloc(int device, size_t bytes, void **out);
+void pool_free(int device, void *p, size_t bytes);
+
 }  // namespace fj

@@ -1691,6 +1691,20 @@ __global__ void __launch_bounds__(256) k_emit_rows(const EmitDev *__restrict__ d
         emit_row(*dp, E, starts, base, r, status);
 }
 
+// ----------------------------------------------------- materialized rows
+// A materialized intermediate becomes a column-stored relation: row-major
+// rows (n x m) to m columns, one thread per row, stores coalesced per column.
+struct RowCols {
+    int32_t *col[FJ_MAX_COLS];
+};
+
+__global__ void __launch_bounds__(256) k_rows_to_cols(const int32_t *__restrict__ rows, u64 n, int m, RowCols c) {
+    const u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int32_t *src = rows + r * (u64)m;
+    for (int j = 0; j < m; j++) c.col[j][r] = src[j];
+}
+
 // ------------------------------------------------------------- launchers
 
 static inline unsigned blocks_for(u64 n, unsigned t) { return (unsigned)((n + t - 1) / t); }
@@ -1770,6 +1784,16 @@ hipError_t launch_filter_lt_group(int n, const int32_t *const *cols, const u64 *
     hipLaunchKernelGGL(k_filter_count_group, dim3((unsigned)nb), dim3(256), 0, s, g);
     hipLaunchKernelGGL(k_filter_scan_group, dim3((unsigned)n), dim3(kScanThreads), 0, s, g);
     hipLaunchKernelGGL(k_filter_write_group, dim3((unsigned)nb), dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_rows_to_cols(const int32_t *rows, u64 n, int m, int32_t *const *cols, hipStream_t s) {
+    if (m < 1 || m > FJ_MAX_COLS) return hipErrorInvalidValue;
+    if (n == 0) return hipSuccess;
+    RowCols c;
+    memset(&c, 0, sizeof(c));
+    for (int j = 0; j < m; j++) c.col[j] = cols[j];
+    hipLaunchKernelGGL(k_rows_to_cols, dim3(blocks_for(n, 256)), dim3(256), 0, s, rows, n, m, c);
     return hipGetLastError();
 }
 

@@ -87,6 +87,9 @@ hipError_t launch_filter_lt(const int32_t *col, unsigned long long n, int32_t bo
 // Selections of n columns (each with its own bound, output and block-sum
 // scratch of rows / 1024 + 1 words) in three launches; totals[i] receives
 // selection i's row count.
+// Row-major rows (n x m int32, m <= FJ_MAX_COLS) to m column arrays of n.
+hipError_t launch_rows_to_cols(const int32_t *rows, unsigned long long n, int m, int32_t *const *cols,
+                               hipStream_t s);
 hipError_t launch_filter_lt_group(int n, const int32_t *const *cols, const unsigned long long *rows,
                                   const int32_t *bounds, uint32_t *const *outs, uint32_t *const *bsums,
                                   uint32_t *const *totals, hipStream_t s);

@@ -78,6 +78,53 @@ class Sketch(C.Structure):
                 "top": [[int(self.top[j][k]) for k in range(SKETCH_TOPK)] for j in range(n)]}
 
 
+MAX_BUSHY = 2 * MAX_ATOMS - 1
+
+
+class Bushy(C.Structure):
+    """A binary join plan (fj_bushy): node i is a leaf when atom[i] >= 0,
+    else the join of nodes left[i] and right[i]."""
+    _fields_ = [("n", C.c_int32), ("root", C.c_int32), ("atom", C.c_int32 * MAX_BUSHY),
+                ("left", C.c_int32 * MAX_BUSHY), ("right", C.c_int32 * MAX_BUSHY)]
+
+
+def bushy(tree) -> Bushy:
+    """A Bushy from a nested tree: an int is an atom, a pair (l, r) a join."""
+    b = Bushy()
+    nodes = []
+
+    def add(t):
+        if isinstance(t, int):
+            nodes.append((int(t), -1, -1))
+        else:
+            l, r = t
+            li = add(l)
+            ri = add(r)
+            nodes.append((-1, li, ri))
+        return len(nodes) - 1
+
+    b.root = add(tree)
+    b.n = len(nodes)
+    if b.n > MAX_BUSHY:
+        raise ValueError("plan too large")
+    for i, (a, l, r) in enumerate(nodes):
+        b.atom[i] = a
+        b.left[i] = l
+        b.right[i] = r
+    return b
+
+
+def bushy_decompose(tree) -> List[List[int]]:
+    """The left-deep plans of a binary plan, in evaluation order (host only):
+    inputs are atom indices, or -(j + 1) for the result of plan j."""
+    b = tree if isinstance(tree, Bushy) else bushy(tree)
+    n = C.c_int32(0)
+    ninp = (C.c_int32 * MAX_BUSHY)()
+    inp = (C.c_int32 * (MAX_BUSHY * MAX_ATOMS))()
+    _check(lib().fj_bushy_decompose(C.byref(b), C.byref(n), ninp, inp))
+    return [[int(inp[k * MAX_ATOMS + i]) for i in range(ninp[k])] for k in range(n.value)]
+
+
 class Candidate(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n", C.c_int32), ("order", C.c_int32 * MAX_VARS)]
 
@@ -117,6 +164,9 @@ def lib():
         L.fj_colt_free.restype = None
         L.fj_execute.argtypes = [vp, P(QueryS), vp, vp, P(C.c_uint64), vp, C.c_uint64,
                                  P(C.c_uint64), P(Stats)]
+        L.fj_bushy_decompose.argtypes = [P(Bushy), P(C.c_int32), vp, vp]
+        L.fj_execute_bushy.argtypes = [vp, P(QueryS), P(Bushy), vp, C.c_uint32, P(C.c_uint64), vp, C.c_uint64,
+                                       P(C.c_uint64)]
         L.fj_batch_create.argtypes = [vp, C.c_int32, vp, vp, vp, vp, P(vp)]
         L.fj_batch_run.argtypes = [vp, vp]
         L.fj_batch_free.argtypes = [vp]
@@ -324,6 +374,19 @@ class Context:
         _check(rc, ok=(0, 1))
         return int(cnt.value), int(wr.value), st
 
+
+    def execute_bushy(self, q: QueryS, tree, rels, factor: bool = True, out=None):
+        """Run a binary plan by its left-deep decomposition; rels: one
+        (cols, sel, nsel) per atom.  Returns (count, written)."""
+        b = tree if isinstance(tree, Bushy) else bushy(tree)
+        ra = (Relation * len(rels))(*[_relation(c, s, n) for c, s, n in rels])
+        cnt = C.c_uint64(0)
+        wr = C.c_uint64(0)
+        cap = int(out.shape[0]) if out is not None else 0
+        rc = lib().fj_execute_bushy(self.h, C.byref(q), C.byref(b), ra, FACTOR if factor else 0, C.byref(cnt),
+                                    C.c_void_p(out.data_ptr()) if out is not None else None, cap, C.byref(wr))
+        _check(rc, ok=(0, 1))
+        return int(cnt.value), int(wr.value)
 
     # ---- statistics and plan choice
     def sketch(self, cols, sel=None, nsel: int = 0) -> Sketch:

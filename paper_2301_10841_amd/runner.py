@@ -100,6 +100,20 @@ class DeviceQuery:
         return {"count": cnt, "rows": rows, "written": written, "stats": st, "colts": colts}
 
 
+    def run_bushy(self, tree, materialize: bool = True, factor: bool = True):
+        """Run a binary plan (nested pairs of atom indices) by its left-deep
+        decomposition.  Returns dict(count, rows (sorted numpy or None), written)."""
+        import torch
+        rels = [(self.atom_cols(a), self.sel[a], self.nsel[a]) for a in range(len(self.dq.atoms))]
+        cnt, _ = self.ctx.execute_bushy(self.q, tree, rels, factor=factor)
+        if not materialize:
+            return {"count": cnt, "rows": None, "written": 0}
+        out = torch.empty((max(int(cnt), 1), self.q.nhead), dtype=torch.int32, device=f"cuda:{self.ctx.device}")
+        cnt2, written = self.ctx.execute_bushy(self.q, tree, rels, factor=factor, out=out)
+        rows = out[:written].cpu().numpy() if written else np.zeros((0, self.q.nhead), np.int32)
+        return {"count": cnt2, "rows": sort_rows(rows), "written": written}
+
+
 def sort_rows(rows: np.ndarray) -> np.ndarray:
     if rows.shape[0] == 0:
         return rows
