@@ -44,7 +44,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-reps", type=int, default=5)
     ap.add_argument("--seed-rep", type=int, default=0)
-    ap.add_argument("--workload", choices=("star", "batch", "rmat", "bushy"), default="star")
+    ap.add_argument("--workload", choices=("star", "batch", "rmat", "bushy", "ablation"), default="star")
     ap.add_argument("--rmat-scale", type=int, default=22)
     ap.add_argument("--rmat-edges", type=int, default=50_000_000)
     ap.add_argument("--cycle4-scale", type=int, default=16, help="rmat workload: scale of the 4-cycle run")
@@ -66,6 +66,8 @@ def main():
         return bench_batch(args)
     if args.workload == "bushy":
         return bench_bushy(args)
+    if args.workload == "ablation":
+        return bench_ablation(args)
     if args.workload == "rmat":
         return bench_rmat(args)
 
@@ -273,6 +275,109 @@ def sampled_triangles(src, dst, xs):
         zs = np.concatenate([d_by_src[out_ptr[y]:out_ptr[y + 1]] for y in ys])
         total += int(np.isin(zs, ins).sum())
     return total
+
+
+def bench_ablation(args):
+    """The paper's ablation (Section 5) on synthetic inputs: the same plans
+    over the three tries (simple trie: every level built ahead; simple lazy
+    trie: every root built ahead, inner levels lazily; COLT), then the COLT
+    with frontier tiles of 2^10 .. 2^24 tuples (the GPU's vectorization
+    batch).  A run is a rebuild of every COLT plus the join, count only;
+    each figure is the median of up to 5 runs, or the first run when that
+    took over 2 s."""
+    import torch
+
+    import datagen
+    from datagen import synth
+    from paper_2301_10841_amd import fj, runner
+    cases = []
+    e = datagen.rmat_edges(datagen.seed_for(3, 1), 18, 3_000_000)
+    tri = synth.triangle_query(e)
+    cases.append(("R-MAT 2^18 / 3M edges, triangle, Generic Join plan", tri,
+                  [[(0, (0,)), (2, (0,))], [(0, (1,)), (1, (1,))], [(1, (2,)), (2, (2,))]]))
+    cases.append(("R-MAT 2^18 / 3M edges, triangle, converted plan [R, S, T]", tri, [0, 1, 2]))
+    cases.append(("star, 10M facts x 4 dims, converted plan", datagen.star_schema(datagen.seed_for(2, 0)),
+                  [0, 1, 2, 3, 4]))
+    qi = 0
+    while True:
+        dq, _ = datagen.batch_query(datagen.seed_for(6, 0), qi, min_rows=1_000_000, max_rows=1_000_000,
+                                    frac_chain=1.0, frac_star=0.0)
+        if len(dq.atoms) == 4:
+            break
+        qi += 1
+    cases.append(("4-chain, 1M rows each, converted plan", dq, [0, 1, 2, 3]))
+
+    def run_case(ctx, dq, spec):
+        d = runner.DeviceQuery(ctx, dq)
+        plan = d.plan_nodes(spec) if isinstance(spec[0], list) else d.plan_binary(spec, True)
+        colts = d.build(plan)
+        try:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            count = ctx.execute(d.q, plan, colts)[0]
+            torch.cuda.synchronize()
+            first = time.perf_counter() - t0
+            if first > 2.0:          # a slow configuration: its first run is the figure
+                return count, first
+            ts = []
+            for _ in range(max(min(args.steps, 5), 1)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                d.rebuild(colts)
+                c = ctx.execute(d.q, plan, colts)[0]
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+                if c != count:
+                    raise SystemExit(f"count changed between runs: {c} vs {count}")
+            return count, statistics.median(ts)
+        finally:
+            for t in colts:
+                t.free()
+
+    modes = [("simple trie", 2), ("simple lazy trie", 1), ("COLT", 0)]
+    tiles = [1 << 12, 1 << 16, 1 << 20, 1 << 24]
+    rows = []
+    for name, dq, spec in cases:
+        row = {"case": name, "trie_ms": {}, "tile_ms": {}}
+        counts = set()
+        for mname, trie in modes:
+            log(f"{name} | {mname} ...")
+            ctx = fj.Context(0, trie=trie)
+            c, t = run_case(ctx, dq, spec)
+            ctx.close()
+            counts.add(c)
+            row["trie_ms"][mname] = t * 1e3
+            log(f"{name} | {mname}: {t * 1e3:.2f} ms")
+        for tile in tiles:
+            log(f"{name} | tile {tile} ...")
+            ctx = fj.Context(0, tile=tile)
+            c, t = run_case(ctx, dq, spec)
+            ctx.close()
+            counts.add(c)
+            row["tile_ms"][str(tile)] = t * 1e3
+            log(f"{name} | tile {tile}: {t * 1e3:.2f} ms")
+        if len(counts) != 1:
+            raise SystemExit(f"{name}: counts differ across tries and tiles: {counts}")
+        row["count"] = counts.pop()
+        rows.append(row)
+
+    def geo(xs):
+        return float(statistics.geometric_mean(xs))
+
+    sp_slt = geo([r["trie_ms"]["simple lazy trie"] / r["trie_ms"]["COLT"] for r in rows])
+    sp_simple = geo([r["trie_ms"]["simple trie"] / r["trie_ms"]["COLT"] for r in rows])
+    sp_tile = geo([r["tile_ms"][str(tiles[0])] / r["tile_ms"][str(tiles[-1])] for r in rows])
+    res = {
+        "metric": "COLT speedup over the simple lazy trie and the simple trie (geometric mean over the cases)",
+        "value": sp_slt, "unit": "x", "n_gpus": 1, "steps": args.steps, "warmup": 0,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic (seeded R-MAT, Zipf star schema, Zipf PK-FK chain)",
+        "config": {"workload": "ablation: tries and frontier tile sizes", "cases": [r["case"] for r in rows],
+                   "tiles": tiles},
+        "colt_over_slt_geomean": sp_slt, "colt_over_simple_trie_geomean": sp_simple,
+        "tile_2p24_over_2p12_geomean": sp_tile, "cases": rows,
+    }
+    print(json.dumps(res), flush=True)
 
 
 def bench_bushy(args):

@@ -91,7 +91,13 @@ typedef struct {
     int32_t tail;        /* 0: multiply trailing single-cover nodes (default);
                             1: run every node through the probe kernel */
     int32_t generic;     /* 1: never use the specialised first-node scan kernel [0] */
-    int32_t reserved[3];
+    int32_t trie;        /* tries, for the paper's ablation (Section 5): 0: COLT [default]:
+                            lazy, and a base table that is its node's only cover is
+                            iterated directly; 1: simple lazy trie: every root map is
+                            built ahead, inner levels lazily; 2: simple trie: every
+                            level of every COLT is built when it is (re)built.
+                            Batches take 0 only. */
+    int32_t reserved[2];
 } fj_options;
 
 /* Per-execution counters (fj_execute fills them when stats is non-null).

@@ -481,6 +481,30 @@ static fj_status colt_level_ready(fj_ctx *c, fj_colt *t, int l) {
     return FJ_OK;
 }
 
+// The simple trie of the paper's ablation: every level below the root is
+// forced now, level by level, each trie of level l being a child of a
+// forced trie of level l - 1.
+static fj_status colt_force_all(fj_ctx *c, fj_colt *t) {
+    if (c->opt.trie != 2 || !t->root_built || t->nroot == 0) return FJ_OK;
+    for (int l = 1; l < t->nlev; l++) {
+        const int slot = t->atom * fj::kMaxLevels + l;
+        const size_t off = offsetof(StatusDev, fq_n) + sizeof(uint32_t) * slot;
+        FJ_TRY(zero_status_field(c, off, sizeof(uint32_t)));
+        {
+            Timer tm(c, FJ_T_BUILD);
+            // the root's one trie has at most nroot keys; below it a trie
+            // starts at any of the nroot positions
+            FJ_HIP(fj::launch_enqueue_children(t->lev[l - 1], t->lev[l], t->nroot, l == 1 ? 1 : 0,
+                                               &c->status_d->fq_n[slot], c->status_d, c->stream));
+        }
+        FJ_TRY(sync_status(c));
+        const uint32_t nh = c->status_h->fq_n[slot];
+        FJ_TRY(force_queue(c, t, l, nh, ~0ull, FJ_T_BUILD, nullptr, -1));
+        FJ_TRY(zero_status_field(c, off, sizeof(uint32_t)));
+    }
+    return FJ_OK;
+}
+
 static fj_status colt_reset(fj_ctx *c, fj_colt *t) {
     FJ_TRY(colt_size(t));
     FJ_TRY(colt_fill_upload(c, t));
@@ -506,7 +530,7 @@ static fj_status colt_reset(fj_ctx *c, fj_colt *t) {
             FJ_TRY(force_queue(c, t, 0, 1, t->nroot, FJ_T_BUILD, nullptr, -1, true));
         }
     }
-    return FJ_OK;
+    return colt_force_all(c, t);
 }
 
 // ---------------------------------------------------------- grouped rebuilds
@@ -991,7 +1015,8 @@ fj_status fj_build_colt(fj_ctx *c, const fj_query *q, const fj_plan *p, int32_t 
     t->nrows = rel->nrows;
     t->nroot = (uint32_t)(rel->sel ? rel->nsel : rel->nrows);
     t->cap_rows = t->nroot;
-    t->root_built = p->root_built[atom];
+    // the ablation's tries build every root map ahead
+    t->root_built = p->root_built[atom] || c->opt.trie >= 1;
     t->nlev = p->nlev[atom];
     for (int l = 0; l < t->nlev; l++) {
         const fj::Subatom &s = p->lev[atom][l];
@@ -1059,7 +1084,9 @@ fj_status fj_colt_rebuild_many(fj_ctx *c, int32_t n, fj_colt *const *colts, cons
     }
     if (!c->group) c->group = new ColtGroup();
     FJ_TRY(group_prepare(c, *c->group, colts, n, 0));
-    return group_launch(c, *c->group);
+    FJ_TRY(group_launch(c, *c->group));
+    for (int k = 0; k < n; k++) FJ_TRY(colt_force_all(c, colts[k]));
+    return FJ_OK;
 }
 
 void fj_colt_free(fj_colt *t) {
@@ -1159,13 +1186,13 @@ bool scan_eligible(const Exec &x, int &cover_sub) {
     cover_sub = L.pure[0];
     const auto &node = p->nodes[0];
     int ca = node[cover_sub].atom;
-    if (p->root_built[ca] || p->nlev[ca] != 1) return false;
+    if (x.colts[ca]->root_built || p->nlev[ca] != 1) return false;
     int nl = 0;
     for (size_t i = 0; i < node.size(); i++) {
         if ((int)i == cover_sub) continue;
         const fj_colt *t = x.colts[node[i].atom];
         const LevelDev &R = t->lev[0];
-        if (p->sub_level[0][i] != 0 || !p->root_built[node[i].atom]) return false;
+        if (p->sub_level[0][i] != 0 || !x.colts[node[i].atom]->root_built) return false;
         if (!(R.mode == fj::KM_K32 || (R.mode == fj::KM_K64 && R.nk == 2))) return false;
         nl++;
     }
@@ -1384,7 +1411,7 @@ fj_status check_exec_args(const fj_query *q, const fj_plan *p, fj_colt *const *c
             for (int j = 0; j < t->lev_nk[l]; j++)
                 if (t->lev_var[l][j] != p->lev[a][l].vars[j]) return fail(FJ_ERR_ARG, "COLT schema does not match the plan");
         }
-        if (t->root_built != p->root_built[a]) return fail(FJ_ERR_ARG, "COLT root rule does not match the plan");
+        if (p->root_built[a] && !t->root_built) return fail(FJ_ERR_ARG, "COLT root rule does not match the plan");
     }
     std::string err;
     return fj::check_query(*q, err) == FJ_OK ? FJ_OK : fail(FJ_ERR_ARG, err);
@@ -1727,6 +1754,7 @@ extern "C" fj_status fj_batch_create(fj_ctx *c, int32_t n, const fj_query *const
                                      fj_colt *const *const *colts, const fj_batch_options *opt, fj_batch **out) {
     if (!c || n < 1 || !qs || !plans || !colts || !out) return fail(FJ_ERR_ARG, "bad argument");
     *out = nullptr;
+    if (c->opt.trie != 0) return fail(FJ_ERR_UNSUPPORTED, "batches run on COLTs (trie option 0)");
     FJ_HIP(hipSetDevice(c->device));
     fj_batch *b = new fj_batch();
     b->c = c;

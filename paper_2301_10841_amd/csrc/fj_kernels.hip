@@ -1691,6 +1691,39 @@ __global__ void __launch_bounds__(256) k_emit_rows(const EmitDev *__restrict__ d
         emit_row(*dp, E, starts, base, r, status);
 }
 
+// ------------------------------------------------------------- eager tries
+// Queue every child trie of level L's forced tries for forcing (the simple
+// trie of the paper's ablation builds every level ahead): position q of L
+// starts a forced trie when st[q] holds its key count + 1; the child starts
+// of its keys are kl[q .. q + keys).  root: L is a root level, whose one
+// trie (position 0) may hold millions of keys: thread q takes its key q, up
+// to nq; otherwise thread q takes the trie starting at position q < nq.
+__device__ __forceinline__ void enqueue_child(const LevelDev &C, uint32_t s, uint32_t *fq_n, StatusDev *status) {
+    if (!CK(s < C.npos)) return;
+    if (atomicCAS(&C.st[s], 0u, kQueued) == 0u) {
+        const uint32_t pos = atomicAdd(fq_n, 1u);
+        if (CK(pos < C.npos)) C.fq[pos] = s;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_enqueue_children(LevelDev L, LevelDev C, uint32_t nq, int root,
+                                                          uint32_t *fq_n, StatusDev *status) {
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    if (root) {
+        const uint32_t st = L.st[0];
+        if (st == 0 || st == kQueued || q >= st - 1 || !CK(q < L.npos)) return;
+        enqueue_child(C, L.kl[q], fq_n, status);
+        return;
+    }
+    if (!CK(q < L.npos)) return;
+    const uint32_t st = L.st[q];
+    if (st == 0 || st == kQueued) return;
+    const uint32_t keys = st - 1;
+    if (!CK((u64)q + keys <= L.npos)) return;
+    for (uint32_t r = 0; r < keys; r++) enqueue_child(C, L.kl[q + r], fq_n, status);
+}
+
 // ----------------------------------------------------- materialized rows
 // A materialized intermediate becomes a column-stored relation: row-major
 // rows (n x m) to m columns, one thread per row, stores coalesced per column.
@@ -1784,6 +1817,13 @@ hipError_t launch_filter_lt_group(int n, const int32_t *const *cols, const u64 *
     hipLaunchKernelGGL(k_filter_count_group, dim3((unsigned)nb), dim3(256), 0, s, g);
     hipLaunchKernelGGL(k_filter_scan_group, dim3((unsigned)n), dim3(kScanThreads), 0, s, g);
     hipLaunchKernelGGL(k_filter_write_group, dim3((unsigned)nb), dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_enqueue_children(const LevelDev &L, const LevelDev &C, uint32_t nq, int root, uint32_t *fq_n,
+                                   StatusDev *st, hipStream_t s) {
+    if (nq == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_enqueue_children, dim3(blocks_for(nq, 256)), dim3(256), 0, s, L, C, nq, root, fq_n, st);
     return hipGetLastError();
 }
 

@@ -87,6 +87,11 @@ hipError_t launch_filter_lt(const int32_t *col, unsigned long long n, int32_t bo
 // Selections of n columns (each with its own bound, output and block-sum
 // scratch of rows / 1024 + 1 words) in three launches; totals[i] receives
 // selection i's row count.
+// Queue every child trie of level L's forced tries on level C's force
+// queue, counting them in *fq_n: root: the keys [0, nq) of L's one trie;
+// otherwise the tries starting at positions [0, nq).
+hipError_t launch_enqueue_children(const LevelDev &L, const LevelDev &C, uint32_t nq, int root, uint32_t *fq_n,
+                                   StatusDev *st, hipStream_t s);
 // Row-major rows (n x m int32, m <= FJ_MAX_COLS) to m column arrays of n.
 hipError_t launch_rows_to_cols(const int32_t *rows, unsigned long long n, int m, int32_t *const *cols,
                                hipStream_t s);

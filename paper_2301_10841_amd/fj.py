@@ -52,7 +52,7 @@ class QueryS(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("tile", C.c_int64), ("block", C.c_int32), ("timing", C.c_int32),
-                ("tail", C.c_int32), ("generic", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("tail", C.c_int32), ("generic", C.c_int32), ("trie", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class Stats(C.Structure):
@@ -278,7 +278,7 @@ class Context:
     """A libfj context bound to a device and a torch stream."""
 
     def __init__(self, device: int = 0, stream=None, tile: int = 0, block: int = 0,
-                 timing: bool = False, tail: int = 0, generic: bool = False):
+                 timing: bool = False, tail: int = 0, generic: bool = False, trie: int = 0):
         import torch
         self.device = device
         if stream is None:
@@ -290,6 +290,7 @@ class Context:
         opt.timing = 1 if timing else 0
         opt.tail = tail
         opt.generic = 1 if generic else 0
+        opt.trie = int(trie)
         h = C.c_void_p()
         _check(lib().fj_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(opt), C.byref(h)))
         self.h = h.value
