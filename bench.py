@@ -44,7 +44,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-reps", type=int, default=5)
     ap.add_argument("--seed-rep", type=int, default=0)
-    ap.add_argument("--workload", choices=("star", "batch", "rmat", "bushy", "ablation"), default="star")
+    ap.add_argument("--workload", choices=("star", "batch", "rmat", "bushy", "ablation", "factorized"), default="star")
     ap.add_argument("--rmat-scale", type=int, default=22)
     ap.add_argument("--rmat-edges", type=int, default=50_000_000)
     ap.add_argument("--cycle4-scale", type=int, default=16, help="rmat workload: scale of the 4-cycle run")
@@ -64,6 +64,8 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "factorized":
+        return bench_factorized(args)
     if args.workload == "bushy":
         return bench_bushy(args)
     if args.workload == "ablation":
@@ -376,6 +378,110 @@ def bench_ablation(args):
                    "tiles": tiles},
         "colt_over_slt_geomean": sp_slt, "colt_over_simple_trie_geomean": sp_simple,
         "tile_2p24_over_2p12_geomean": sp_tile, "cases": rows,
+    }
+    print(json.dumps(res), flush=True)
+
+
+def bench_factorized(args):
+    """Factorized against full results on a fan-out chain R(x, y) join S(y, z)
+    (1M R rows, 100K keys, 20 S rows per key: 20M result rows from 1M final
+    bindings).  A step runs the plan keeping the final bindings (Section 4.4's
+    factorized view, kept as the result as in Section 5.2); the full path
+    writes every row.  Expansion of all rows in 1M-row pages is timed apart."""
+    import torch
+
+    import datagen
+    from paper_2301_10841_amd import fj, runner
+    dq = datagen.fanout_chain(datagen.seed_for(10, args.seed_rep))
+    ctx = fj.Context(0)
+    d = runner.DeviceQuery(ctx, dq)
+    plan = d.plan_binary([0, 1], True)
+    colts = d.build(plan)
+    count = ctx.execute(d.q, plan, colts)[0]
+    d.rebuild(colts)
+    out = torch.empty((count, d.q.nhead), dtype=torch.int32, device="cuda:0")
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            r = fn()
+            if isinstance(r, fj.Result):
+                r.free()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r = fn()
+            if isinstance(r, fj.Result):
+                r.free()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps
+
+    def full_step():
+        c, w, _ = ctx.execute(d.q, plan, colts, out=out)
+        if c != count or w != count:
+            raise SystemExit(f"full run wrote {w} of {c} rows, expected {count}")
+
+    def fact_step():
+        return ctx.execute_factorized(d.q, plan, colts)
+
+    log("factorized: full materialization")
+    t_full = timed(full_step)
+    sums_full = out.to(torch.int64).sum(dim=0).cpu().tolist()
+    log("factorized: bindings kept")
+    t_fact = timed(fact_step)
+    res = ctx.execute_factorized(d.q, plan, colts)
+    if res.count != count:
+        raise SystemExit(f"factorized count {res.count} != {count}")
+    page = 1 << 20
+    pbuf = out[:page]
+    log("factorized: expansion")
+    # checked pass (also computes the row counts' scan, once per result)
+    sums = torch.zeros(d.q.nhead, dtype=torch.int64, device="cuda:0")
+    first = 0
+    while first < count:
+        w = res.expand(first, pbuf)
+        sums += pbuf[:w].to(torch.int64).sum(dim=0)
+        first += w
+    if sums.cpu().tolist() != sums_full:
+        raise SystemExit("expanded rows differ from the fully materialized rows")
+    # timed pass: every page, nothing else
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    first = 0
+    while first < count:
+        first += res.expand(first, pbuf)
+    torch.cuda.synchronize()
+    t_exp = time.perf_counter() - t0
+    bindings = res.bindings
+    res.free()
+    # bytes the result holds: x, y values, one handle into S's level and a
+    # multiplicity per binding, against nhead int32 per row
+    fact_bytes = bindings * (2 * 4 + 4 + 8)
+    full_bytes = count * d.q.nhead * 4
+    cpu = None
+    if not args.no_cpu:
+        from oracle import cfj
+        from oracle import plans as P
+        t0 = time.perf_counter()
+        want = cfj.run(dq, P.factor(P.binary2fj(dq, [0, 1])), batch=1000, materialize=False, counters=False)
+        tc = time.perf_counter() - t0
+        if want["count"] != count:
+            raise SystemExit(f"count mismatch: GPU {count} vs CPU oracle {want['count']}")
+        cpu = {"value": count / tc, "unit": "output tuples/s", "cores": 1, "kind": "oracle",
+               "sample": "the full workload counted (no rows written), one run, single-threaded C oracle",
+               "s_per_run": tc}
+    for t in colts:
+        t.free()
+    res = {
+        "metric": "output tuples/s with the result kept factorized",
+        "value": count / t_fact, "unit": "output tuples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_fact * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic (seeded uniform fan-out chain)",
+        "config": {"workload": "R(x,y) 1M rows join S(y,z) 2M rows, 100K keys, 20 S rows per key; "
+                               "20M result rows"},
+        "full_ms": t_full * 1e3, "expand_all_ms": t_exp * 1e3, "rows": count, "bindings": bindings,
+        "factorized_bytes": fact_bytes, "full_bytes": full_bytes,
+        "full_over_factorized_time": t_full / t_fact,
+        "roofline": None, "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
 

@@ -15,6 +15,7 @@ from .synth import (  # noqa: F401
     rmat_edges,
     zipf_keys,
     random_tiny_query,
+    fanout_chain,
     batch_mix,
     batch_query,
     seed_for,

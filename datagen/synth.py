@@ -261,6 +261,21 @@ def star_schema(seed: int, n_fact: int = 10_000_000, n_dim: int = 1_000_000,
 _SHAPES = ("triangle", "clover", "chain3", "chain4", "star3", "cycle4", "clover_u", "pair", "single")
 
 
+def fanout_chain(seed: int, n_left: int = 1_000_000, n_keys: int = 100_000, fanout: int = 20) -> Query:
+    """R(x, y) join S(y, z): R has n_left rows with y uniform over n_keys; S
+    holds `fanout` rows for every key y (z uniform), so each R row meets
+    `fanout` S rows.  The result has n_left * fanout rows but only n_left
+    bindings before the last variable."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = rng.integers(0, 1 << 30, n_left, dtype=np.int32)
+    y = rng.integers(0, n_keys, n_left, dtype=np.int32)
+    sy = np.repeat(np.arange(n_keys, dtype=np.int32), fanout)
+    sy = sy[rng.permutation(sy.shape[0])]
+    z = rng.integers(-(1 << 30), 1 << 30, sy.shape[0], dtype=np.int32)
+    return make_query(["x", "y", "z"], [Relation("R", [x, y]), Relation("S", [sy, z])],
+                      [(0, (0, 1)), (1, (1, 2))], kind="fanout_chain")
+
+
 def random_tiny_query(seed: int, shape: str, max_rows: int = 10, domain: int = 4) -> Query:
     """Small bag instances over a tiny domain so that duplicates, skew and
     hash collisions all occur; used against nested-loop enumeration."""

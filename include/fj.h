@@ -217,6 +217,30 @@ fj_status fj_execute(fj_ctx *ctx, const fj_query *q, const fj_plan *p, fj_colt *
                      uint64_t *count, int32_t *out, uint64_t cap, uint64_t *written,
                      fj_stats *stats);
 
+/* ------------------------------------------------------- factorized results */
+
+typedef struct fj_result fj_result;
+
+/* Join phase that keeps the result factorized (Section 4.4's view of a trie
+   as a factorized relation, used in Section 5.2 to avoid building large
+   outputs): the final bindings of the plan's last enumerated node are
+   kept, each standing for its multiplicity times the product of its
+   trailing tries' lengths, instead of being expanded into rows.  *count
+   (host) receives the exact result count and *bindings (host, nullable)
+   the number of bindings kept.  The result reads the COLTs' tries when it
+   is expanded: the COLTs must stay alive and must not be rebuilt until
+   fj_result_free.  Device memory for the bindings is owned by the result. */
+fj_status fj_execute_factorized(fj_ctx *ctx, const fj_query *q, const fj_plan *p, fj_colt *const *colts,
+                                fj_result **out, uint64_t *count, uint64_t *bindings);
+
+/* Rows [first, first + n) of a factorized result, in head order, written
+   row-major to out (device, cap x q->nhead int32) with n = min(cap, count -
+   first); *written (host) receives n.  Rows keep one fixed order across
+   calls, so pages of consecutive ranges cover the result exactly once. */
+fj_status fj_result_expand(fj_ctx *ctx, fj_result *r, uint64_t first, int32_t *out, uint64_t cap,
+                           uint64_t *written);
+void fj_result_free(fj_result *r);
+
 /* ------------------------------------------------------------- bushy plans */
 
 #define FJ_MAX_BUSHY (2 * FJ_MAX_ATOMS - 1)   /* nodes of a binary join tree */

@@ -1121,6 +1121,7 @@ struct Exec {
     std::vector<int> head_src;
     uint32_t *dA = nullptr, *dB = nullptr;
     uint8_t *dA_j = nullptr, *dB_j = nullptr;
+    fj_result *res = nullptr;           // factorized: keep the final bindings instead of rows
 };
 
 void fill_level_sub(SubDev &S, const fj_colt *t, int level) {
@@ -1172,6 +1173,103 @@ fj_status emit_rows(Exec &x, uint32_t E) {
         Timer t(c, FJ_T_EMIT);
         FJ_HIP(fj::launch_emit_rows(x.emit_d, E, starts, x.cap - x.written, c->status_d, c->stream));
     }
+    return FJ_OK;
+}
+
+}  // namespace
+
+// A factorized result (fj_execute_factorized): the final bindings (values,
+// handles and multiplicities, structure of arrays of capacity cap, in one
+// pooled buffer) with what expanding them into rows needs.
+struct fj_result {
+    int device = 0;
+    int nvals = 0, nhdl = 0;
+    u64 E = 0, cap = 0;
+    void *buf = nullptr;
+    size_t bytes = 0;
+    int32_t *vals = nullptr;
+    uint32_t *hdl = nullptr;
+    u64 *mult = nullptr;
+    u64 count = 0;
+    std::vector<int> in_var, in_hatom, head_src;
+    std::vector<TailDev> tails;
+    u64 *starts = nullptr;      // E + 1 scanned row counts, once expanded
+    size_t starts_bytes = 0;
+    void *emit_d = nullptr;     // device emit descriptor
+    std::vector<char> emit_h;   // its host copy
+    ~fj_result() {
+        fj::pool_free(device, buf, bytes);
+        fj::pool_free(device, starts, starts_bytes);
+        fj::pool_free(device, emit_d, fj::emit_dev_size());
+    }
+};
+
+namespace {
+
+// Room for `want` bindings, keeping those held (the caller's stream orders
+// the copies; the old buffer is freed once they are done).
+fj_status result_reserve(fj_ctx *c, fj_result *r, u64 want) {
+    if (want <= r->cap) return FJ_OK;
+    const u64 ncap = std::max<u64>(std::max<u64>(want, 2 * r->cap), 1024);
+    const size_t bv = align256(sizeof(int32_t) * ncap * r->nvals), bh = align256(sizeof(uint32_t) * ncap * r->nhdl);
+    const size_t bytes = bv + bh + align256(sizeof(u64) * ncap);
+    void *nb = nullptr;
+    FJ_TRY(fj::pool_alloc(r->device, bytes, &nb));
+    int32_t *nv = (int32_t *)nb;
+    uint32_t *nh = (uint32_t *)((char *)nb + bv);
+    u64 *nm = (u64 *)((char *)nb + bv + bh);
+    if (r->E) {
+        for (int j = 0; j < r->nvals; j++)
+            FJ_HIP(hipMemcpyAsync(nv + j * ncap, r->vals + j * r->cap, sizeof(int32_t) * r->E,
+                                  hipMemcpyDeviceToDevice, c->stream));
+        for (int j = 0; j < r->nhdl; j++)
+            FJ_HIP(hipMemcpyAsync(nh + j * ncap, r->hdl + j * r->cap, sizeof(uint32_t) * r->E,
+                                  hipMemcpyDeviceToDevice, c->stream));
+        FJ_HIP(hipMemcpyAsync(nm, r->mult, sizeof(u64) * r->E, hipMemcpyDeviceToDevice, c->stream));
+        FJ_HIP(hipStreamSynchronize(c->stream));
+    }
+    fj::pool_free(r->device, r->buf, r->bytes);
+    r->buf = nb;
+    r->bytes = bytes;
+    r->vals = nv;
+    r->hdl = nh;
+    r->mult = nm;
+    r->cap = ncap;
+    return FJ_OK;
+}
+
+// The E final bindings of the current tile (frontier F[tail_from]) join the
+// factorized result.
+fj_status result_keep(Exec &x, uint32_t E) {
+    fj_ctx *c = x.c;
+    fj_result *r = x.res;
+    if (E == 0) return FJ_OK;
+    if (r->E + E > 0xFFFFFFFFull) return fail(FJ_ERR_UNSUPPORTED, "a factorized result holds 2^32 bindings or more");
+    FJ_TRY(result_reserve(c, r, r->E + E));
+    const FrontierDev &F = x.F[x.tail_from];
+    for (int j = 0; j < r->nvals; j++)
+        FJ_HIP(hipMemcpyAsync(r->vals + j * r->cap + r->E, F.vals + j * F.cap, sizeof(int32_t) * E,
+                              hipMemcpyDeviceToDevice, c->stream));
+    for (int j = 0; j < r->nhdl; j++)
+        FJ_HIP(hipMemcpyAsync(r->hdl + j * r->cap + r->E, F.hdl + j * F.cap, sizeof(uint32_t) * E,
+                              hipMemcpyDeviceToDevice, c->stream));
+    if (F.mult) {
+        FJ_HIP(hipMemcpyAsync(r->mult + r->E, F.mult, sizeof(u64) * E, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+        // the single empty binding of a plan that is all products
+        static const u64 one = 1;
+        FJ_HIP(hipMemcpyAsync(r->mult + r->E, &one, sizeof(u64), hipMemcpyHostToDevice, c->stream));
+        FJ_HIP(hipStreamSynchronize(c->stream));
+    }
+    r->E += E;
+    return FJ_OK;
+}
+
+// A tile's final bindings: expanded into rows, kept factorized, or (count
+// only) dropped.
+fj_status emit_or_keep(Exec &x, uint32_t E) {
+    if (x.res) return result_keep(x, E);
+    if (x.out) return emit_rows(x, E);
     return FJ_OK;
 }
 
@@ -1304,7 +1402,7 @@ fj_status exec_node(Exec &x, int k, uint32_t E) {
         const uint32_t surv = (uint32_t)(c->status_h->survivors - surv_base);
         if (x.stats && !emit) x.stats->survivors[k] += surv;
         if (emit) {
-            if (x.out) FJ_TRY(emit_rows(x, surv));
+            FJ_TRY(emit_or_keep(x, surv));
         } else if (surv) {
             FJ_TRY(exec_node(x, k + 1, surv));
         }
@@ -1350,7 +1448,7 @@ fj_status exec_scan_node(Exec &x, int cover_sub, u64 T, uint32_t) {
     for (int j = 0; j < sl.nout; j++) sl.out_col[j] = cover_col(LN.in_var[j]);
     sl.out = x.F[1];
     sl.emit = x.tail_from == 1;
-    sl.materialize = sl.emit && x.out != nullptr;
+    sl.materialize = sl.emit && (x.out != nullptr || x.res != nullptr);
     if (sl.emit) {
         sl.ntail = (int)x.tails.size();
         for (int q = 0; q < sl.ntail; q++) {
@@ -1388,7 +1486,7 @@ fj_status exec_scan_node(Exec &x, int cover_sub, u64 T, uint32_t) {
         FJ_TRY(sync_status(c));
         const uint32_t surv = (uint32_t)(c->status_h->survivors - surv_base);
         if (sl.emit) {
-            if (x.out) FJ_TRY(emit_rows(x, surv));
+            FJ_TRY(emit_or_keep(x, surv));
         } else {
             if (x.stats) x.stats->survivors[0] += surv;
             if (surv) FJ_TRY(exec_node(x, 1, surv));
@@ -1419,8 +1517,9 @@ fj_status check_exec_args(const fj_query *q, const fj_plan *p, fj_colt *const *c
 
 }  // namespace
 
-extern "C" fj_status fj_execute(fj_ctx *c, const fj_query *q, const fj_plan *p, fj_colt *const *colts,
-                                uint64_t *count, int32_t *out, uint64_t cap, uint64_t *written, fj_stats *stats) {
+static fj_status execute_impl(fj_ctx *c, const fj_query *q, const fj_plan *p, fj_colt *const *colts,
+                              uint64_t *count, int32_t *out, uint64_t cap, uint64_t *written, fj_stats *stats,
+                              fj_result *res) {
     if (!c || !q || !p || !colts || !count) return fail(FJ_ERR_ARG, "null argument");
     FJ_TRY(check_exec_args(q, p, colts));
     FJ_HIP(hipSetDevice(c->device));
@@ -1432,6 +1531,7 @@ extern "C" fj_status fj_execute(fj_ctx *c, const fj_query *q, const fj_plan *p, 
     x.out = cap ? out : nullptr;
     x.cap = out ? cap : 0;
     x.stats = stats;
+    x.res = res;
     x.nnodes = (int)p->nodes.size();
     x.tail_from = c->opt.tail == 1 ? x.nnodes : p->tail_from;
     x.C = (u64)c->opt.tile;
@@ -1502,6 +1602,16 @@ extern "C" fj_status fj_execute(fj_ctx *c, const fj_query *q, const fj_plan *p, 
         x.head_src.push_back(src);
     }
 
+    if (res) {
+        const fj::NodeLayout &LT0 = p->layout[x.tail_from];
+        res->nvals = (int)LT0.in_var.size();
+        res->nhdl = (int)LT0.in_hatom.size();
+        res->in_var.assign(LT0.in_var.begin(), LT0.in_var.end());
+        res->in_hatom.assign(LT0.in_hatom.begin(), LT0.in_hatom.end());
+        res->head_src = x.head_src;
+        res->tails = x.tails;
+    }
+
     // node descriptors
     size_t nd_bytes = align256(sizeof(NodeDev) * std::max(x.tail_from, 1));
     size_t em_bytes = align256(fj::emit_dev_size());
@@ -1560,7 +1670,7 @@ extern "C" fj_status fj_execute(fj_ctx *c, const fj_query *q, const fj_plan *p, 
         nd.nout_h = (int)LN.in_hatom.size();
         for (int i = 0; i < nd.nout_h; i++) nd.out_h_atom[i] = LN.in_hatom[i];
         nd.emit = (k == x.tail_from - 1);
-        nd.materialize = nd.emit && x.out != nullptr;
+        nd.materialize = nd.emit && (x.out != nullptr || x.res != nullptr);
         if (nd.emit) {
             nd.ntail = (int)x.tails.size();
             for (int i = 0; i < nd.ntail; i++) nd.tail[i] = x.tails[i];
@@ -1592,7 +1702,7 @@ extern "C" fj_status fj_execute(fj_ctx *c, const fj_query *q, const fj_plan *p, 
         for (const auto &T : x.tails) total *= T.root_len;
         c->status_h->count = total;
         FJ_HIP(hipMemcpyAsync(c->status_d, c->status_h, sizeof(u64), hipMemcpyHostToDevice, c->stream));
-        st = x.out ? emit_rows(x, 1) : FJ_OK;
+        st = emit_or_keep(x, 1);
     } else {
         st = exec_node(x, 0, 1);
     }
@@ -1611,6 +1721,90 @@ extern "C" fj_status fj_execute(fj_ctx *c, const fj_query *q, const fj_plan *p, 
         if (x.tail_from > 0) stats->survivors[x.tail_from - 1] = 0;
     }
     return (x.out && *count > x.cap) ? FJ_TRUNCATED : FJ_OK;
+}
+
+extern "C" fj_status fj_execute(fj_ctx *c, const fj_query *q, const fj_plan *p, fj_colt *const *colts,
+                                uint64_t *count, int32_t *out, uint64_t cap, uint64_t *written, fj_stats *stats) {
+    return execute_impl(c, q, p, colts, count, out, cap, written, stats, nullptr);
+}
+
+// ------------------------------------------------------ factorized results
+
+extern "C" fj_status fj_execute_factorized(fj_ctx *c, const fj_query *q, const fj_plan *p, fj_colt *const *colts,
+                                           fj_result **out, uint64_t *count, uint64_t *bindings) {
+    if (!out) return fail(FJ_ERR_ARG, "null argument");
+    *out = nullptr;
+    if (!c || !q || !count) return fail(FJ_ERR_ARG, "null argument");
+    fj_result *r = new fj_result;
+    r->device = c->device;
+    fj_status st = execute_impl(c, q, p, colts, count, nullptr, 0, nullptr, nullptr, r);
+    if (st != FJ_OK) {
+        hipStreamSynchronize(c->stream);
+        delete r;
+        return st;
+    }
+    r->count = *count;
+    if (bindings) *bindings = r->E;
+    *out = r;
+    return FJ_OK;
+}
+
+extern "C" fj_status fj_result_expand(fj_ctx *c, fj_result *r, uint64_t first, int32_t *out, uint64_t cap,
+                                      uint64_t *written) {
+    if (!c || !r || !written || (cap && !out)) return fail(FJ_ERR_ARG, "null argument");
+    *written = 0;
+    if (c->device != r->device) return fail(FJ_ERR_ARG, "the result is on another device than the context");
+    if (first >= r->count || cap == 0) return FJ_OK;
+    FJ_HIP(hipSetDevice(c->device));
+    const u64 n = std::min<u64>(cap, r->count - first);
+    FrontierDev F;
+    memset(&F, 0, sizeof(F));
+    F.vals = r->vals;
+    F.hdl = r->hdl;
+    F.mult = r->mult;
+    F.cap = r->cap;
+    F.nvals = r->nvals;
+    F.nhdl = r->nhdl;
+    // the emit descriptor names the caller's buffer, so it is written anew
+    r->emit_h.resize(fj::emit_dev_size());
+    fj::emit_dev_fill(r->emit_h.data(), F, r->in_var.data(), (int)r->in_var.size(), r->in_hatom.data(),
+                      (int)r->in_hatom.size(), r->tails.data(), (int)r->tails.size(), r->head_src.data(),
+                      (int)r->head_src.size(), out, n);
+    if (!r->emit_d) FJ_TRY(fj::pool_alloc(r->device, fj::emit_dev_size(), &r->emit_d));
+    FJ_HIP(hipMemcpyAsync(r->emit_d, r->emit_h.data(), fj::emit_dev_size(), hipMemcpyHostToDevice, c->stream));
+    const uint32_t E = (uint32_t)r->E;
+    if (!r->starts) {
+        // every binding's row count and their scan, once per result
+        r->starts_bytes = sizeof(u64) * (r->E + 1);
+        FJ_TRY(fj::pool_alloc(r->device, r->starts_bytes, (void **)&r->starts));
+        void *cnt = nullptr;
+        FJ_TRY(fj::pool_alloc(r->device, sizeof(u64) * r->E, &cnt));
+        fj_status st = FJ_OK;
+        if (fj::launch_emit_count(r->emit_d, E, (u64 *)cnt, c->status_d, c->stream) != hipSuccess)
+            st = fail(FJ_ERR_HIP, "emit count launch failed");
+        if (st == FJ_OK) st = scan_u64(c, (const u64 *)cnt, r->starts, r->E);
+        hipStreamSynchronize(c->stream);
+        fj::pool_free(r->device, cnt, sizeof(u64) * r->E);
+        if (st != FJ_OK) {
+            fj::pool_free(r->device, r->starts, r->starts_bytes);
+            r->starts = nullptr;
+            return st;
+        }
+    }
+    {
+        Timer t(c, FJ_T_EMIT);
+        FJ_HIP(fj::launch_emit_range(r->emit_d, E, r->starts, first, n, c->status_d, c->stream));
+    }
+    FJ_TRY(sync_status(c));
+    *written = n;
+    return FJ_OK;
+}
+
+extern "C" void fj_result_free(fj_result *r) {
+    if (!r) return;
+    hipSetDevice(r->device);
+    hipDeviceSynchronize();
+    delete r;
 }
 
 // ------------------------------------------------------------------ batches

@@ -1648,12 +1648,10 @@ __global__ void __launch_bounds__(256) k_emit_count(const EmitDev *__restrict__ 
     if (e < E) cnt[e] = emit_rows_of(*dp, e, status);
 }
 
-__device__ __forceinline__ void emit_row(const EmitDev &d, uint32_t E, const u64 *starts, u64 base, u64 r,
-                                         StatusDev *status) {
-    // binding r first (one row per binding is the common case), else search
-    uint32_t e = (uint32_t)(r < E ? r : E - 1);
-    if (E > 1 && !(starts[e] <= r && r < starts[e + 1])) e = upper_entry(starts, 0, E, r);
-    if (!CK(e < E && e < d.F.cap && r >= starts[e] && r < starts[e + 1] && base + r < d.out_rows)) return;
+// Result row r, of binding e (starts[e] <= r < starts[e + 1]), to output row o.
+__device__ __forceinline__ void emit_row_at(const EmitDev &d, uint32_t E, const u64 *starts, uint32_t e, u64 r, u64 o,
+                                            StatusDev *status) {
+    if (!CK(e < E && e < d.F.cap && r >= starts[e] && r < starts[e + 1] && o < d.out_rows)) return;
     u64 idx = r - starts[e];
     uint32_t rows[FJ_MAX_NODES];
     for (int q = d.ntail - 1; q >= 0; q--) {
@@ -1668,27 +1666,46 @@ __device__ __forceinline__ void emit_row(const EmitDev &d, uint32_t E, const u64
         rows[q] = T.L.offs ? T.L.offs[pos] : pos;
         if (!CK(rows[q] < T.L.nrows)) return;
     }
-    int32_t *o = d.out + (base + r) * (u64)d.nhead;
+    int32_t *dst = d.out + o * (u64)d.nhead;
     for (int j = 0; j < d.nhead; j++) {
         int s = d.head_src[j];
         if (s >= 0) {
-            o[j] = d.F.vals[(u64)s * d.F.cap + e];
+            dst[j] = d.F.vals[(u64)s * d.F.cap + e];
         } else {
             int z = -s - 1;
             int q = z / FJ_MAX_COLS, c = z % FJ_MAX_COLS;
             const TailDev &T = d.tail[q];
-            o[j] = T.cols[T.kcol[c]][rows[q]];
+            dst[j] = T.cols[T.kcol[c]][rows[q]];
         }
     }
 }
 
+// The binding of row r: r itself when every binding holds one row, else
+// the largest e with starts[e] <= r.
+__device__ __forceinline__ uint32_t binding_of(const u64 *starts, uint32_t E, u64 r) {
+    uint32_t e = (uint32_t)(r < E ? r : E - 1);
+    if (!(starts[e] <= r && r < starts[e + 1])) e = upper_entry(starts, 0, E, r);
+    return e;
+}
+
 // Rows [0, emit_rows) of the current emit, at output rows emit_base + r
-// (both set on the device by the emit's scan), grid-stride.
+// (both set on the device by the emit's scan), grid-stride.  Each thread
+// finds its row's binding on its own: with many waves in flight the search
+// hides behind the row's gathers, which bound the kernel.
 __global__ void __launch_bounds__(256) k_emit_rows(const EmitDev *__restrict__ dp, uint32_t E, const u64 *starts,
                                                    StatusDev *status) {
     const u64 nrows = status->emit_rows, base = status->emit_base;
+    if (E == 0) return;
     for (u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += (u64)gridDim.x * blockDim.x)
-        emit_row(*dp, E, starts, base, r, status);
+        emit_row_at(*dp, E, starts, binding_of(starts, E, r), r, base + r, status);
+}
+
+// Rows [first, first + n) of a factorized result to output rows [0, n).
+__global__ void __launch_bounds__(256) k_emit_range(const EmitDev *__restrict__ dp, uint32_t E, const u64 *starts,
+                                                    u64 first, u64 n, StatusDev *status) {
+    if (E == 0) return;
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x)
+        emit_row_at(*dp, E, starts, binding_of(starts, E, first + i), first + i, i, status);
 }
 
 // ------------------------------------------------------------- eager tries
@@ -1935,6 +1952,14 @@ hipError_t launch_emit_rows(const void *emit_dev, uint32_t E, const u64 *starts,
     if (!max_rows) return hipSuccess;
     const unsigned grid = (unsigned)std::min<u64>(blocks_for(max_rows, 256), 2048);
     hipLaunchKernelGGL(k_emit_rows, dim3(grid), dim3(256), 0, s, (const EmitDev *)emit_dev, E, starts, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit_range(const void *emit_dev, uint32_t E, const u64 *starts, u64 first, u64 n, StatusDev *st,
+                             hipStream_t s) {
+    if (!n) return hipSuccess;
+    const unsigned grid = (unsigned)std::min<u64>(blocks_for(n, 256), 4096);
+    hipLaunchKernelGGL(k_emit_range, dim3(grid), dim3(256), 0, s, (const EmitDev *)emit_dev, E, starts, first, n, st);
     return hipGetLastError();
 }
 

@@ -120,6 +120,10 @@ hipError_t launch_emit_count(const void *emit_dev, uint32_t E, unsigned long lon
 // grid-stride over at most max_rows.
 hipError_t launch_emit_rows(const void *emit_dev, uint32_t E, const unsigned long long *starts,
                             unsigned long long max_rows, StatusDev *st, hipStream_t s);
+// Rows [first, first + n) of E bindings laid out by starts, to output rows
+// [0, n) of the emit descriptor's output.
+hipError_t launch_emit_range(const void *emit_dev, uint32_t E, const unsigned long long *starts,
+                             unsigned long long first, unsigned long long n, StatusDev *st, hipStream_t s);
 // Exclusive scan of an emit's n > 0 row counts that also places the emit in
 // the output: st->emit_base = st->written, st->emit_rows = the total cut to
 // cap rows, st->written advanced.

@@ -167,6 +167,10 @@ def lib():
         L.fj_bushy_decompose.argtypes = [P(Bushy), P(C.c_int32), vp, vp]
         L.fj_execute_bushy.argtypes = [vp, P(QueryS), P(Bushy), vp, C.c_uint32, P(C.c_uint64), vp, C.c_uint64,
                                        P(C.c_uint64)]
+        L.fj_execute_factorized.argtypes = [vp, P(QueryS), vp, vp, P(vp), P(C.c_uint64), P(C.c_uint64)]
+        L.fj_result_expand.argtypes = [vp, vp, C.c_uint64, vp, C.c_uint64, P(C.c_uint64)]
+        L.fj_result_free.argtypes = [vp]
+        L.fj_result_free.restype = None
         L.fj_batch_create.argtypes = [vp, C.c_int32, vp, vp, vp, vp, P(vp)]
         L.fj_batch_run.argtypes = [vp, vp]
         L.fj_batch_free.argtypes = [vp]
@@ -188,7 +192,8 @@ def lib():
         L.fj_choose_plan.argtypes = [vp, vp, P(QueryS), vp, C.c_float, P(vp), P(C.c_int32), vp]
         for name in ("fj_ctx_create", "fj_timings", "fj_timings_reset", "fj_plan_from_binary",
                      "fj_plan_from_nodes", "fj_plan_get", "fj_filter_lt", "fj_filter_lt_batch", "fj_build_colt",
-                     "fj_colt_rebuild", "fj_colt_rebuild_many", "fj_execute", "fj_batch_create", "fj_batch_run", "fj_sketch_relation",
+                     "fj_colt_rebuild", "fj_colt_rebuild_many", "fj_execute", "fj_execute_factorized",
+                     "fj_result_expand", "fj_execute_bushy", "fj_bushy_decompose", "fj_batch_create", "fj_batch_run", "fj_sketch_relation",
                      "fj_greedy_order", "fj_plan_candidates", "fj_candidate_plan", "fj_mlp_create",
                      "fj_mlp_set_params", "fj_mlp_get_params", "fj_mlp_forward", "fj_mlp_gradient",
                      "fj_mlp_train_step", "fj_choose_plan"):
@@ -376,6 +381,17 @@ class Context:
         return int(cnt.value), int(wr.value), st
 
 
+    def execute_factorized(self, q: QueryS, plan: Plan, colts: Sequence["Colt"]) -> "Result":
+        """Run the plan but keep its final bindings instead of rows (a
+        factorized result); Result.expand writes pages of rows."""
+        arr = (C.c_void_p * len(colts))(*[c.h for c in colts])
+        h = C.c_void_p()
+        cnt = C.c_uint64(0)
+        nb = C.c_uint64(0)
+        _check(lib().fj_execute_factorized(self.h, C.byref(q), plan.h, arr, C.byref(h), C.byref(cnt),
+                                           C.byref(nb)))
+        return Result(h.value, self, int(cnt.value), int(nb.value), int(q.nhead), list(colts))
+
     def execute_bushy(self, q: QueryS, tree, rels, factor: bool = True, out=None):
         """Run a binary plan by its left-deep decomposition; rels: one
         (cols, sel, nsel) per atom.  Returns (count, written)."""
@@ -538,6 +554,37 @@ class Batch:
     def free(self):
         if getattr(self, "h", None) and _lib is not None:
             _lib.fj_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.free()
+
+
+class Result:
+    """A factorized result: count rows held as `bindings` final bindings.
+    It keeps its COLTs (and through them the relations) alive; they must not
+    be rebuilt while the result is in use."""
+
+    def __init__(self, handle: int, ctx: "Context", count: int, bindings: int, nhead: int, colts):
+        self.h = handle
+        self.ctx = ctx
+        self.count = count
+        self.bindings = bindings
+        self.nhead = nhead
+        self.keep = colts
+
+    def expand(self, first: int, out) -> int:
+        """Rows [first, first + len(out)) into out (device int32 [cap, nhead]);
+        returns how many were written."""
+        wr = C.c_uint64(0)
+        cap = int(out.shape[0])
+        _check(lib().fj_result_expand(self.ctx.h, self.h, int(first),
+                                      C.c_void_p(out.data_ptr()) if cap else None, cap, C.byref(wr)))
+        return int(wr.value)
+
+    def free(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.fj_result_free(self.h)
             self.h = None
 
     def __del__(self):

@@ -100,6 +100,33 @@ class DeviceQuery:
         return {"count": cnt, "rows": rows, "written": written, "stats": st, "colts": colts}
 
 
+    def run_factorized(self, plan: fj.Plan, page: Optional[int] = None, colts=None):
+        """Run with a factorized result, then expand it page by page (all at
+        once when page is None).  Returns dict(count, bindings, rows (sorted
+        numpy), pages)."""
+        import torch
+        if colts is None:
+            colts = self.build(plan)
+        res = self.ctx.execute_factorized(self.q, plan, colts)
+        try:
+            n = res.count
+            page = max(int(page if page is not None else n), 1)
+            out = torch.empty((min(page, max(n, 1)), self.q.nhead), dtype=torch.int32,
+                              device=f"cuda:{self.ctx.device}")
+            parts, first, pages = [], 0, 0
+            while first < n:
+                w = res.expand(first, out)
+                if w == 0:
+                    raise RuntimeError("expansion wrote no rows")
+                parts.append(out[:w].cpu().numpy())
+                first += w
+                pages += 1
+            rows = np.concatenate(parts) if parts else np.zeros((0, self.q.nhead), np.int32)
+            return {"count": n, "bindings": res.bindings, "rows": sort_rows(rows), "unsorted": rows,
+                    "pages": pages}
+        finally:
+            res.free()
+
     def run_bushy(self, tree, materialize: bool = True, factor: bool = True):
         """Run a binary plan (nested pairs of atom indices) by its left-deep
         decomposition.  Returns dict(count, rows (sorted numpy or None), written)."""
