@@ -86,7 +86,7 @@ def main():
     n_fact = dq.relations[0].nrows
     log(f"generated star workload in {time.time() - t0:.1f}s")
 
-    ctx = fj.Context(0, timing=True)
+    ctx = fj.Context(0, timing=2)   # events around the node-0 probe only
     d = runner.DeviceQuery(ctx, dq)
     plan = d.plan_binary([0, 1, 2, 3, 4], True)
     colts = d.build(plan)

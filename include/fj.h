@@ -87,7 +87,10 @@ typedef struct fj_colt fj_colt;
 typedef struct {
     int64_t tile;        /* max cover tuples per probe launch = frontier capacity [1<<24] */
     int32_t block;       /* threads per workgroup for probe kernels, 64..1024 [256] */
-    int32_t timing;      /* nonzero: time kernel classes with hipEvents [0] */
+    int32_t timing;      /* time kernel classes with hipEvents: 0 off [default];
+                            2: the node-0 probe (FJ_T_PROBE0) alone, two event
+                            records per launch of it and none elsewhere; any
+                            other nonzero value: every class */
     int32_t tail;        /* 0: multiply trailing single-cover nodes (default);
                             1: run every node through the probe kernel */
     int32_t generic;     /* 1: never use the specialised first-node scan kernel [0] */

@@ -130,16 +130,17 @@ struct Timer {
     int cls;
     hipEvent_t a = nullptr, b = nullptr;
     Timer(fj_ctx *ctx, int k) : c(ctx), cls(k) {
-        if (!c->opt.timing) return;
+        if (!on()) return;
         a = get();
         b = get();
         hipEventRecord(a, c->stream);
     }
     ~Timer() {
-        if (!c->opt.timing) return;
+        if (!on()) return;
         hipEventRecord(b, c->stream);
         c->pending.push_back({cls, a, b});
     }
+    bool on() const { return c->opt.timing == 2 ? cls == FJ_T_PROBE0 : c->opt.timing != 0; }
     hipEvent_t get() {
         if (!c->pool.empty()) {
             hipEvent_t e = c->pool.back();

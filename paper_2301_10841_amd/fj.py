@@ -283,7 +283,7 @@ class Context:
     """A libfj context bound to a device and a torch stream."""
 
     def __init__(self, device: int = 0, stream=None, tile: int = 0, block: int = 0,
-                 timing: bool = False, tail: int = 0, generic: bool = False, trie: int = 0):
+                 timing=False, tail: int = 0, generic: bool = False, trie: int = 0):
         import torch
         self.device = device
         if stream is None:
@@ -292,7 +292,7 @@ class Context:
         opt = Options()
         opt.tile = tile
         opt.block = block
-        opt.timing = 1 if timing else 0
+        opt.timing = int(timing)   # True: every kernel class; 2: the node-0 probe only
         opt.tail = tail
         opt.generic = 1 if generic else 0
         opt.trie = int(trie)
@@ -334,14 +334,14 @@ class Context:
 
     def filter_lt_batch(self, specs):
         """specs: list of (col tensor, bound, out tensor).  Returns the counts."""
-        n = len(specs)
-        cols = (C.c_void_p * max(n, 1))(*[c.data_ptr() for c, _, _ in specs])
-        nrows = (C.c_int64 * max(n, 1))(*[int(c.shape[0]) for c, _, _ in specs])
-        bounds = (C.c_int32 * max(n, 1))(*[int(b) for _, b, _ in specs])
-        outs = (C.c_void_p * max(n, 1))(*[o.data_ptr() for _, _, o in specs])
-        counts = (C.c_int64 * max(n, 1))()
-        _check(lib().fj_filter_lt_batch(self.h, n, cols, nrows, bounds, outs, counts))
-        return [int(counts[i]) for i in range(n)]
+        args = filter_args(specs)
+        self.filter_lt_prepared(args)
+        return [int(args[-1][i]) for i in range(args[0])]
+
+    def filter_lt_prepared(self, args):
+        """Run selections whose arguments filter_args() marshalled once; the
+        counts land in args[-1]."""
+        _check(lib().fj_filter_lt_batch(self.h, *args))
 
     # ---- COLTs
     def build_colt(self, q: QueryS, plan: Plan, atom: int, cols, sel=None, nsel: int = 0) -> "Colt":
@@ -362,14 +362,23 @@ class Context:
             return
         rels = (Relation * n)(*[_relation(*sp) for sp in specs])
         arr = (C.c_void_p * n)(*[c.h for c in colts])
-        _check(lib().fj_colt_rebuild_many(self.h, n, arr, rels))
+        self.rebuild_colts_prepared(n, arr, rels)
         for c, sp in zip(colts, specs):
             c.keep = (sp[0], sp[1])
+
+    def rebuild_colts_prepared(self, n: int, arr, rels):
+        """As rebuild_colts, with the handle and relation arrays already
+        marshalled (the caller keeps the buffers alive)."""
+        _check(lib().fj_colt_rebuild_many(self.h, n, arr, rels))
 
     # ---- join
     def execute(self, q: QueryS, plan: Plan, colts: Sequence["Colt"], out=None, stats: bool = False):
         """Returns (count, written, Stats or None).  out: device int32 [cap, nhead] or None."""
-        arr = (C.c_void_p * len(colts))(*[c.h for c in colts])
+        key = tuple(c.h for c in colts)
+        if getattr(self, "_exec_key", None) != key:
+            self._exec_key = key
+            self._exec_arr = (C.c_void_p * len(key))(*key)
+        arr = self._exec_arr
         cnt = C.c_uint64(0)
         wr = C.c_uint64(0)
         st = Stats() if stats else None
@@ -603,6 +612,18 @@ class Colt:
 
     def __del__(self):
         self.free()
+
+
+def filter_args(specs):
+    """fj_filter_lt_batch's arguments for specs = [(col, bound, out)], the
+    counts array last."""
+    n = len(specs)
+    cols = (C.c_void_p * max(n, 1))(*[c.data_ptr() for c, _, _ in specs])
+    nrows = (C.c_int64 * max(n, 1))(*[int(c.shape[0]) for c, _, _ in specs])
+    bounds = (C.c_int32 * max(n, 1))(*[int(b) for _, b, _ in specs])
+    outs = (C.c_void_p * max(n, 1))(*[o.data_ptr() for _, _, o in specs])
+    counts = (C.c_int64 * max(n, 1))()
+    return (n, cols, nrows, bounds, outs, counts)
 
 
 def _relation(cols, sel, nsel) -> Relation:

@@ -27,22 +27,30 @@ class DeviceQuery:
         self.q = fj.make_query([vs for _, vs in dq.atoms], dq.nvars, dq.head)
         self.sel: List = [None] * len(dq.atoms)
         self.nsel: List[int] = [0] * len(dq.atoms)
+        self._flt = None      # selections' marshalled arguments (the buffers are fixed)
+        self._rb = None       # (COLT handles, handle array, relation array) of the last rebuild
         self.apply_filters()
 
     def apply_filters(self):
         import torch
-        specs, atoms = [], []
-        for a, f in enumerate(self.dq.filters):
-            if f is None:
-                continue
-            col = self.rel_cols[self.dq.atoms[a][0]][f[0]]
-            if self.sel[a] is None:
-                self.sel[a] = torch.empty(max(int(col.shape[0]), 1), dtype=torch.int32, device=col.device)
-            specs.append((col, f[1], self.sel[a]))
-            atoms.append(a)
-        if specs:
-            for a, n in zip(atoms, self.ctx.filter_lt_batch(specs)):
-                self.nsel[a] = n
+        if self._flt is None:
+            specs, atoms = [], []
+            for a, f in enumerate(self.dq.filters):
+                if f is None:
+                    continue
+                col = self.rel_cols[self.dq.atoms[a][0]][f[0]]
+                if self.sel[a] is None:
+                    self.sel[a] = torch.empty(max(int(col.shape[0]), 1), dtype=torch.int32, device=col.device)
+                specs.append((col, f[1], self.sel[a]))
+                atoms.append(a)
+            self._flt = (atoms, fj.filter_args(specs) if specs else None)
+        atoms, args = self._flt
+        if args is None:
+            return
+        self.ctx.filter_lt_prepared(args)
+        counts = args[-1]
+        for i, a in enumerate(atoms):
+            self.nsel[a] = int(counts[i])
 
     def atom_cols(self, a: int):
         return self.rel_cols[self.dq.atoms[a][0]]
@@ -72,8 +80,26 @@ class DeviceQuery:
                 for a in range(len(self.dq.atoms))]
 
     def rebuild(self, colts):
-        """Rebuild every COLT of the query in one grouped pass."""
-        self.ctx.rebuild_colts(colts, [(self.atom_cols(a), self.sel[a], self.nsel[a]) for a in range(len(colts))])
+        """Rebuild every COLT of the query in one grouped pass.  The relation
+        array is marshalled once per set of COLTs; later calls only update
+        the selection sizes."""
+        import ctypes as C
+        n = len(colts)
+        if n == 0:
+            return
+        key = tuple(c.h for c in colts)
+        if self._rb is None or self._rb[0] != key:
+            specs = [(self.atom_cols(a), self.sel[a], self.nsel[a]) for a in range(n)]
+            rels = (fj.Relation * n)(*[fj._relation(*sp) for sp in specs])
+            self._rb = (key, (C.c_void_p * n)(*key), rels)
+            for c, sp in zip(colts, specs):
+                c.keep = (sp[0], sp[1])
+        else:
+            rels = self._rb[2]
+            for a in range(n):
+                if self.sel[a] is not None:
+                    rels[a].nsel = int(self.nsel[a])
+        self.ctx.rebuild_colts_prepared(n, self._rb[1], self._rb[2])
 
     def run(self, plan: fj.Plan, materialize: bool = True, cap: Optional[int] = None,
             stats: bool = False, colts=None):
