@@ -14,8 +14,9 @@ min(count, 1M) result rows.  ``value`` is fact tuples probed per second over
 whole steps.
 
 Prints one JSON line.  Extra fields: the dominant kernel's roofline (live
-HIP-event timing inside the library), per-phase times and the CPU oracle timed
-on the host (the ``cpu_baseline`` leg, the only part that runs the oracle).
+HIP-event timing inside the library, around the node-0 probe alone), the
+one-filter variant, the learned chooser's leg and the CPU oracle timed on the
+host (the ``cpu_baseline`` leg, the only part that runs the oracle).
 """
 
 import argparse

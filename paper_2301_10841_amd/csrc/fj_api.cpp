@@ -549,6 +549,7 @@ struct ColtGroup {
     size_t o_wpre = 0, o_roots = 0, o_pre = 0, o_fill = 0, meta_bytes = 0;
     size_t w_cntv = 0, w_ex = 0, w_bsum = 0, w_total = 0;
     std::vector<char> stage, last;   // host image of meta, and the last one uploaded
+    std::vector<char> last_key;      // the inputs that image was made from
     char *stage_h = nullptr;         // pinned copy source
     size_t stage_h_bytes = 0;
     void release() {
@@ -558,6 +559,7 @@ struct ColtGroup {
         stage_h = nullptr;
         stage_h_bytes = 0;
         last.clear();
+        last_key.clear();
     }
 };
 
@@ -573,7 +575,41 @@ constexpr u64 kFillChunk = 4096;   // words per fill block
 
 // Lay out and upload the group's descriptors for the COLTs' current
 // relations; wcap_min sizes the scratch (at least the current total).
+template <typename T>
+void key_put(std::vector<char> &key, const T &v) {
+    const char *b = (const char *)&v;
+    key.insert(key.end(), b, b + sizeof(T));
+}
+
 fj_status group_prepare(fj_ctx *c, ColtGroup &G, fj_colt *const *colts, int n, u64 wcap_min) {
+    // every member starts over: the root ranges over the current relation,
+    // inner levels are initialised again before their first force
+    for (int k = 0; k < n; k++) {
+        fj_colt *t = colts[k];
+        for (int l = 0; l <= t->nlev; l++) t->lev[l].nrows = (uint32_t)t->nrows;
+        for (int l = 0; l < t->nlev; l++) t->lev_ready[l] = false;
+        t->lev[0].offs = const_cast<uint32_t *>(t->sel);
+    }
+    // the uploaded image depends only on these inputs: when they are the
+    // last call's (a query rebuilt step after step), it is still current
+    std::vector<char> key;
+    key.reserve(64 + (size_t)n * (2 * sizeof(LevelDev) + sizeof(fj::FillList) + 128));
+    key_put(key, n);
+    key_put(key, wcap_min);
+    for (int k = 0; k < n; k++) {
+        const fj_colt *t = colts[k];
+        key_put(key, t);
+        key_put(key, t->nroot);
+        key_put(key, t->root_built);
+        key_put(key, t->nrows);
+        key_put(key, t->sel);
+        key_put(key, t->cols);
+        key_put(key, t->lev[0]);
+        key_put(key, t->lev[1]);
+        key_put(key, t->fill_h);
+    }
+    if (!G.last.empty() && key == G.last_key && G.n == n) return FJ_OK;
+    G.last_key.clear();
     G.n = n;
     std::vector<u64> wpre(n + 1, 0);
     for (int k = 0; k < n; k++) {
@@ -619,10 +655,7 @@ fj_status group_prepare(fj_ctx *c, ColtGroup &G, fj_colt *const *colts, int n, u
     memcpy(h + G.o_wpre, wpre.data(), sizeof(u64) * (n + 1));
     for (int k = 0; k < n; k++) {
         fj_colt *t = colts[k];
-        for (int l = 0; l <= t->nlev; l++) t->lev[l].nrows = (uint32_t)t->nrows;
-        for (int l = 0; l < t->nlev; l++) t->lev_ready[l] = false;
         LevelDev &R = t->lev[0];
-        R.offs = const_cast<uint32_t *>(t->sel);
         uint32_t *pre_d = (uint32_t *)(meta + G.o_pre) + 2 * k;
         fj::ForceArgs &a = descs[k];
         a.L = R;
@@ -659,6 +692,7 @@ fj_status group_prepare(fj_ctx *c, ColtGroup &G, fj_colt *const *colts, int n, u
         FJ_HIP(hipMemcpyAsync(meta, G.stage_h, G.meta_bytes, hipMemcpyHostToDevice, c->stream));
         G.last = G.stage;
     }
+    G.last_key = std::move(key);
     return FJ_OK;
 }
 
