@@ -1157,6 +1157,8 @@ struct Exec {
     uint32_t *dA = nullptr, *dB = nullptr;
     uint8_t *dA_j = nullptr, *dB_j = nullptr;
     fj_result *res = nullptr;           // factorized: keep the final bindings instead of rows
+    bool emit_pending = false;          // the last scan tile's emit was enqueued before its count was known
+    u64 emit_pending_base = 0;          // the survivor counter before that tile
 };
 
 void fill_level_sub(SubDev &S, const fj_colt *t, int level) {
@@ -1518,6 +1520,18 @@ fj_status exec_scan_node(Exec &x, int cover_sub, u64 T, uint32_t) {
             FJ_HIP(fj::launch_scan_probe(sl, c->stream));
         }
         if (x.stats) x.stats->tiles++;
+        if (sl.emit && x.out && !x.res && t0 + n >= T) {
+            // the last tile's rows: emitted on the device without a wait for
+            // its survivor count when the bindings are few (one workgroup);
+            // the host finishes a larger emit after its final wait
+            u64 *starts = c->emitbuf.as<u64>(align256(sizeof(u64) * x.C));
+            Timer t(c, FJ_T_EMIT);
+            FJ_HIP(fj::launch_emit_small_dev(x.emit_d, &c->status_d->survivors, surv_base, starts, c->status_d,
+                                             x.cap, c->stream));
+            x.emit_pending = true;
+            x.emit_pending_base = surv_base;
+            break;
+        }
         FJ_TRY(sync_status(c));
         const uint32_t surv = (uint32_t)(c->status_h->survivors - surv_base);
         if (sl.emit) {
@@ -1743,6 +1757,24 @@ static fj_status execute_impl(fj_ctx *c, const fj_query *q, const fj_plan *p, fj
     }
     if (st != FJ_OK) return st;
     FJ_TRY(sync_status(c));
+    if (x.emit_pending) {
+        const u64 E = c->status_h->survivors - x.emit_pending_base;
+        if (E > fj::emit_small_max()) {
+            // too many bindings for the one-workgroup emit, which left the
+            // status alone: the general path
+            FJ_TRY(emit_rows(x, (uint32_t)E));
+            FJ_TRY(sync_status(c));
+        } else if (E > 0 && c->status_h->emit_rows > 0) {
+            // placed, but too many rows to write in one workgroup
+            const u64 *starts = c->emitbuf.as<u64>(align256(sizeof(u64) * x.C));
+            {
+                Timer t(c, FJ_T_EMIT);
+                FJ_HIP(fj::launch_emit_rows(x.emit_d, (uint32_t)E, starts, c->status_h->emit_rows, c->status_d,
+                                            c->stream));
+            }
+            FJ_TRY(sync_status(c));
+        }
+    }
     x.written = c->status_h->written;
     u64 total = c->status_h->count;
     for (int q = 0; q < fj::kCountParts; q++) total += c->status_h->count_part[q * fj::kPartStride];

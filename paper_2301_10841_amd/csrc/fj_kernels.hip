@@ -1648,11 +1648,11 @@ __global__ void __launch_bounds__(256) k_emit_count(const EmitDev *__restrict__ 
     if (e < E) cnt[e] = emit_rows_of(*dp, e, status);
 }
 
-// Result row r, of binding e (starts[e] <= r < starts[e + 1]), to output row o.
-__device__ __forceinline__ void emit_row_at(const EmitDev &d, uint32_t E, const u64 *starts, uint32_t e, u64 r, u64 o,
+// Result row r, of binding e whose rows are [s0, s1), to output row o.
+__device__ __forceinline__ void emit_row_at(const EmitDev &d, uint32_t E, uint32_t e, u64 s0, u64 s1, u64 r, u64 o,
                                             StatusDev *status) {
-    if (!CK(e < E && e < d.F.cap && r >= starts[e] && r < starts[e + 1] && o < d.out_rows)) return;
-    u64 idx = r - starts[e];
+    if (!CK(e < E && e < d.F.cap && r >= s0 && r < s1 && o < d.out_rows)) return;
+    u64 idx = r - s0;
     uint32_t rows[FJ_MAX_NODES];
     for (int q = d.ntail - 1; q >= 0; q--) {
         const TailDev &T = d.tail[q];
@@ -1696,16 +1696,68 @@ __global__ void __launch_bounds__(256) k_emit_rows(const EmitDev *__restrict__ d
                                                    StatusDev *status) {
     const u64 nrows = status->emit_rows, base = status->emit_base;
     if (E == 0) return;
-    for (u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += (u64)gridDim.x * blockDim.x)
-        emit_row_at(*dp, E, starts, binding_of(starts, E, r), r, base + r, status);
+    for (u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += (u64)gridDim.x * blockDim.x) {
+        const uint32_t e = binding_of(starts, E, r);
+        emit_row_at(*dp, E, e, starts[e], starts[e + 1], r, base + r, status);
+    }
 }
 
 // Rows [first, first + n) of a factorized result to output rows [0, n).
 __global__ void __launch_bounds__(256) k_emit_range(const EmitDev *__restrict__ dp, uint32_t E, const u64 *starts,
                                                     u64 first, u64 n, StatusDev *status) {
     if (E == 0) return;
-    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x)
-        emit_row_at(*dp, E, starts, binding_of(starts, E, first + i), first + i, i, status);
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) {
+        const uint32_t e = binding_of(starts, E, first + i);
+        emit_row_at(*dp, E, e, starts[e], starts[e + 1], first + i, i, status);
+    }
+}
+
+// The emit of a node-0 scan's last tile, enqueued before its survivor count
+// is known on the host: E = *surv - surv_base bindings, read here.  Up to
+// kEmitSmall bindings it does what k_emit_count_small does (counts, scan,
+// place), keeping the scan in LDS, and when the rows are at most kEmitFuse
+// it also writes them, leaving emit_rows = 0; otherwise it leaves the status
+// untouched for the host's general path after its wait.
+constexpr u64 kEmitFuse = 1u << 16;
+
+__global__ void __launch_bounds__(kEmitSmallThreads) k_emit_small_dev(const EmitDev *__restrict__ dp,
+                                                                      const u64 *surv, u64 surv_base, u64 *starts,
+                                                                      StatusDev *status, u64 cap) {
+    __shared__ u64 lds[17];
+    __shared__ u64 sst[kEmitSmall + 1];
+    __shared__ u64 place[2];
+    const EmitDev &d = *dp;
+    const u64 En = *surv - surv_base;   // the same value for every thread
+    if (En == 0 || En > kEmitSmall) return;
+    const uint32_t E = (uint32_t)En;
+    const uint32_t e = threadIdx.x;
+    const u64 v = e < E ? emit_rows_of(d, e, status) : 0ull;
+    u64 tot;
+    const u64 ex = block_excl_scan<u64>(v, lds, tot);
+    if (e < E) {
+        starts[e] = ex;
+        sst[e] = ex;
+    }
+    if (threadIdx.x == 0) {
+        starts[E] = tot;
+        sst[E] = tot;
+        status->total = tot;
+        const u64 base = status->written;
+        const u64 rows = base < cap ? (tot < cap - base ? tot : cap - base) : 0;
+        status->emit_base = base;
+        status->written = base + rows;
+        status->emit_rows = rows <= kEmitFuse ? 0ull : rows;
+        place[0] = base;
+        place[1] = rows;
+    }
+    __syncthreads();
+    const u64 base = place[0], rows = place[1];
+    if (rows > kEmitFuse) return;   // the host's k_emit_rows writes them
+    for (u64 r = threadIdx.x; r < rows; r += blockDim.x) {
+        uint32_t b = (uint32_t)(r < E ? r : E - 1);
+        if (!(sst[b] <= r && r < sst[b + 1])) b = upper_entry_lds(sst, 0, E, r);
+        emit_row_at(d, E, b, sst[b], sst[b + 1], r, base + r, status);
+    }
 }
 
 // ------------------------------------------------------------- eager tries
@@ -1940,6 +1992,13 @@ hipError_t launch_emit_count_small(const void *emit_dev, uint32_t E, u64 *starts
 }
 
 uint32_t emit_small_max() { return kEmitSmall; }
+
+hipError_t launch_emit_small_dev(const void *emit_dev, const u64 *surv, u64 surv_base, u64 *starts, StatusDev *st,
+                                 u64 cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_emit_small_dev, dim3(1), dim3(kEmitSmallThreads), 0, s, (const EmitDev *)emit_dev, surv,
+                       surv_base, starts, st, cap);
+    return hipGetLastError();
+}
 
 hipError_t launch_emit_count(const void *emit_dev, uint32_t E, u64 *cnt, StatusDev *st, hipStream_t s) {
     hipLaunchKernelGGL(k_emit_count, dim3(blocks_for(E, 256)), dim3(256), 0, s, (const EmitDev *)emit_dev, E, cnt,

@@ -111,6 +111,8 @@ hipError_t launch_cover_fill(const NodeDev *nd, uint32_t E, const uint8_t *cov, 
 hipError_t launch_probe(const ProbeLaunch &p, hipStream_t s);
 // Counts, scan and output placement of E <= emit_small_max() bindings in
 // one workgroup (starts has E + 1 entries).
+hipError_t launch_emit_small_dev(const void *emit_dev, const unsigned long long *surv, unsigned long long surv_base,
+                                 unsigned long long *starts, StatusDev *st, unsigned long long cap, hipStream_t s);
 hipError_t launch_emit_count_small(const void *emit_dev, uint32_t E, unsigned long long *starts, StatusDev *st,
                                    unsigned long long cap, hipStream_t s);
 uint32_t emit_small_max();

@@ -374,3 +374,22 @@ def test_filters_match_numpy(fjm, ctx, torch_mod):
         assert np.array_equal(out[:k].cpu().numpy(), w)
         out2, k2 = ctx.filter_lt(c, b)
         assert k2 == k and np.array_equal(out2[:k2].cpu().numpy(), w)
+
+
+@pytest.mark.parametrize("n_left,n_keys,fanout", [(500, 50, 20), (800, 10, 100), (3000, 50, 40)],
+                         ids=["fused", "rows_apart", "many_bindings"])
+def test_last_tile_emit_paths(fjm, ctx, n_left, n_keys, fanout):
+    # the node-0 scan's last emit is enqueued before its binding count is
+    # known: few bindings and rows are written by one workgroup, few bindings
+    # with many rows by a second launch, many bindings by the general path
+    dq = datagen.fanout_chain(datagen.seed_for(9, 2), n_left=n_left, n_keys=n_keys, fanout=fanout)
+    want = oracle_run(dq, oracle_plan_binary(dq, [0, 1], True), counters=False)
+    got = gpu_run(fjm, ctx, dq, [0, 1], True)
+    assert got["count"] == want["count"] == n_left * fanout
+    assert_same_rows(got["rows"], want["rows"])
+    cut = gpu_run(fjm, ctx, dq, [0, 1], True, cap=777)
+    assert cut["count"] == n_left * fanout and cut["written"] == 777
+    from collections import Counter
+    w = Counter(map(tuple, want["rows"].tolist()))
+    g = Counter(map(tuple, cut["rows"].tolist()))
+    assert all(g[k] <= w[k] for k in g)
