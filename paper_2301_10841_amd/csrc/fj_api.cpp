@@ -220,6 +220,7 @@ struct fj_colt {
     u64 fill_lev_words[fj::kMaxLevels] = {0};
     bool lev_ready[fj::kMaxLevels] = {false};
     bool fill_stale = true;   // the device copies of the fill lists are out of date
+    u64 sized_rows = ~0ull;   // the root rows the maps and fill lists were last sized for
     std::vector<std::pair<void *, size_t>> allocs;   // pooled device buffers and their sizes
 };
 
@@ -307,6 +308,7 @@ fj_status colt_allocate(fj_colt *t) {
 void colt_free_all(fj_colt *t) {
     for (const auto &a : t->allocs) fj::pool_free(t->device, a.first, a.second);
     t->allocs.clear();
+    t->sized_rows = ~0ull;
 }
 
 }  // namespace
@@ -437,6 +439,7 @@ static fj_status colt_fill_list(fj_colt *t, u64 rows) {
 // copies are marked stale when they change.
 static fj_status colt_size(fj_colt *t) {
     const u64 rows = std::max<uint32_t>(t->nroot, 1);
+    if (rows == t->sized_rows) return FJ_OK;   // maps and fill lists are as the last sizing left them
     for (int l = 0; l < t->nlev; l++) {
         LevelDev &L = t->lev[l];
         if (!L.table) continue;
@@ -451,6 +454,7 @@ static fj_status colt_size(fj_colt *t) {
     if (memcmp(&old, &t->fill_h, sizeof(old)) != 0 ||
         memcmp(old_lev.data(), t->fill_lev_h, sizeof(fj::FillList) * fj::kMaxLevels) != 0)
         t->fill_stale = true;
+    t->sized_rows = rows;
     return FJ_OK;
 }
 
