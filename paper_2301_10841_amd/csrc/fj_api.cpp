@@ -963,7 +963,7 @@ fj_status fj_filter_lt_batch(fj_ctx *c, int32_t n, const int32_t *const *cols, c
     FJ_TRY(c->scanb.ensure(off[n] + 256, c->stream));
     FJ_TRY(zero_status_field(c, offsetof(StatusDev, ftotal), sizeof(c->status_h->ftotal)));
     {
-        // the non-empty selections in one grouped pass of three launches
+        // the non-empty selections in one grouped pass of two launches
         const int32_t *gc[FJ_MAX_ATOMS];
         u64 gr[FJ_MAX_ATOMS];
         int32_t gb[FJ_MAX_ATOMS];

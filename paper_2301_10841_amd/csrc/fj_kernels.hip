@@ -457,10 +457,11 @@ __global__ void __launch_bounds__(256) k_filter_write(const int32_t *__restrict_
         if (bits & (1u << r)) out[pos++] = (uint32_t)(first + r);
 }
 
-// Many selections in three launches: block b of a grouped launch belongs to
-// selection i with bpre[i] <= b < bpre[i + 1] and is its block b - bpre[i];
-// the middle launch scans each selection's block sums in a workgroup of its
-// own.
+// Many selections in two launches: block b of a grouped launch belongs to
+// selection i with bpre[i] <= b < bpre[i + 1] and is its block b - bpre[i].
+// The first launch counts each block's kept rows; in the second, each block
+// sums the counts of its selection's earlier blocks (a few hundred
+// contiguous words) for its place, and writes its rows in order.
 struct FilterGroup {
     int n;
     const int32_t *col[FJ_MAX_ATOMS];
@@ -490,31 +491,20 @@ __global__ void __launch_bounds__(256) k_filter_count_group(FilterGroup g) {
     if (threadIdx.x == 0) g.bsum[i][b] = tot;
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_filter_scan_group(FilterGroup g) {
-    __shared__ uint32_t lds[17];
-    const int i = blockIdx.x;
-    uint32_t *bsum = g.bsum[i];
-    const u64 nb = g.bpre[i + 1] - g.bpre[i];
-    uint32_t carry = 0;
-    for (u64 c = 0; c < nb; c += kScanThreads) {
-        const u64 k = c + threadIdx.x;
-        const uint32_t v = k < nb ? bsum[k] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan<uint32_t>(v, lds, tot);
-        if (k < nb) bsum[k] = carry + ex;
-        carry += tot;
-    }
-    if (threadIdx.x == 0) *g.total[i] = carry;
-}
-
 __global__ void __launch_bounds__(256) k_filter_write_group(FilterGroup g) {
     __shared__ uint32_t lds[17];
     const int i = filter_member(g, blockIdx.x);
     const uint32_t b = blockIdx.x - g.bpre[i];
+    const uint32_t *bsum = g.bsum[i];
+    uint32_t part = 0;
+    for (uint32_t k = threadIdx.x; k < b; k += 256) part += bsum[k];
+    uint32_t base;
+    block_excl_scan<uint32_t>(part, lds, base);
     const u64 first = ((u64)b * 256 + threadIdx.x) * kFilterRows;
     const uint32_t bits = filter_bits(g.col[i], g.rows[i], g.bound[i], first, g.vec[i]);
     uint32_t tot;
-    uint32_t pos = g.bsum[i][b] + block_excl_scan<uint32_t>((uint32_t)__popc(bits), lds, tot);
+    uint32_t pos = base + block_excl_scan<uint32_t>((uint32_t)__popc(bits), lds, tot);
+    if (threadIdx.x == 0 && b + 1 == g.bpre[i + 1] - g.bpre[i]) *g.total[i] = base + tot;
     uint32_t *out = g.out[i];
     for (int r = 0; r < kFilterRows; r++)
         if (bits & (1u << r)) out[pos++] = (uint32_t)(first + r);
@@ -1884,7 +1874,6 @@ hipError_t launch_filter_lt_group(int n, const int32_t *const *cols, const u64 *
     if (nb > 0x7fffffffu) return hipErrorInvalidValue;
     g.bpre[n] = (uint32_t)nb;
     hipLaunchKernelGGL(k_filter_count_group, dim3((unsigned)nb), dim3(256), 0, s, g);
-    hipLaunchKernelGGL(k_filter_scan_group, dim3((unsigned)n), dim3(kScanThreads), 0, s, g);
     hipLaunchKernelGGL(k_filter_write_group, dim3((unsigned)nb), dim3(256), 0, s, g);
     return hipGetLastError();
 }
