@@ -115,6 +115,8 @@ struct fj_ctx {
     void *desc_h = nullptr;         // pinned staging for descriptors
     size_t desc_h_bytes = 0;
     hipEvent_t desc_done = nullptr; // the last copy out of desc_h has finished
+    std::vector<char> desc_last;    // the descriptors last copied to the device
+    void *desc_last_dev = nullptr;  // and where they went
     // timing
     struct Pending { int cls; hipEvent_t a, b; };
     std::vector<hipEvent_t> pool;
@@ -1668,6 +1670,7 @@ static fj_status execute_impl(fj_ctx *c, const fj_query *q, const fj_plan *p, fj
     // node descriptors
     size_t nd_bytes = align256(sizeof(NodeDev) * std::max(x.tail_from, 1));
     size_t em_bytes = align256(fj::emit_dev_size());
+    if (nd_bytes + em_bytes > c->desc.bytes) c->desc_last.clear();   // a new device buffer holds nothing yet
     FJ_TRY(c->desc.ensure(nd_bytes + em_bytes, c->stream));
     // the staging buffer mirrors the device layout (node descriptors, then
     // the emit descriptor) and goes over in one copy; only that copy of the
@@ -1738,8 +1741,15 @@ static fj_status execute_impl(fj_ctx *c, const fj_query *q, const fj_plan *p, fj
                           x.head_src.data(), (int)x.head_src.size(), x.out, x.cap);
     }
     if (x.tail_from > 0 || x.out) {
+        // kernels only read the descriptors: when they are the ones already
+        // on the device (the same query run again), the copy is skipped
         const size_t bytes = x.out ? nd_bytes + fj::emit_dev_size() : sizeof(NodeDev) * x.tail_from;
-        FJ_HIP(hipMemcpyAsync(c->desc.p, c->desc_h, bytes, hipMemcpyHostToDevice, c->stream));
+        if (!(c->desc_last_dev == c->desc.p && c->desc_last.size() == bytes &&
+              memcmp(c->desc_last.data(), c->desc_h, bytes) == 0)) {
+            FJ_HIP(hipMemcpyAsync(c->desc.p, c->desc_h, bytes, hipMemcpyHostToDevice, c->stream));
+            c->desc_last.assign((const char *)c->desc_h, (const char *)c->desc_h + bytes);
+            c->desc_last_dev = c->desc.p;
+        }
     }
     FJ_HIP(hipEventRecord(c->desc_done, c->stream));
 
