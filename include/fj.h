@@ -230,18 +230,26 @@ typedef struct fj_result fj_result;
    kept, each standing for its multiplicity times the product of its
    trailing tries' lengths, instead of being expanded into rows.  *count
    (host) receives the exact result count and *bindings (host, nullable)
-   the number of bindings kept.  The result reads the COLTs' tries when it
-   is expanded: the COLTs must stay alive and must not be rebuilt until
-   fj_result_free.  Device memory for the bindings is owned by the result. */
+   the number of bindings kept.  The result reads the COLTs' tries and
+   their relations' columns when it is expanded: the COLTs and the columns
+   must stay alive, and the COLTs must not be rebuilt, until fj_result_free.
+   Device memory for the bindings is owned by the result (pooled).  Errors:
+   FJ_ERR_ARG for null arguments or those fj_execute refuses,
+   FJ_ERR_UNSUPPORTED for 2^32 bindings or more; *out is then null. */
 fj_status fj_execute_factorized(fj_ctx *ctx, const fj_query *q, const fj_plan *p, fj_colt *const *colts,
                                 fj_result **out, uint64_t *count, uint64_t *bindings);
 
 /* Rows [first, first + n) of a factorized result, in head order, written
    row-major to out (device, cap x q->nhead int32) with n = min(cap, count -
-   first); *written (host) receives n.  Rows keep one fixed order across
-   calls, so pages of consecutive ranges cover the result exactly once. */
+   first); *written (host) receives n, 0 when first >= count.  Rows keep
+   one fixed order across calls, so pages of consecutive ranges cover the
+   result exactly once.  The first call also counts every binding's rows
+   (device memory of 8 bytes per binding, kept with the result).  ctx must
+   be on the result's device (FJ_ERR_ARG otherwise); calls on one result
+   must not overlap. */
 fj_status fj_result_expand(fj_ctx *ctx, fj_result *r, uint64_t first, int32_t *out, uint64_t cap,
                            uint64_t *written);
+/* Frees the result and its device memory (null is a no-op). */
 void fj_result_free(fj_result *r);
 
 /* ------------------------------------------------------------- bushy plans */
