@@ -330,7 +330,7 @@ def main(argv=None):
     ap.add_argument("--margin", type=float, default=0.0)
     ap.add_argument("--train-seed", type=int, default=None)
     ap.add_argument("--heldout-seed", type=int, default=None)
-    ap.add_argument("--out", default="gpurun_out/chooser")
+    ap.add_argument("--out", default="chooser_report")
     ap.add_argument("--weights", default=None, help="skip training: evaluate these weights")
     args = ap.parse_args(argv)
     supply = QuerySupply(args.workers)     # fork before the GPU is touched
