@@ -151,3 +151,22 @@ def test_plan_invariance_rmat_small():
     for plan in (P.factor(P.binary2fj(q4, [0, 1, 2, 3])), P.gj_plan(q4, [0, 1, 2, 3]),
                  P.gj_plan(q4, [1, 3, 0, 2])):
         assert cfj.run(q4, plan, materialize=False)["count"] == want
+
+
+def test_fanout_chain_counts_and_rows():
+    # R(x, y) join S(y, z) where S holds exactly `fanout` rows per key: the
+    # count is |R| * fanout for every plan, and the rows are each R row
+    # paired with its key's S rows (written out here by a dictionary join)
+    q = datagen.fanout_chain(datagen.seed_for(9, 7), n_left=400, n_keys=30, fanout=7)
+    rx, ry = q.relations[0].cols
+    sy, sz = q.relations[1].cols
+    assert np.bincount(sy, minlength=30).tolist() == [7] * 30
+    by_key = {}
+    for y, z in zip(sy.tolist(), sz.tolist()):
+        by_key.setdefault(y, []).append(z)
+    want = np.array(sorted((x, y, z) for x, y in zip(rx.tolist(), ry.tolist()) for z in by_key[y]),
+                    np.int32)
+    for plan in all_plans(q):
+        r = cfj.run(q, plan, batch=97)
+        assert r["count"] == 400 * 7
+        assert np.array_equal(r["rows"], want)
