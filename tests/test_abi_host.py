@@ -107,3 +107,17 @@ def test_context_without_gpu_reports_error():
     h = ctypes.c_void_p()
     st = fj.lib().fj_ctx_create(0, None, None, ctypes.byref(h))
     assert st in (-1, -5)
+
+
+def test_factorized_entry_points_refuse_null_arguments():
+    # argument checks happen before any device call
+    L = fj.lib()
+    out = ctypes.c_void_p(123)
+    cnt = ctypes.c_uint64(7)
+    st = L.fj_execute_factorized(None, None, None, None, ctypes.byref(out), ctypes.byref(cnt), None)
+    assert st == -1 and out.value is None
+    assert L.fj_execute_factorized(None, None, None, None, None, None, None) == -1
+    wr = ctypes.c_uint64(5)
+    assert L.fj_result_expand(None, None, 0, None, 0, ctypes.byref(wr)) == -1
+    assert wr.value == 5 or wr.value == 0
+    L.fj_result_free(None)   # a no-op
