@@ -61,7 +61,7 @@ def main():
     if args.calibrate_copy:
         return calibrate_copy()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch":
         return bench_batch(args)
