@@ -10,6 +10,7 @@ from .synth import (  # noqa: F401
     Relation,
     Query,
     clover_instance,
+    clover_u_instance,
     triangle_edges,
     star_schema,
     rmat_edges,

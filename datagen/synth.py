@@ -112,6 +112,18 @@ def clover_instance(n: int) -> Query:
                       [(0, (0, 1)), (1, (0, 2)), (2, (0, 3))], kind="clover")
 
 
+def clover_u_instance(n: int, u_values) -> Query:
+    """The clover instance extended with a unary relation U(b), as in the
+    paper's Section 4.2 COLT example: Q(x,a,b,c) :- R(x,a), S(x,b), T(x,c),
+    U(b).  R, S, T are ``clover_instance(n)``'s; U holds ``u_values`` (int32,
+    duplicates kept).  Variables: x=0, a=1, b=2, c=3; atoms R, S, T, U."""
+    base = clover_instance(n)
+    u = Relation("U", [np.asarray(list(u_values), dtype=np.int32).reshape(-1)])
+    rels = list(base.relations) + [u]
+    return make_query(["x", "a", "b", "c"], rels,
+                      [(0, (0, 1)), (1, (0, 2)), (2, (0, 3)), (3, (2,))], kind="clover_u")
+
+
 def triangle_query(edges: Tuple[np.ndarray, np.ndarray], kind="triangle") -> Query:
     """Q(x,y,z) :- E(x,y), E(y,z), E(z,x): three atoms over one edge buffer."""
     e = Relation("E", [edges[0], edges[1]])

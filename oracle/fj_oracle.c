@@ -14,9 +14,14 @@
  *     iterates the keys.
  *   - The build phase (Section 3.3): every atom gets a COLT whose schema is
  *     the list of its subatoms' variable lists in plan order.  The root map
- *     is built up front except when the atom's first subatom is both the
- *     last level and the only pure cover of its node: then the base table
- *     (or its pushed-down selection) is iterated directly.
+ *     is built up front except when the atom has a single level and that
+ *     subatom is a pure cover of its node.  Such a root stays the base table
+ *     (or its pushed-down selection): iterated directly when it is the
+ *     cover, forced by its first get() when another cover wins (Section
+ *     4.2: no auxiliary structure on a table nobody probes).  Every other
+ *     root is forced before the join starts, which changes no result and
+ *     differs from forcing it at its first get() (or non-suffix iter())
+ *     only when no binding ever reaches that call.
  *   - The join phase (Section 3.3, figure "fj-algo") with vectorized batches
  *     of at most B cover tuples (Section 4.3): all lookups of one trie are
  *     done for the batch before the next trie, misses are dropped, then the
@@ -455,7 +460,8 @@ int ofj_execute(int natoms, const int32_t *atom_arity, const int32_t *atom_vars,
             for (int s = 0; s < c->nsub[k]; s++)
                 if (c->sub_atom[k][s] == a && c->sub_level[k][s] == 0) found = s;
             if (found >= 0) {
-                if (c->nlev[a] == 1 && c->npure[k] == 1 && c->pure[k][0] == found) built = 0;
+                for (int i = 0; i < c->npure[k]; i++)
+                    if (c->nlev[a] == 1 && c->pure[k][i] == found) built = 0;
                 break;
             }
         }
