@@ -40,7 +40,9 @@ typedef enum {
     FJ_ERR_PLAN_NO_PURE_COVER = -3, /* a node has no cover free of bound vars */
     FJ_ERR_OOM = -4,                /* device or host allocation failed      */
     FJ_ERR_HIP = -5,                /* a HIP runtime call failed             */
-    FJ_ERR_UNSUPPORTED = -6         /* outside the documented limits         */
+    FJ_ERR_UNSUPPORTED = -6,        /* outside the documented limits         */
+    FJ_ERR_INTERNAL = -7            /* a device bounds check or an internal
+                                       consistency check failed (a library bug) */
 } fj_status;
 
 #define FJ_MAX_COLS 8     /* columns per relation / variables per subatom */
@@ -269,10 +271,11 @@ typedef struct {
     int32_t right[FJ_MAX_BUSHY];
 } fj_bushy;
 
-/* Decompose a binary plan into left-deep plans (Section 2.2): every join
-   node that is a right child becomes the root of its own plan, which is
-   evaluated first and its result materialized; the tree's left spines give
-   each plan's order.  Writes the plans in evaluation order (the whole plan
+/* Split a binary plan into left-deep plans (Section 2.2).  A join whose
+   result feeds its parent from the right, with the subtree under it, is
+   run as a plan of its own, ahead of the plan that consumes it, and its
+   result is materialized as a relation; what remains of each tree along
+   its left edge, read from the bottom, is that plan's left-deep order.  Writes the plans in evaluation order (the whole plan
    last) to *nplans (host) and, for plan k, its inputs in left-deep order to
    inputs[k * FJ_MAX_ATOMS + i] (host, FJ_MAX_BUSHY * FJ_MAX_ATOMS entries)
    with their number in ninputs[k] (host, FJ_MAX_BUSHY entries): an input

@@ -25,7 +25,18 @@ Tiers
   ``cfj``; pinned by the paper's decomposition example and by nested-loop
   enumeration of the query result.
 
-Pins: see ``tests/test_oracle_*.py``.  Parity unpinned: nothing in the
-join-result tiers; the MLP reference in ``mlp`` is pinned by finite
-differences only (the paper has no learned component).
+* ``stats``   -- per-relation sketches (row count, distinct counts, top-k
+  frequencies) and the greedy left-deep order of the plain baseline plan.
+* ``mlp``     -- a float64 perceptron (forward, backward, Adam) that the
+  learned plan chooser's kernels are checked against.
+
+Pins: see ``tests/test_oracle_*.py``.  The join tiers are pinned by the
+paper's worked plans, brute force, closed forms, the clover instance's probe
+counts and its Section 4.2 extension's forced tries, and Generic Join's
+triangle counters derived from vertex degrees.  ``mlp`` is pinned by a
+hand-worked forward and backward pass, central finite differences, the
+all-active ReLU closed form and the closed form of Adam's first two steps;
+``stats`` by hand-counted sketches and hand-worked greedy orders.  Parity
+unpinned: the chooser's estimate features (this library's own definition;
+they change speed, never results).
 """

@@ -41,23 +41,24 @@ def atom_vars(query, a: int) -> Tuple[int, ...]:
 
 
 def binary2fj(query, order: Sequence[int]) -> Plan:
-    """Left-deep binary plan [R1..Rm] (atom indices) -> Free Join plan."""
+    """Left-deep binary plan [R1..Rm] (atom indices) -> Free Join plan
+    (Section 4.1): node i covers the variables R_i adds to those of the
+    relations before it and, for i < m, looks R_{i+1} up on the variables
+    it shares with R_1..R_i."""
     order = list(order)
     if sorted(order) != list(range(len(query.atoms))):
         raise PlanError("the left-deep order must list every atom once")
+    m = len(order)
+    seen = [set()]                       # seen[i]: variables of R_1..R_i
+    for a in order:
+        seen.append(seen[-1] | set(atom_vars(query, a)))
     plan: Plan = []
-    first = order[0]
-    phi: Node = [(first, atom_vars(query, first))]
-    available = set(atom_vars(query, first))
-    for s in order[1:]:
-        sv = atom_vars(query, s)
-        probe = tuple(v for v in sv if v in available)
-        phi.append((s, probe))
-        plan.append(phi)
-        rest = tuple(v for v in sv if v not in available)
-        phi = [(s, rest)]
-        available |= set(rest)
-    plan.append(phi)
+    for i, a in enumerate(order):
+        node = [(a, tuple(v for v in atom_vars(query, a) if v not in seen[i]))]
+        if i + 1 < m:
+            b = order[i + 1]
+            node.append((b, tuple(v for v in atom_vars(query, b) if v in seen[i + 1])))
+        plan.append(node)
     return plan
 
 

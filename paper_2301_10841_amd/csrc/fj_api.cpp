@@ -165,7 +165,7 @@ fj_status sync_status(fj_ctx *c) {
         // report once, then let the context continue
         hipMemsetAsync(&c->status_d->err_line, 0, 2 * sizeof(uint32_t), c->stream);
         hipStreamSynchronize(c->stream);
-        return fail(FJ_ERR_HIP, msg);
+        return fail(FJ_ERR_INTERNAL, msg);
     }
     return FJ_OK;
 }
@@ -206,6 +206,7 @@ struct fj_colt {
     uint32_t nroot = 0;      // rows the root ranges over
     uint32_t cap_rows = 0;   // rows the buffers were sized for
     bool root_built = false;
+    bool root_lazy = false;  // unbuilt root that a probe may force (its map is allocated)
     int lev_nk[fj::kMaxLevels] = {0};
     int lev_var[fj::kMaxLevels][FJ_MAX_COLS] = {{0}};
     LevelDev lev[fj::kMaxLevels + 1];
@@ -273,8 +274,8 @@ fj_status colt_allocate(fj_colt *t) {
         // each offset (written when its parent is forced)
         if (l > 0 && t->lev_nk[l] == 1) FJ_TRY(colt_alloc(t, &L.kv, n));
         FJ_TRY(colt_alloc(t, &L.st, n));
-        if (l == 0 && !t->root_built && t->nlev == 1) {
-            // a base table iterated directly is never forced: no map, no scratch
+        if (l == 0 && !t->root_built && !t->root_lazy && t->nlev == 1) {
+            // a base table only ever iterated directly: no map, no scratch
             L.nk = t->lev_nk[l];
             L.mode = fj::KM_ZERO;
             continue;
@@ -355,7 +356,7 @@ static fj_status force_queue(fj_ctx *c, fj_colt *t, int l, uint32_t nh, u64 W_kn
         FJ_TRY(sync_status(c));
         W = c->status_h->total32;
     }
-    if (W > Wmax) return fail(FJ_ERR_HIP, "forced offsets exceed the relation size");
+    if (W > Wmax) return fail(FJ_ERR_INTERNAL, "forced offsets exceed the relation size");
     fj::ForceLaunch f;
     f.L = L;
     f.C = C;
@@ -1058,6 +1059,7 @@ fj_status fj_build_colt(fj_ctx *c, const fj_query *q, const fj_plan *p, int32_t 
     t->cap_rows = t->nroot;
     // the ablation's tries build every root map ahead
     t->root_built = p->root_built[atom] || c->opt.trie >= 1;
+    t->root_lazy = !t->root_built && p->root_lazy[atom];
     t->nlev = p->nlev[atom];
     for (int l = 0; l < t->nlev; l++) {
         const fj::Subatom &s = p->lev[atom][l];
@@ -1423,7 +1425,7 @@ fj_status exec_node(Exec &x, int k, uint32_t E) {
             // each round forces the tries the deferred tuples met, so a tuple
             // advances by at least one lookup per round
             if (++rounds > (int)p->nodes[k].size() + 1)
-                return fail(FJ_ERR_HIP, "lazy forcing made no progress");
+                return fail(FJ_ERR_INTERNAL, "lazy forcing made no progress");
             uint32_t nd_n = (uint32_t)(c->status_h->deferred - def_base);
             def_base = c->status_h->deferred;
             if (x.stats) x.stats->deferred += nd_n;
@@ -1507,7 +1509,7 @@ fj_status exec_scan_node(Exec &x, int cover_sub, u64 T, uint32_t) {
                     if (node[i].atom == Td.atom) sl.tail_lk[q] = j;
                     j++;
                 }
-                if (sl.tail_lk[q] < 0) return fail(FJ_ERR_HIP, "tail trie not reached by the first node");
+                if (sl.tail_lk[q] < 0) return fail(FJ_ERR_INTERNAL, "tail trie not reached by the first node");
             }
         }
     }
@@ -1565,6 +1567,8 @@ fj_status check_exec_args(const fj_query *q, const fj_plan *p, fj_colt *const *c
                 if (t->lev_var[l][j] != p->lev[a][l].vars[j]) return fail(FJ_ERR_ARG, "COLT schema does not match the plan");
         }
         if (p->root_built[a] && !t->root_built) return fail(FJ_ERR_ARG, "COLT root rule does not match the plan");
+        if (p->root_lazy[a] && !t->root_built && !t->root_lazy)
+            return fail(FJ_ERR_ARG, "COLT root rule does not match the plan");
     }
     std::string err;
     return fj::check_query(*q, err) == FJ_OK ? FJ_OK : fail(FJ_ERR_ARG, err);

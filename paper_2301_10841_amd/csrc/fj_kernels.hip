@@ -858,6 +858,25 @@ __global__ void __launch_bounds__(256) k_cover_choose(const NodeDev *__restrict_
     }
     cov[e] = (uint8_t)(nd.pure[best] | (keys_mode << 7));
     cnt[e] = n;
+    // The first lookup after the cover, in node order, is reached by the
+    // binding's first cover tuple whenever the cover is not empty, so its
+    // get() is certain: its trie joins the force queue now, with the
+    // covers', instead of deferring every tuple that meets it unforced.
+    // The forced tries are the ones a tuple-at-a-time run forces.
+    if (forced ? n == 0 : trie_len(S, best_p) == 0) return;
+    for (int j = 0; j < nd.nsub; j++) {
+        if (j == nd.pure[best]) continue;
+        const SubDev &P = nd.sub[j];
+        if (P.level == 0 && !P.L.fq) break;   // a root built up front
+        const uint32_t ph = handle_of(P, nd.in, nd, e);
+        if (!CK(ph < P.L.npos)) return;
+        if (P.L.st[ph] == 0u && atomicCAS(&P.L.st[ph], 0u, kQueued) == 0u) {
+            const uint32_t pos = atomicAdd(&status->fq_n[P.fq_slot], 1u);
+            if (CK(pos < P.L.npos)) P.L.fq[pos] = ph;
+            atomicAdd(&status->pending, 1u);
+        }
+        break;
+    }
 }
 
 __global__ void __launch_bounds__(256) k_cover_fill(const NodeDev *__restrict__ ndp, uint32_t E, const uint8_t *cov,
@@ -1019,7 +1038,9 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
             if (!CK(ph < P.L.npos)) { survive = false; break; }
             const uint32_t st = P.L.st[ph];
             if (st == 0 || st == kQueued) {
-                if (!CK(P.level > 0)) { survive = false; break; }
+                // an inner trie, or a root left as its base table by the
+                // build phase (a single-level pure cover of this node)
+                if (!CK(P.level > 0 || P.L.fq != nullptr)) { survive = false; break; }
                 if (st == 0 && atomicCAS(&P.L.st[ph], 0u, kQueued) == 0u) {
                     uint32_t pos = atomicAdd(&status->fq_n[P.fq_slot], 1u);
                     if (CK(pos < P.L.npos)) P.L.fq[pos] = ph;

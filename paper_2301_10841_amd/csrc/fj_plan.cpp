@@ -72,23 +72,19 @@ fj_status check_query(const fj_query &q, std::string &err) {
     return FJ_OK;
 }
 
-// Section 4.1, figure "bj2fj": iterate the left relation; each next relation
-// is probed with the variables already available (those of the emitted nodes
-// and of the current one) and its remaining variables start the next node.
+// Section 4.1: a left-deep binary plan R_1 ... R_m becomes one node per
+// relation.  Node i iterates the variables R_i adds to those of R_1..R_{i-1}
+// and, unless it is the last node, looks R_{i+1} up on the variables it
+// shares with R_1..R_i (reading A2: the current relation's variables count
+// as available).
 static std::vector<std::vector<Subatom>> binary_to_fj(const fj_query &q, const int32_t *order, int n) {
-    std::vector<std::vector<Subatom>> plan;
-    int r = order[0];
-    std::vector<Subatom> cur{make_sub(q, r, atom_vset(q, r))};
-    VarSet avail = atom_vset(q, r);
-    for (int i = 1; i < n; i++) {
-        int s = order[i];
-        VarSet sv = atom_vset(q, s);
-        cur.push_back(make_sub(q, s, sv & avail));
-        plan.push_back(cur);
-        cur.assign(1, make_sub(q, s, sv & ~avail));
-        avail |= sv;
+    std::vector<VarSet> bound(n + 1, 0);   // bound[i]: variables of the first i relations
+    for (int i = 0; i < n; i++) bound[i + 1] = bound[i] | atom_vset(q, order[i]);
+    std::vector<std::vector<Subatom>> plan(n);
+    for (int i = 0; i < n; i++) {
+        plan[i].push_back(make_sub(q, order[i], atom_vset(q, order[i]) & ~bound[i]));
+        if (i + 1 < n) plan[i].push_back(make_sub(q, order[i + 1], atom_vset(q, order[i + 1]) & bound[i + 1]));
     }
-    plan.push_back(cur);
     return plan;
 }
 
@@ -186,15 +182,22 @@ static fj_status finish_plan(const fj_query &q, const std::vector<std::vector<Su
         for (const auto &s : nodes[k]) lev_at[s.atom]++;
         bound |= nv;
     }
-    // build-phase rule for roots: iterate the base table directly only when
-    // the atom's first subatom is its single level and the only pure cover.
+    // build-phase rule for roots (Section 4.2: no auxiliary structure on a
+    // table nobody probes): a single-level atom whose subatom is a pure
+    // cover of its node keeps its base table.  When it is the node's only
+    // pure cover it is always iterated directly; when other covers compete
+    // for some bindings it is forced by the first probe that reaches it.
     for (int a = 0; a < q.natoms; a++) {
         out->root_built[a] = true;
+        out->root_lazy[a] = false;
         for (int k = 0; k < nn; k++) {
             for (int i = 0; i < (int)nodes[k].size(); i++) {
-                if (nodes[k][i].atom == a && out->sub_level[k][i] == 0) {
-                    const auto &pc = out->layout[k].pure;
-                    if (out->nlev[a] == 1 && pc.size() == 1 && pc[0] == i) out->root_built[a] = false;
+                if (nodes[k][i].atom != a || out->sub_level[k][i] != 0 || out->nlev[a] != 1) continue;
+                const auto &pc = out->layout[k].pure;
+                for (int j = 0; j < (int)pc.size(); j++) {
+                    if (pc[j] != i) continue;
+                    out->root_built[a] = false;
+                    out->root_lazy[a] = pc.size() > 1;
                 }
             }
         }

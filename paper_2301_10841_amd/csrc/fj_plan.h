@@ -57,6 +57,9 @@ struct fj_plan {
     int sub_level[FJ_MAX_NODES][FJ_MAX_ATOMS] = {};  // [node][subatom] -> level in its atom
     fj::NodeLayout layout[FJ_MAX_NODES + 1];          // nnodes + 1 used (last = final)
     bool root_built[FJ_MAX_ATOMS] = {false};
+    // an unbuilt root that another cover of its node may win: forced by the
+    // first probe that reaches it, so its map is allocated but not filled
+    bool root_lazy[FJ_MAX_ATOMS] = {false};
     int tail_from = 0;                        // nodes >= tail_from are single-cover products
 };
 

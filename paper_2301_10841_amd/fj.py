@@ -26,7 +26,8 @@ CAND_BINARY = 0
 CAND_GJ = 1
 
 STATUS = {0: "FJ_OK", 1: "FJ_TRUNCATED", -1: "FJ_ERR_ARG", -2: "FJ_ERR_PLAN_INVALID",
-          -3: "FJ_ERR_PLAN_NO_PURE_COVER", -4: "FJ_ERR_OOM", -5: "FJ_ERR_HIP", -6: "FJ_ERR_UNSUPPORTED"}
+          -3: "FJ_ERR_PLAN_NO_PURE_COVER", -4: "FJ_ERR_OOM", -5: "FJ_ERR_HIP", -6: "FJ_ERR_UNSUPPORTED",
+          -7: "FJ_ERR_INTERNAL"}
 TIMERS = ("filter", "build", "cover", "probe", "probe0", "force", "emit", "scan")
 
 

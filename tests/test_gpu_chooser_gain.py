@@ -5,7 +5,7 @@ order converted and factored) and with the plan the committed network picks.
 End-to-end time = choice (host + GPU inference) + root builds + join, median
 of 5 runs each.  Both plans must give the same count; the learned total must
 not exceed the plain total.  (On the 512 held-out queries of the training
-run the learned total was 0.71 of the plain total; subsets of 64 of them
+run the learned total was 0.771 of the plain total; subsets of 64 of them
 exceed 1.0 with probability below 0.1%.)"""
 
 import os

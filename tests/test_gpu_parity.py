@@ -83,9 +83,10 @@ def test_clover_instance(fjm, ctx_small, n):
     assert gj["count"] == 1
 
 
-def test_clover_u_laziness(fjm, ctx_small):
-    # Section 4.2 example: [[R(x,a),S(x),T(x)],[U(b),S(b)],[T(c)]]: only the
-    # sub-tries reached from x0 are ever forced
+def test_clover_u_random_rows(fjm, ctx_small):
+    # Section 4.2's plan [[R(x,a),S(x),T(x)],[U(b),S(b)],[T(c)]] on a random
+    # bag instance: count and rows against the oracle (which tries get
+    # forced is checked in test_gpu_laziness.py)
     dq = datagen.random_tiny_query(4, "clover_u", max_rows=12, domain=4)
     nodes = [[(0, (0, 1)), (1, (0,)), (2, (0,))], [(3, (2,)), (1, (2,))], [(2, (3,))]]
     want = oracle_run(dq, nodes)
