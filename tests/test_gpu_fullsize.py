@@ -1,8 +1,10 @@
-"""Parity at the workloads' full sizes, where the oracle cannot run the whole
-query: R-MAT with 2^22 vertices and 50M edges (plan invariance, and the
-triangles through sampled vertices against the oracle and the closed form),
+"""Parity at the workloads' full sizes: R-MAT with 2^22 vertices and 50M
+edges (the triangle count against the oracle's, summed over disjoint parts
+of x by a committed script, plan invariance, and the triangles through
+sampled vertices against the oracle and the closed form),
 and batched-mix queries at full relation sizes (counts against the oracle)."""
 
+import os
 import sys
 
 import numpy as np
@@ -42,6 +44,15 @@ def _count(runner, ctx, dq, order=None, nodes=None):
     return r["count"]
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rmat_s22_triangles.txt")
+
+
+def golden_triangles():
+    """The oracle's count for the full graph (tests/golden/make_rmat_triangles.py)."""
+    lines = [ln for ln in open(GOLDEN) if ln.strip() and not ln.startswith("#")]
+    return int(lines[0])
+
+
 def test_rmat_full_scale_triangles(env):
     fj, runner, ctx = env
     src, dst = datagen.rmat_edges(datagen.seed_for(3, 1), 22, 50_000_000)
@@ -51,7 +62,7 @@ def test_rmat_full_scale_triangles(env):
     gj = _count(runner, ctx, tq, nodes=gj_nodes(tq, [0, 1, 2]))
     conv = _count(runner, ctx, tq, order=[0, 1, 2])
     _say("triangles", gj, conv)
-    assert gj == conv
+    assert gj == conv == golden_triangles()
     # the triangles through 256 sampled x vertices use exactly the R rows
     # leaving the sample, the S rows those reach and the T rows closing back
     rng = np.random.default_rng(99)
