@@ -57,6 +57,23 @@ def cycle_count(src, dst, k: int) -> int:
     return int(q.multiply(p.T).sum())
 
 
+def cycle4_count_blocked(src, dst, rows_per_block: int = 1 << 14) -> int:
+    """trace(A^4) = sum over (u, v) of (A^2)[u, v] (A^2)[v, u], with A^2
+    formed one block of rows u at a time: the block's rows A[U, :] A and
+    its columns A A[:, U] (transposed) are multiplied elementwise and summed,
+    so memory stays bounded for graphs whose A^2 does not fit."""
+    n = _domain(src, dst)
+    a = _mult_matrix(src, dst, n)
+    ac = a.tocsc()
+    total = 0
+    for u0 in range(0, n, rows_per_block):
+        u1 = min(n, u0 + rows_per_block)
+        rows = a[u0:u1, :] @ a                # (A^2)[U, :]
+        cols = (a @ ac[:, u0:u1]).T.tocsr()   # (A^2)[:, U] transposed
+        total += int(rows.multiply(cols).sum())
+    return total
+
+
 def chain_count(rels) -> int:
     """1^T M_1 ... M_k 1 for R1(x0,x1), ..., Rk(x_{k-1},x_k)."""
     n = _domain(*[c for r in rels for c in r])

@@ -76,3 +76,50 @@ def test_batch_refuses_plans_with_inner_probes(env):
     assert e.value.status == -6
     for c in colts:
         c.free()
+
+
+def _golden_batch_counts():
+    import os
+    f = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch_seed4_counts.txt")
+    out = {}
+    for ln in open(f):
+        if ln.startswith("#") or not ln.strip():
+            continue
+        i, kind, n = ln.split()
+        out[int(i)] = (kind, int(n))
+    return out
+
+
+def test_batch_full_workload_matches_oracle(env):
+    # the batched workload at its real shape: the 256 queries of
+    # batch_mix(seed_for(4, 0)) (relations of 1K-2M rows) in one persistent
+    # launch, against the oracle's counts (tests/golden/make_batch_counts.py),
+    # on two replays, with the default and with autotuned-style chunks
+    fj, runner, ctx = env
+    from paper_2301_10841_amd import autotune
+    golden = _golden_batch_counts()
+    n = len(golden)
+    assert n == 256
+    seed = datagen.seed_for(4, 0)
+    items, rows = [], []
+    for i in range(n):
+        dq, _ = datagen.batch_query(seed, i)
+        assert dq.kind == golden[i][0]
+        d = runner.DeviceQuery(ctx, dq)
+        plan = d.plan_binary(list(range(len(dq.atoms))), True)
+        items.append((d.q, plan, d.build(plan)))
+        rows.append(dq.relations[dq.atoms[0][0]].nrows)
+    want = [golden[i][1] for i in range(n)]
+    print("loaded", n, "queries,", sum(rows), "first-node rows", flush=True)
+    b = fj.Batch(ctx, items)
+    assert b.run() == want
+    assert b.run() == want
+    b.free()
+    # a tuner-shaped setting: small chunks for short queries, large for long
+    setting = {"block": 128, "chunk_by_bucket": {"0": 64, "1": 256, "2": 1024, "3": 4096, "4": 4096}}
+    b2 = fj.Batch(ctx, items, block=setting["block"], query_chunk=autotune.chunks_for(setting, rows))
+    assert b2.run() == want
+    b2.free()
+    for _, _, cs in items:
+        for c in cs:
+            c.free()

@@ -91,3 +91,30 @@ def test_batch_queries_at_full_size(env):
         want = cfj.run(dq, P.factor(P.binary2fj(dq, order)), materialize=False, counters=False)["count"]
         _say(i, dq.kind, [r.nrows for r in dq.relations], got)
         assert got == want, (i, dq.kind)
+
+
+def _golden_cycle4():
+    f = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rmat_cycle4_counts.txt")
+    out = {}
+    for ln in open(f):
+        if ln.strip() and not ln.startswith("#"):
+            s, e, n = ln.split()
+            out[int(s)] = (int(e), int(n))
+    return out
+
+
+@pytest.mark.parametrize("scale", [16, 18])
+def test_rmat_cycle4_reduced_scales(env, scale):
+    # the directed 4-cycle Q(w,x,y,z) :- E(w,x),E(x,y),E(y,z),E(z,w) with
+    # Generic Join's plan, counted without materializing (the last node's
+    # intersections are counted, not emitted), against trace(A^4)
+    # (tests/golden/make_rmat_cycle4.py)
+    fj, runner, ctx = env
+    n_edges, want = _golden_cycle4()[scale]
+    src, dst = datagen.rmat_edges(datagen.seed_for(3, 1), scale, n_edges)
+    assert src.size == n_edges
+    q4 = synth.four_cycle_query((src, dst))
+    nodes = [[(0, (0,)), (3, (0,))], [(0, (1,)), (1, (1,))], [(1, (2,)), (2, (2,))], [(2, (3,)), (3, (3,))]]
+    got = _count(runner, ctx, q4, nodes=nodes)
+    _say("4-cycles", scale, got, want)
+    assert got == want
