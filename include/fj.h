@@ -143,6 +143,11 @@ const char *fj_last_error(void);
 fj_status fj_timings(fj_ctx *ctx, double *ms, uint64_t *launches);
 fj_status fj_timings_reset(fj_ctx *ctx);
 
+/* Change the context's timing mode (the values of fj_options.timing) for
+   the calls that follow; timings already taken are kept.  FJ_ERR_ARG for a
+   null context or a mode other than 0, 1 or 2.  Host only. */
+fj_status fj_set_timing(fj_ctx *ctx, int32_t mode);
+
 /* -------------------------------------------------------------------- plans */
 
 #define FJ_FACTOR 1u   /* apply conservative factoring (Section 4.1) */

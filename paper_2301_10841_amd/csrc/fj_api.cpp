@@ -291,6 +291,7 @@ fj_status colt_allocate(fj_colt *t) {
         FJ_TRY(colt_alloc(t, &L.fq, n));
         L.nk = t->lev_nk[l];
         L.mode = key_mode(l, L.nk);
+        L.local = l > 0 && (L.mode == fj::KM_K64 || L.mode == fj::KM_REP);
         if (L.mode != fj::KM_ZERO) {
             // sized for the capacity; each (re)build uses the part its rows need
             const u64 cap = map_cap(n);
@@ -866,6 +867,13 @@ fj_status fj_timings_reset(fj_ctx *c) {
     if (!c) return fail(FJ_ERR_ARG, "null ctx");
     FJ_TRY(fj_timings(c, nullptr, nullptr));
     for (int i = 0; i < FJ_T_COUNT; i++) { c->ms[i] = 0; c->launches[i] = 0; }
+    return FJ_OK;
+}
+
+fj_status fj_set_timing(fj_ctx *c, int32_t mode) {
+    if (!c) return fail(FJ_ERR_ARG, "null ctx");
+    if (mode < 0 || mode > 2) return fail(FJ_ERR_ARG, "timing mode is 0, 1 or 2");
+    c->opt.timing = mode;
     return FJ_OK;
 }
 
@@ -1493,7 +1501,11 @@ fj_status exec_scan_node(Exec &x, int cover_sub, u64 T, uint32_t) {
     for (int j = 0; j < sl.nout; j++) sl.out_col[j] = cover_col(LN.in_var[j]);
     sl.out = x.F[1];
     sl.emit = x.tail_from == 1;
-    sl.materialize = sl.emit && (x.out != nullptr || x.res != nullptr);
+    // rows wanted from the first node: the kernel writes them itself
+    sl.direct = sl.emit && x.out && !x.res;
+    sl.ed = x.emit_d;
+    sl.cap = x.cap;
+    sl.materialize = sl.emit && !sl.direct && (x.out != nullptr || x.res != nullptr);
     if (sl.emit) {
         sl.ntail = (int)x.tails.size();
         for (int q = 0; q < sl.ntail; q++) {
@@ -1528,6 +1540,7 @@ fj_status exec_scan_node(Exec &x, int cover_sub, u64 T, uint32_t) {
             FJ_HIP(fj::launch_scan_probe(sl, c->stream));
         }
         if (x.stats) x.stats->tiles++;
+        if (sl.direct) continue;   // rows and count land on the device; no wait per tile
         if (sl.emit && x.out && !x.res && t0 + n >= T) {
             // the last tile's rows: emitted on the device without a wait for
             // its survivor count when the bindings are few (one workgroup);
@@ -1793,7 +1806,8 @@ static fj_status execute_impl(fj_ctx *c, const fj_query *q, const fj_plan *p, fj
             FJ_TRY(sync_status(c));
         }
     }
-    x.written = c->status_h->written;
+    // a direct emit reserves every row it counts: what passed cap was not written
+    x.written = std::min<u64>(c->status_h->written, x.cap);
     u64 total = c->status_h->count;
     for (int q = 0; q < fj::kCountParts; q++) total += c->status_h->count_part[q * fj::kPartStride];
     *count = total;

@@ -65,6 +65,8 @@ struct LevelDev {
     uint32_t npos;       // entries of every position-indexed array (>= 1)
     uint32_t nrows;      // rows of the relation's columns
     unsigned long long nslots;  // hash slots including the reserved one (0: no map)
+    int local;           // per-trie maps (levels below the root, KM_K64 / KM_REP): the trie at
+                         // position p with len[p] offsets owns slots [2p, 2p + 2 len[p])
 };
 
 struct SubDev {

@@ -42,8 +42,19 @@ __device__ __forceinline__ u64 mix64(u64 k) {
 
 struct Key {
     uint32_t h;                  // handle (start position) of the probed trie
+    uint32_t span;               // per-trie maps: the trie's offset count (its map has 2 span slots)
     int32_t v[FJ_MAX_COLS];
 };
+
+// Below the root each forced trie has a map of its own, as in the paper's
+// COLT, where every trie node is a hash map: the trie starting at position p
+// with n offsets (so at most n keys) owns the 2n slots from 2p, a disjoint
+// range since tries of one level own disjoint position ranges.  All lookups
+// of one trie, which the threads of one binding make together, touch only
+// its own few cache lines instead of lines spread over the level's table.
+// The start within the range takes the hash's top 32 bits times the range
+// size (a multiply-shift range reduction, no division).
+__device__ __forceinline__ u64 local_pick(u64 h, uint32_t n) { return ((h >> 32) * (u64)n) >> 32; }
 
 // Probing walks forward slot by slot from the start of a 32-byte bucket:
 // four KM_K32 slots (keys first, then values), or two 16-byte slots, so one
@@ -97,6 +108,22 @@ __device__ __forceinline__ u64 table_find(const LevelDev &L, const int32_t *cons
     } else if (L.mode == KM_K64) {
         const Slot64 *T = (const Slot64 *)L.table;
         u64 key = pack64(L, k);
+        if (L.local) {
+            // the trie's own buckets: span pairs of slots from 2h
+            if (k.span == 0) return ~0ull;
+            const u64 base = 2 * (u64)k.h, end = base + 2 * (u64)k.span;
+            u64 b = base + 2 * local_pick(mix64(key), k.span);
+            for (uint32_t n = 0; n < k.span; n++) {
+                const u64 c0 = T[b].key, c1 = T[b + 1].key;
+                if (c0 == key) return b;
+                if (c0 == kEmpty64) return ~0ull;
+                if (c1 == key) return b + 1;
+                if (c1 == kEmpty64) return ~0ull;
+                b += 2;
+                if (b == end) b = base;
+            }
+            return L.nslots;
+        }
         if (key == kEmpty64) return T[mask + 1].key ? mask + 1 : ~0ull;
         // a bucket's two slots in one 32-byte read, then the next bucket
         u64 b = bucket_start<Slot64>(mix64(key), mask);
@@ -110,13 +137,16 @@ __device__ __forceinline__ u64 table_find(const LevelDev &L, const int32_t *cons
         }
     } else {
         const SlotRep *T = (const SlotRep *)L.table;
-        u64 i = bucket_start<SlotRep>(rep_hash(k, L.nk), mask);
-        for (u64 n = 0; n <= mask; n++) {
-            u64 c = T[i].hr;
+        const u64 hh = rep_hash(k, L.nk);
+        const u64 base = L.local ? 2 * (u64)k.h : 0, m = L.local ? 2 * (u64)k.span : mask + 1;
+        if (m == 0) return ~0ull;
+        u64 i = L.local ? local_pick(hh, 2 * k.span) : bucket_start<SlotRep>(hh, mask);
+        for (u64 n = 0; n < m; n++) {
+            u64 c = T[base + i].hr;
             if (c == kEmpty64) return ~0ull;
             if ((uint32_t)c == k.h && (uint32_t)(c >> 32) < L.nrows &&
-                rep_equal(L, cols, (uint32_t)(c >> 32), k)) return i;
-            i = (i + 1) & mask;
+                rep_equal(L, cols, (uint32_t)(c >> 32), k)) return base + i;
+            if (++i == m) i = 0;
         }
     }
     return L.nslots;  // no empty slot: the map is corrupt (callers check the index)
@@ -174,11 +204,31 @@ __device__ __forceinline__ u64 table_insert(const LevelDev &L, const int32_t *co
     } else if (L.mode == KM_K64) {
         Slot64 *T = (Slot64 *)L.table;
         u64 key = pack64(L, k);
+        // as for KM_K32: read the bucket's two keys, swap the first empty one
+        if (L.local) {
+            if (k.span == 0) return L.nslots;
+            const u64 base = 2 * (u64)k.h, end = base + 2 * (u64)k.span;
+            u64 b = base + 2 * local_pick(mix64(key), k.span);
+            for (uint32_t n = 0; n < k.span; n++) {
+                const u64 ks[2] = {T[b].key, T[b + 1].key};
+#pragma unroll
+                for (int s = 0; s < 2; s++) {
+                    u64 c = ks[s];
+                    if (c == kEmpty64) {
+                        c = atomicCAS(&T[b + s].key, kEmpty64, key);
+                        if (c == kEmpty64) { claimed = true; return b + s; }
+                    }
+                    if (c == key) return b + s;
+                }
+                b += 2;
+                if (b == end) b = base;
+            }
+            return L.nslots;
+        }
         if (key == kEmpty64) {
             claimed = atomicCAS(&T[mask + 1].key, 0ull, 1ull) == 0ull;
             return mask + 1;
         }
-        // as for KM_K32: read the bucket's two keys, swap the first empty one
         u64 b = bucket_start<Slot64>(mix64(key), mask);
         for (u64 n = 0; n <= mask; n += 2) {
             const u64 ks[2] = {T[b].key, T[b + 1].key};
@@ -196,17 +246,20 @@ __device__ __forceinline__ u64 table_insert(const LevelDev &L, const int32_t *co
     } else {
         SlotRep *T = (SlotRep *)L.table;
         u64 mine = ((u64)row << 32) | k.h;
-        u64 i = bucket_start<SlotRep>(rep_hash(k, L.nk), mask);
-        for (u64 n = 0; n <= mask; n++) {
-            u64 c = T[i].hr;         // may be stale-empty; the CAS settles it
+        const u64 hh = rep_hash(k, L.nk);
+        const u64 base = L.local ? 2 * (u64)k.h : 0, m = L.local ? 2 * (u64)k.span : mask + 1;
+        if (m == 0) return L.nslots;
+        u64 i = L.local ? local_pick(hh, 2 * k.span) : bucket_start<SlotRep>(hh, mask);
+        for (u64 n = 0; n < m; n++) {
+            u64 c = T[base + i].hr;   // may be stale-empty; the CAS settles it
             if (c == kEmpty64) {
-                u64 old = atomicCAS(&T[i].hr, kEmpty64, mine);
-                if (old == kEmpty64) { claimed = true; return i; }
+                u64 old = atomicCAS(&T[base + i].hr, kEmpty64, mine);
+                if (old == kEmpty64) { claimed = true; return base + i; }
                 c = old;
             }
             if ((uint32_t)c == k.h && (uint32_t)(c >> 32) < L.nrows &&
-                rep_equal(L, cols, (uint32_t)(c >> 32), k)) return i;
-            i = (i + 1) & mask;
+                rep_equal(L, cols, (uint32_t)(c >> 32), k)) return base + i;
+            if (++i == m) i = 0;
         }
     }
     return L.nslots;  // the map is full: callers check the index
@@ -563,9 +616,12 @@ __device__ __forceinline__ void force_insert_item(const ForceArgs &a, uint32_t w
     }
     Key k;
     k.h = p;
+    k.span = 0;
     k.v[0] = k.v[1] = 0;
-    if (todo)
+    if (todo) {
         for (int c = 0; c < a.L.nk; c++) k.v[c] = a.cols[a.L.kcol[c]][row];
+        if (a.L.local) k.span = a.L.len[p];
+    }
     // Up to two rounds: the lanes holding the same key (same map, handle and
     // key of at most two columns) as the wave's first remaining lane insert
     // it once and add their number at once, which keeps a heavy key under
@@ -948,11 +1004,24 @@ __device__ __forceinline__ uint32_t upper_entry_lds(const u64 *sst, uint32_t lo,
 
 constexpr uint32_t kProbeStartsLds = 1024;   // scanned cover counts a block caches for its search
 
+#ifndef FJ_PROBE_WAVES
+#define FJ_PROBE_WAVES 1
+#endif
 template <int MV, int MA>
-__global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
+__global__ void __launch_bounds__(256, FJ_PROBE_WAVES) k_probe(ProbeArgs a) {
     __shared__ u64 red[17];
     __shared__ u64 sst[kProbeStartsLds];
+    // The node's subatom descriptors, copied to LDS once per workgroup: a
+    // tuple's cover is its binding's choice, so threads index them by a
+    // per-lane number, and from LDS those reads cost no memory round trips.
+    __shared__ SubDev ssub[FJ_MAX_ATOMS];
     const NodeDev &nd = *a.nd;
+    {
+        const uint32_t words = (uint32_t)(min(nd.nsub, FJ_MAX_ATOMS) * sizeof(SubDev) / sizeof(uint32_t));
+        const uint32_t *src = (const uint32_t *)nd.sub;
+        uint32_t *dst = (uint32_t *)ssub;
+        for (uint32_t k = threadIdx.x; k < words; k += blockDim.x) dst[k] = src[k];
+    }
     StatusDev *status = a.status;
     const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
     bool survive = false, defer = false;
@@ -973,11 +1042,10 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
         hi = a.chunk_e[blockIdx.x + 1] + 1;
         range_ok = CK(lo < hi && hi <= a.E);
         in_lds = range_ok && hi - lo + 1 <= kProbeStartsLds;   // block-uniform
-        if (in_lds) {
+        if (in_lds)
             for (uint32_t k = threadIdx.x; k <= hi - lo; k += blockDim.x) sst[k] = a.starts[lo + k];
-            __syncthreads();
-        }
     }
+    __syncthreads();
     bool ok = idx < a.n && range_ok;
     if (ok) {
         if (a.din) { t = a.din[idx]; resume = a.din_j[idx]; } else { t = idx; }
@@ -997,7 +1065,7 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
         // bind the cover tuple
         const uint8_t cb = a.cov[e];
         const int ci = cb & 0x7F;
-        const SubDev &S = nd.sub[ci];
+        const SubDev &S = ssub[ci & (FJ_MAX_ATOMS - 1)];
         const uint32_t p = S.level == 0 ? 0u : h[(S.atom) & (MA - 1)];
         if (cb & 0x80) {
             ok = CK(p + i < S.L.npos);
@@ -1033,7 +1101,7 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
         survive = ok;
         for (int j = 0; j < nd.nsub && survive; j++) {
             if (j == ci) continue;
-            const SubDev &P = nd.sub[j];
+            const SubDev &P = ssub[j & (FJ_MAX_ATOMS - 1)];
             const uint32_t ph = P.level == 0 ? 0u : h[(P.atom) & (MA - 1)];
             if (!CK(ph < P.L.npos)) { survive = false; break; }
             const uint32_t st = P.L.st[ph];
@@ -1058,6 +1126,7 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
             } else {
                 Key k;
                 k.h = ph;
+                k.span = P.L.local ? P.L.len[ph] : 0u;
                 for (int c = 0; c < P.nk; c++) k.v[c] = v[(P.kslot[c]) & (MV - 1)];
                 const u64 slot = table_find(P.L, P.cols, k);
                 if (slot == ~0ull) { survive = false; break; }
@@ -1109,6 +1178,25 @@ __global__ void __launch_bounds__(256) k_probe(ProbeArgs a) {
         if (O.mult) O.mult[pos] = mult;
     }
 }
+
+// ------------------------------------------------------------------- emit
+// Materialization: every final binding stands for mult * prod(tail lengths)
+// result tuples, whose values come from the binding and from each tail
+// trie's rows (mixed radix over the tails, the last one fastest).
+
+struct EmitDev {
+    FrontierDev F;
+    int nin;
+    int in_var[FJ_MAX_VARS];
+    int nin_h;
+    int in_h_atom[FJ_MAX_ATOMS];
+    int ntail;
+    TailDev tail[FJ_MAX_NODES];
+    int nhead;
+    int head_src[FJ_MAX_VARS];    // >= 0: frontier value column; < 0: -(tail * FJ_MAX_COLS + c) - 1
+    int32_t *out;
+    u64 out_rows;                 // capacity of out in rows
+};
 
 // ------------------------------------------------------------ scan probe
 // Specialised first node: the cover is a base table (or its selection)
@@ -1164,6 +1252,13 @@ struct ScanArgs {
     int count_stats;
     int node;
     u64 surv_base;            // survivor counter before this launch
+    // direct emit (the first node is the last probing node and rows are
+    // wanted): the flush writes result rows itself, placed by one atomic
+    // reservation per wave on status->written (which may pass cap: the host
+    // clamps it); no frontier, no emit launch
+    int direct;
+    const EmitDev *ed;        // head mapping, tails and output of the execution
+    u64 cap;                  // output capacity in rows
 };
 
 // One row's probe of a root map in two steps, so that several rows' loads
@@ -1307,6 +1402,81 @@ struct ScanLds {
     uint32_t *cnt;      // cnt[0]: batch entries; cnt[j]: entries alive after round j
 };
 
+// Direct emit of one chunk of final bindings, wave by wave (the thread's
+// entry is entry i of the flush, with e result rows, 0 for none; fin lists
+// the flush's batch entries, or null when entry i is batch entry i): a
+// scan of the wave's row counts in registers, one reservation of the
+// wave's rows in the output, then the wave writes them together, each row
+// finding its lane by a search over the lanes' starts and its tail rows by
+// mixed radix.  No LDS, so the kernel's occupancy is unchanged.
+__device__ __forceinline__ void scan_emit_wave(const ScanArgs &a, const uint32_t *bh, const uint32_t *brow,
+                                            const uint16_t *fin, uint32_t i, uint32_t nf, u64 e) {
+    StatusDev *status = a.status;
+    const EmitDev &d = *a.ed;
+    const int lane = __lane_id();
+    u64 x = e;
+    for (int o = 1; o < 64; o <<= 1) {
+        const u64 y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    const u64 wtot = __shfl(x, 63, 64);
+    const u64 ex = x - e;
+    if (wtot == 0) return;   // wave-uniform
+    u64 base = 0;
+    if (lane == 0) base = atomicAdd(&status->written, wtot);
+    base = __shfl(base, 0, 64);
+    const u64 room = base < a.cap ? a.cap - base : 0;
+    const u64 nw = wtot < room ? wtot : room;   // rows past the output are counted, not written
+    const uint32_t i_lane0 = i - (uint32_t)lane;
+    for (u64 r0 = 0; r0 < nw; r0 += 64) {
+        const u64 r = r0 + lane;
+        // the lane t whose rows hold r: the largest t with ex_t <= r (every
+        // lane takes part in the search's shuffles)
+        int lo = 0, hi = 64;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (__shfl(ex, mid, 64) <= r) lo = mid; else hi = mid;
+        }
+        const u64 ex_t = __shfl(ex, lo, 64);
+        if (r >= nw) continue;
+        const uint32_t t = (uint32_t)lo;
+        if (!CK(i_lane0 + t < nf)) continue;
+        const uint32_t eb = fin ? fin[i_lane0 + t] : i_lane0 + t;
+        u64 idx = r - ex_t;
+        uint32_t rows[FJ_MAX_NODES];
+        bool ok = true;
+        for (int q = d.ntail - 1; q >= 0 && ok; q--) {
+            const TailDev &T = d.tail[q];
+            uint32_t p = 0, len = a.tail_root_len[q];
+            if (a.tail_lk[q] >= 0) {
+                p = bh[a.tail_lk[q] * kBatch + eb];
+                ok = CK(p < T.L.npos);
+                len = ok ? T.L.len[p] : 0u;
+            }
+            ok = ok && CK(len > 0);
+            if (!ok) break;
+            const uint32_t pos = p + (uint32_t)(idx % len);
+            idx /= len;
+            ok = CK(pos < T.L.npos || (T.level == 0 && pos < T.root_len));
+            rows[q] = ok ? (T.L.offs ? T.L.offs[pos] : pos) : 0u;
+            ok = ok && CK(rows[q] < T.L.nrows);
+        }
+        if (!ok) continue;
+        const uint32_t crow = brow[eb];
+        int32_t *dst = d.out + (base + r) * (u64)d.nhead;
+        for (int j = 0; j < d.nhead; j++) {
+            const int src = d.head_src[j];
+            if (src >= 0) {
+                dst[j] = a.cols[a.out_col[src]][crow];
+            } else {
+                const int z = -src - 1;
+                const TailDev &T = d.tail[z / FJ_MAX_COLS];
+                dst[j] = T.cols[T.kcol[z % FJ_MAX_COLS]][rows[z / FJ_MAX_COLS]];
+            }
+        }
+    }
+}
+
 // Round 0, second half: scan the issued probes of the thread's rows; rows
 // that hit join the batch.
 template <int MODE, bool STATS>
@@ -1409,47 +1579,53 @@ __device__ __forceinline__ void scan_flush(const ScanArgs &a, const ScanLds &S, 
     }
     if (nf > 0) {
         const uint16_t *fin = last == 0 ? nullptr : S.lists + (last & 1) * kBatch;
-        const bool write = !a.emit || a.materialize;
+        const bool write = (!a.emit || a.materialize) && !a.direct;
         if (write) {
             if (threadIdx.x == 0) red[16] = atomicAdd(&a.status->survivors, (u64)nf);
             __syncthreads();
         }
         const u64 base = write ? red[16] - a.surv_base : 0;
-        for (uint32_t i = threadIdx.x; i < nf; i += 256) {
-            const uint32_t b = fin ? fin[i] : i;
+        // chunks of 256 entries, one per thread (all threads take part in
+        // every chunk: the direct emit scans each chunk)
+        for (uint32_t i0 = 0; i0 < nf; i0 += 256) {
+            const uint32_t i = i0 + threadIdx.x;
+            const bool live = i < nf;
+            const uint32_t b = live ? (fin ? fin[i] : i) : 0u;
             // slots of KM_K32 maps become their values (the child handles)
-            bool ok = true;
-            for (int j = 0; j < a.nl; j++) {
+            bool ok = live;
+            for (int j = 0; j < a.nl && live; j++) {
                 const ScanLookup &L = a.lk[j];
                 if (L.mode != KM_K32) continue;
                 const uint32_t v = ((const uint32_t *)L.table)[k32_key_word(S.bh[j * kBatch + b]) + 4];
                 ok = ok && CK(v < L.cnpos);
                 S.bh[j * kBatch + b] = v;
             }
-            if (!ok) continue;
-            u64 m = 1;
-            for (int j = 0; j < a.nl; j++)
-                if (a.lk[j].child_leaf) m *= a.lk[j].clen[S.bh[j * kBatch + b]];
-            if (a.emit) {
-                u64 e = m;
-                for (int q = 0; q < a.ntail; q++) {
-                    if (a.tail_lk[q] < 0) { e *= a.tail_root_len[q]; continue; }
-                    const uint32_t th = S.bh[a.tail_lk[q] * kBatch + b];
-                    if (!CK(th < a.tail_npos[q])) { e = 0; break; }
-                    e *= a.tail_len[q][th];
-                }
-                tot += e;
-            }
-            if (write) {
-                const u64 pos = base + i;
-                const FrontierDev &O = a.out;
-                if (!CK(pos < O.cap)) continue;
-                const uint32_t row = S.brow[b];
-                for (int j = 0; j < a.nout; j++) O.vals[(u64)j * O.cap + pos] = a.cols[a.out_col[j]][row];
+            u64 e = 0;
+            if (ok) {
+                u64 m = 1;
                 for (int j = 0; j < a.nl; j++)
-                    if (a.lk[j].hcol >= 0) O.hdl[(u64)a.lk[j].hcol * O.cap + pos] = S.bh[j * kBatch + b];
-                if (O.mult) O.mult[pos] = m;
+                    if (a.lk[j].child_leaf) m *= a.lk[j].clen[S.bh[j * kBatch + b]];
+                if (a.emit) {
+                    e = m;
+                    for (int q = 0; q < a.ntail; q++) {
+                        if (a.tail_lk[q] < 0) { e *= a.tail_root_len[q]; continue; }
+                        const uint32_t th = S.bh[a.tail_lk[q] * kBatch + b];
+                        if (!CK(th < a.tail_npos[q])) { e = 0; break; }
+                        e *= a.tail_len[q][th];
+                    }
+                    tot += e;
+                }
+                const u64 pos = base + i;
+                if (write && CK(pos < a.out.cap)) {
+                    const FrontierDev &O = a.out;
+                    const uint32_t row = S.brow[b];
+                    for (int j = 0; j < a.nout; j++) O.vals[(u64)j * O.cap + pos] = a.cols[a.out_col[j]][row];
+                    for (int j = 0; j < a.nl; j++)
+                        if (a.lk[j].hcol >= 0) O.hdl[(u64)a.lk[j].hcol * O.cap + pos] = S.bh[j * kBatch + b];
+                    if (O.mult) O.mult[pos] = m;
+                }
             }
+            if (a.direct) scan_emit_wave(a, S.bh, S.brow, fin, i, nf, e);
         }
     }
     __syncthreads();   // every entry of the batch is read: empty it
@@ -1573,23 +1749,10 @@ __global__ void __launch_bounds__(256, FJ_SCAN_WAVES) k_scan_probe(ScanArgs a) {
     if (a.emit) block_add_count(tot, status, red);
 }
 
-// ------------------------------------------------------------------- emit
-// Materialization: every final binding stands for mult * prod(tail lengths)
-// result tuples; rows are laid out by a scan of those counts.
+// ------------------------------------------------------- emit (launches)
+// Rows are laid out by a scan of the bindings' row counts.
 
-struct EmitDev {
-    FrontierDev F;
-    int nin;
-    int in_var[FJ_MAX_VARS];
-    int nin_h;
-    int in_h_atom[FJ_MAX_ATOMS];
-    int ntail;
-    TailDev tail[FJ_MAX_NODES];
-    int nhead;
-    int head_src[FJ_MAX_VARS];    // >= 0: frontier value column; < 0: -(tail * FJ_MAX_COLS + c) - 1
-    int32_t *out;
-    u64 out_rows;                 // capacity of out in rows
-};
+
 
 __device__ __forceinline__ uint32_t emit_handle(const EmitDev &d, int atom, uint32_t e) {
     for (int j = 0; j < d.nin_h; j++)
@@ -1860,9 +2023,11 @@ hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, u64 n, uint32_t *b
     return scan_impl<uint32_t>(in, out, n, bsum, total, s);
 }
 
+u64 filter_lt_blocks(u64 n) { return std::max<u64>((n + kFilterBlock - 1) / kFilterBlock, 1); }
+
 hipError_t launch_filter_lt(const int32_t *col, u64 n, int32_t bound, uint32_t *out, uint32_t *bsum,
                             uint32_t *total, hipStream_t s) {
-    const u64 nb = std::max<u64>((n + kFilterBlock - 1) / kFilterBlock, 1);
+    const u64 nb = filter_lt_blocks(n);
     const int vec = ((uintptr_t)col % 16) == 0;
     hipLaunchKernelGGL(k_filter_count, dim3((unsigned)nb), dim3(256), 0, s, col, n, bound, vec, bsum);
     hipLaunchKernelGGL(k_scan_blocks<uint32_t>, dim3(1), dim3(kScanThreads), 0, s, bsum, nb, total,
@@ -2071,6 +2236,8 @@ hipError_t launch_scan_probe(const ScanLaunch &l, hipStream_t s) {
         a.tail_npos[q] = l.tail_npos[q]; a.tail_root_len[q] = l.tail_root_len[q];
     }
     a.status = l.status; a.count_stats = l.count_stats; a.node = l.node; a.surv_base = l.surv_base;
+    if (l.direct && (!l.ed || !l.emit || l.materialize)) return hipErrorInvalidValue;
+    a.direct = l.direct; a.ed = (const EmitDev *)l.ed; a.cap = l.cap;
     // persistent workgroups: as many as are resident at once, at most one
     // per tile
     constexpr int kMaxDevices = 64;

@@ -68,6 +68,9 @@ struct ScanLaunch {
     int count_stats;
     int node;
     unsigned long long surv_base;
+    int direct;                // the kernel writes result rows itself (the first node emits)
+    const void *ed;            // the execution's device emit descriptor (direct)
+    unsigned long long cap;    // output capacity in rows (direct)
 };
 
 hipError_t launch_scan_probe(const ScanLaunch &l, hipStream_t s);
@@ -84,6 +87,8 @@ hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, unsigned long long
                            uint32_t *total, hipStream_t s);
 hipError_t launch_filter_lt(const int32_t *col, unsigned long long n, int32_t bound, uint32_t *out,
                             uint32_t *bsum, uint32_t *total, hipStream_t s);
+// Block sums (32-bit words of bsum) launch_filter_lt uses for n rows.
+unsigned long long filter_lt_blocks(unsigned long long n);
 // Selections of n columns (each with its own bound, output and block-sum
 // scratch of rows / 1024 + 1 words) in three launches; totals[i] receives
 // selection i's row count.

@@ -151,6 +151,7 @@ def lib():
         L.fj_ctx_destroy.restype = None
         L.fj_timings.argtypes = [vp, vp, vp]
         L.fj_timings_reset.argtypes = [vp]
+        L.fj_set_timing.argtypes = [vp, C.c_int32]
         L.fj_plan_from_binary.argtypes = [P(QueryS), vp, C.c_int32, C.c_uint32, P(vp)]
         L.fj_plan_from_nodes.argtypes = [P(QueryS), C.c_int32, vp, vp, vp, vp, P(vp)]
         L.fj_plan_get.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int32]
@@ -320,6 +321,10 @@ class Context:
 
     def timings_reset(self):
         _check(lib().fj_timings_reset(self.h))
+
+    def set_timing(self, mode):
+        """True / 1: every kernel class; 2: the node-0 probe only; 0: off."""
+        _check(lib().fj_set_timing(self.h, int(mode)))
 
     # ---- selection
     def filter_lt(self, col, bound: int, out_sel=None):

@@ -394,3 +394,22 @@ def test_last_tile_emit_paths(fjm, ctx, n_left, n_keys, fanout):
     w = Counter(map(tuple, want["rows"].tolist()))
     g = Counter(map(tuple, cut["rows"].tolist()))
     assert all(g[k] <= w[k] for k in g)
+
+
+def test_star_rows_written_by_the_probe_kernel(fjm, ctx):
+    # the star's first node is its last probing node: the probe kernel writes
+    # the result rows itself (four tails, one row per binding); a cap below
+    # the count keeps the count exact and writes a sub-multiset of the rows
+    dq = datagen.star_schema(datagen.seed_for(2, 5), n_fact=400_000, n_dim=20_000, attr_lt=40)
+    want = oracle_run(dq, oracle_plan_binary(dq, [0, 1, 2, 3, 4], True), counters=False)
+    assert want["count"] > 1000
+    got = gpu_run(fjm, ctx, dq, [0, 1, 2, 3, 4], True)
+    assert got["count"] == want["count"]
+    assert_same_rows(got["rows"], want["rows"])
+    cap = want["count"] // 3
+    cut = gpu_run(fjm, ctx, dq, [0, 1, 2, 3, 4], True, cap=cap)
+    assert cut["count"] == want["count"] and cut["written"] == cap
+    from collections import Counter
+    w = Counter(map(tuple, want["rows"].tolist()))
+    g = Counter(map(tuple, cut["rows"].tolist()))
+    assert all(g[k] <= w[k] for k in g)
