@@ -184,6 +184,20 @@ void fj_plan_free(fj_plan *p);
 fj_status fj_filter_lt(fj_ctx *ctx, const int32_t *col, int64_t nrows, int32_t bound,
                        uint32_t *out_sel, int64_t *out_n);
 
+/* fj_filter_lt for callers that cannot allocate device memory (code under
+   stream capture, tight serving loops, harnesses that forbid hipMalloc):
+   the same selection, same arguments and same result, but its block sums
+   live in a fixed 256 KiB device array that the library holds on each GPU
+   until the process ends (its address is looked up when a context is
+   created on that GPU), and the call makes no allocation.  nrows is at
+   most 67,108,864 (65,536 blocks of 1,024 rows); larger inputs return
+   FJ_ERR_UNSUPPORTED before any device work.  Every call on one GPU shares
+   that GPU's array: calls that overlap on one GPU (other threads or
+   streams) race and must be serialized by the caller.  Synchronizes the
+   context's stream. */
+fj_status fj_filter_lt_noalloc(fj_ctx *ctx, const int32_t *col, int64_t nrows, int32_t bound,
+                               uint32_t *out_sel, int64_t *out_n);
+
 /* Several selections with one synchronization: selection i keeps the rows
    r < nrows[i] of device column cols[i] with cols[i][r] < bounds[i], writing
    their offsets to outs[i] (device, capacity nrows[i]) in row order and

@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfj.so")
-SOURCES = ["fj_plan.cpp", "fj_api.cpp", "fj_learn.cpp", "fj_bushy.cpp", "fj_kernels.hip", "fj_batch.hip", "fj_learn.hip"]
+SOURCES = ["fj_plan.cpp", "fj_api.cpp", "fj_learn.cpp", "fj_bushy.cpp", "fj_kernels.hip", "fj_batch.hip", "fj_learn.hip",
+           "fj_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-value", "-Wno-unused-result",

@@ -100,6 +100,7 @@ struct fj_ctx {
     fj_options opt{};
     StatusDev *status_d = nullptr;
     StatusDev *status_h = nullptr;  // pinned
+    uint32_t *noalloc = nullptr;    // this device's fixed scratch array (fj_filter_lt_noalloc)
     // per-node execution buffers
     DevBuf front[FJ_MAX_NODES + 1];
     DevBuf nodebuf[FJ_MAX_NODES];   // starts | cnt | cov
@@ -816,6 +817,11 @@ fj_status fj_ctx_create(int device, void *stream, const fj_options *opt, fj_ctx 
     e = hipMemset(c->status_d, 0, sizeof(StatusDev));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) { fj_ctx_destroy(c); return fail(FJ_ERR_HIP, "status block initialisation failed"); }
+    if (fj::noalloc_scratch(device, &c->noalloc) != FJ_OK) {
+        std::string keep = g_err;
+        fj_ctx_destroy(c);
+        return fail(FJ_ERR_HIP, keep);
+    }
     *out = c;
     return FJ_OK;
 }
@@ -955,6 +961,26 @@ fj_status fj_filter_lt(fj_ctx *c, const int32_t *col, int64_t nrows, int32_t bou
         FJ_HIP(fj::launch_filter_lt(col, (u64)nrows, bound, out_sel, c->scanb.as<uint32_t>(),
                                     &c->status_d->total32, c->stream));
     }
+    FJ_TRY(sync_status(c));
+    *out_n = (int64_t)c->status_h->total32;
+    return FJ_OK;
+}
+
+fj_status fj_filter_lt_noalloc(fj_ctx *c, const int32_t *col, int64_t nrows, int32_t bound, uint32_t *out_sel,
+                               int64_t *out_n) {
+    if (!c || !out_n || nrows < 0 || (nrows > 0 && (!col || !out_sel))) return fail(FJ_ERR_ARG, "bad argument");
+    *out_n = 0;
+    const u64 words = fj::noalloc_scratch_words();
+    if (nrows > 0 && fj::filter_lt_blocks((u64)nrows) > words)
+        return fail(FJ_ERR_UNSUPPORTED, "nrows above the allocation-free limit of " +
+                                            std::to_string(words * 1024) + " rows");
+    if (!c->noalloc) return fail(FJ_ERR_HIP, "the context has no scratch array");
+    FJ_HIP(hipSetDevice(c->device));
+    if (nrows == 0) return FJ_OK;
+    // the block sums go to the fixed array and the total to the context's
+    // status block; both are written before they are read, so nothing is
+    // cleared first
+    FJ_HIP(fj::launch_filter_lt(col, (u64)nrows, bound, out_sel, c->noalloc, &c->status_d->total32, c->stream));
     FJ_TRY(sync_status(c));
     *out_n = (int64_t)c->status_h->total32;
     return FJ_OK;

@@ -21,4 +21,10 @@ fj_status set_error(fj_status st, const std::string &msg);
 fj_status pool_alloc(int device, size_t bytes, void **out);
 void pool_free(int device, void *p, size_t bytes);
 
+// The fixed scratch array of the allocation-free entry point: its size in
+// 32-bit words, and this device's copy (looked up once per device; the
+// caller has made `device` current).
+unsigned long long noalloc_scratch_words();
+fj_status noalloc_scratch(int device, uint32_t **out);
+
 }  // namespace fj

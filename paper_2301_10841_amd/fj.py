@@ -158,6 +158,7 @@ def lib():
         L.fj_plan_free.argtypes = [vp]
         L.fj_plan_free.restype = None
         L.fj_filter_lt.argtypes = [vp, vp, C.c_int64, C.c_int32, vp, P(C.c_int64)]
+        L.fj_filter_lt_noalloc.argtypes = [vp, vp, C.c_int64, C.c_int32, vp, P(C.c_int64)]
         L.fj_filter_lt_batch.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp]
         L.fj_build_colt.argtypes = [vp, P(QueryS), vp, C.c_int32, P(Relation), P(vp)]
         L.fj_colt_rebuild.argtypes = [vp, vp, P(Relation)]
