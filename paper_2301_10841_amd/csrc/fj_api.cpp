@@ -112,6 +112,7 @@ struct fj_ctx {
     DevBuf chunkb;                  // per-block binding bounds of a probe launch
     DevBuf sketch;                  // column sketch table and results
     struct ColtGroup *group = nullptr;  // fj_colt_rebuild_many's descriptors and scratch
+    struct ColtGroup *group1 = nullptr; // single rebuilds of roots built range by range
     unsigned long long *sketch_h = nullptr;  // pinned sketch results
     void *desc_h = nullptr;         // pinned staging for descriptors
     size_t desc_h_bytes = 0;
@@ -208,6 +209,7 @@ struct fj_colt {
     uint32_t cap_rows = 0;   // rows the buffers were sized for
     bool root_built = false;
     bool root_lazy = false;  // unbuilt root that a probe may force (its map is allocated)
+    bool root_part = false;  // root map (KM_K32) built range by range by the grouped path
     int lev_nk[fj::kMaxLevels] = {0};
     int lev_var[fj::kMaxLevels][FJ_MAX_COLS] = {{0}};
     LevelDev lev[fj::kMaxLevels + 1];
@@ -410,7 +412,8 @@ static fj_status colt_fill_list(fj_colt *t, u64 rows) {
     t->fill_words = 0;
     for (int l = 0; l < t->nlev; l++) {
         LevelDev &L = t->lev[l];
-        add(t->fill_h, t->fill_words, L.st, l == 0 ? 1 : n, {0u});
+        // (the root's state word is set with the root handle, not filled)
+        if (l > 0) add(t->fill_h, t->fill_words, L.st, n, {0u});
         fj::FillList &fl = l == 0 ? t->fill_h : t->fill_lev_h[l];
         u64 &words = l == 0 ? t->fill_words : t->fill_lev_words[l];
         if (l > 0) {
@@ -419,7 +422,7 @@ static fj_status colt_fill_list(fj_colt *t, u64 rows) {
         }
         if (!L.cnt) continue;  // directly iterated base table
         add(fl, words, L.cnt, n, {0u});
-        if (!L.table) continue;
+        if (!L.table || (l == 0 && t->root_part)) continue;
         const u64 ns = t->table_slots[l];
         uint32_t *T = (uint32_t *)L.table;
         if (L.mode == fj::KM_K32) {
@@ -444,15 +447,24 @@ static fj_status colt_fill_list(fj_colt *t, u64 rows) {
 // copies are marked stale when they change.
 static fj_status colt_size(fj_colt *t) {
     const u64 rows = std::max<uint32_t>(t->nroot, 1);
-    if (rows == t->sized_rows) return FJ_OK;   // maps and fill lists are as the last sizing left them
+    const bool part_was = t->root_part;
     for (int l = 0; l < t->nlev; l++) {
         LevelDev &L = t->lev[l];
-        if (!L.table) continue;
+        if (!L.table || rows == t->sized_rows) continue;
         const u64 cap = std::min(map_cap(rows), t->table_cap[l]);
         L.mask = cap - 1;
         L.nslots = cap + 1;
         t->table_slots[l] = cap + 1;
     }
+    // a built KM_K32 root of at most kMaxParts ranges is built range by
+    // range, which writes its whole table: the fill lists leave it out
+    {
+        const LevelDev &R = t->lev[0];
+        const u64 cap = R.mask + 1, psz = std::min<u64>(cap, fj::kK32Part);
+        t->root_part = t->root_built && t->nroot > 0 && t->nlev >= 1 && R.table && R.mode == fj::KM_K32 &&
+                       cap / psz <= fj::kMaxParts;
+    }
+    if (rows == t->sized_rows && part_was == t->root_part) return FJ_OK;   // as the last sizing left them
     const fj::FillList old = t->fill_h;
     std::vector<fj::FillList> old_lev(t->fill_lev_h, t->fill_lev_h + fj::kMaxLevels);
     FJ_TRY(colt_fill_list(t, rows));
@@ -515,9 +527,12 @@ static fj_status colt_force_all(fj_ctx *c, fj_colt *t) {
     return FJ_OK;
 }
 
+static fj_status colt_rebuild_group(fj_ctx *c, fj_colt *t);
+
 static fj_status colt_reset(fj_ctx *c, fj_colt *t) {
     FJ_TRY(colt_size(t));
     FJ_TRY(colt_fill_upload(c, t));
+    if (t->root_part) return colt_rebuild_group(c, t);
     for (int l = 0; l <= t->nlev; l++) t->lev[l].nrows = (uint32_t)t->nrows;
     for (int l = 0; l < t->nlev; l++) t->lev_ready[l] = false;
     LevelDev &R = t->lev[0];
@@ -553,10 +568,16 @@ struct ColtGroup {
     int n = 0;
     u64 wtot = 0;
     uint32_t nfill = 0;
-    DevBuf meta;   // descs | wpre | roots | pre | fill blocks
-    DevBuf work;   // wslot | cntv | ex | block sums | total
-    size_t o_wpre = 0, o_roots = 0, o_pre = 0, o_fill = 0, meta_bytes = 0;
+    // members whose KM_K32 root maps are built range by range
+    int npm = 0;
+    uint32_t nparts = 0, nblocks = 0;
+    u64 wp = 0;
+    DevBuf meta;   // descs | wpre | roots | pre | part members | fill blocks
+    DevBuf work;   // wslot | cntv | ex | block sums | total | range arrays
+    size_t o_wpre = 0, o_roots = 0, o_pre = 0, o_pmem = 0, o_fill = 0, meta_bytes = 0;
     size_t w_cntv = 0, w_ex = 0, w_bsum = 0, w_total = 0;
+    size_t w_ipart = 0, w_irow = 0, w_ikey = 0, w_ikv = 0, w_pcnt = 0, w_pcur = 0, w_pstart = 0;
+    size_t w_prow = 0, w_pkey = 0, w_pkv = 0, w_scnt = 0, w_pdist = 0, w_rstart = 0, w_pbsum = 0;
     std::vector<char> stage, last;   // host image of meta, and the last one uploaded
     std::vector<char> last_key;      // the inputs that image was made from
     char *stage_h = nullptr;         // pinned copy source
@@ -610,6 +631,7 @@ fj_status group_prepare(fj_ctx *c, ColtGroup &G, fj_colt *const *colts, int n, u
         key_put(key, t);
         key_put(key, t->nroot);
         key_put(key, t->root_built);
+        key_put(key, t->root_part);
         key_put(key, t->nrows);
         key_put(key, t->sel);
         key_put(key, t->cols);
@@ -620,14 +642,77 @@ fj_status group_prepare(fj_ctx *c, ColtGroup &G, fj_colt *const *colts, int n, u
     if (!G.last.empty() && key == G.last_key && G.n == n) return FJ_OK;
     G.last_key.clear();
     G.n = n;
+    // the general path takes the built roots not built range by range
     std::vector<u64> wpre(n + 1, 0);
+    std::vector<fj::PartMember> pm;
+    u64 wp = 0, nslots = 0;
+    uint32_t nparts = 0, nblocks = 0;
     for (int k = 0; k < n; k++) {
         const fj_colt *t = colts[k];
-        wpre[k + 1] = wpre[k] + ((t->root_built && t->nroot > 0) ? t->nroot : 0);
+        wpre[k + 1] = wpre[k] + ((t->root_built && t->nroot > 0 && !t->root_part) ? t->nroot : 0);
+        if (!t->root_part) continue;
+        const u64 cap = t->lev[0].mask + 1, psz = std::min<u64>(cap, fj::kK32Part);
+        fj::PartMember m;
+        m.desc = k;
+        m.np = (uint32_t)(cap / psz);
+        m.plog = 0;
+        while ((1ull << m.plog) < psz) m.plog++;
+        m.part_base = nparts;
+        m.block_base = nblocks;
+        m.item_base = (uint32_t)wp;
+        m.W = t->nroot;
+        m.slot_base = nslots;
+        nslots += (u64)m.np << m.plog;
+        if (wp + t->nroot > 0xFFFFFFFFull) return fail(FJ_ERR_UNSUPPORTED, "grouped roots of 2^32 rows or more");
+        nparts += m.np;
+        nblocks += (uint32_t)((t->nroot + fj::kPartItems - 1) / fj::kPartItems);
+        wp += t->nroot;
+        pm.push_back(m);
     }
     G.wtot = wpre[n];
+    G.npm = (int)pm.size();
+    G.nparts = nparts;
+    G.nblocks = nblocks;
+    G.wp = wp;
     const u64 wcap = std::max<u64>(G.wtot, wcap_min);
+    // work layout: the general path's per-item scratch, then the range arrays
+    G.w_cntv = align256(sizeof(uint32_t) * (wcap + 1));
+    G.w_ex = G.w_cntv + align256(sizeof(u64) * (wcap + 1));
+    G.w_bsum = G.w_ex + align256(sizeof(u64) * (wcap + 2));
+    G.w_total = G.w_bsum + align256(sizeof(u64) * (wcap / 1024 + 2));
+    const size_t item_bytes = align256(sizeof(uint32_t) * (wp + 1));
+    G.w_ipart = G.w_total + 256;
+    G.w_irow = G.w_ipart + align256(sizeof(uint16_t) * (wp + 1));
+    G.w_ikey = G.w_irow + item_bytes;
+    G.w_ikv = G.w_ikey + item_bytes;
+    G.w_prow = G.w_ikv + item_bytes;
+    G.w_pkey = G.w_prow + item_bytes;
+    G.w_pkv = G.w_pkey + item_bytes;
+    G.w_scnt = G.w_pkv + item_bytes;
+    G.w_pcnt = G.w_scnt + align256(sizeof(uint32_t) * (nslots + 1));
+    G.w_pcur = G.w_pcnt + align256(sizeof(uint32_t) * (nparts + 1));
+    G.w_pstart = G.w_pcur + align256(sizeof(uint32_t) * (nparts + 1));
+    G.w_pdist = G.w_pstart + align256(sizeof(uint32_t) * (nparts + 1));
+    G.w_rstart = G.w_pdist + align256(sizeof(uint32_t) * (nparts + 1));
+    G.w_pbsum = G.w_rstart + align256(sizeof(uint32_t) * (nparts + 1));
+    const size_t work_bytes = G.w_pbsum + align256(sizeof(uint32_t) * (nparts / 1024 + 2)) + 256;
+    FJ_TRY(G.work.ensure(work_bytes, c->stream));
     std::vector<fj::FillBlock> fb;
+    auto add_zero = [&](uint32_t *p, u64 nwords) {
+        for (u64 off = 0; off < nwords; off += kFillChunk) {
+            fj::FillBlock b;
+            memset(&b, 0, sizeof(b));
+            b.p = p;
+            b.start = off;
+            b.n = std::min<u64>(kFillChunk, nwords - off);
+            b.period = 1;
+            fb.push_back(b);
+        }
+    };
+    if (nparts) {
+        add_zero(G.work.as<uint32_t>(G.w_pcnt), nparts);
+        add_zero(G.work.as<uint32_t>(G.w_pcur), nparts);
+    }
     for (int k = 0; k < n; k++) {
         const fj::FillList &fl = colts[k]->fill_h;
         for (int r = 0; r < fl.n; r++)
@@ -646,14 +731,10 @@ fj_status group_prepare(fj_ctx *c, ColtGroup &G, fj_colt *const *colts, int n, u
     G.o_wpre = align256(sizeof(fj::ForceArgs) * n);
     G.o_roots = G.o_wpre + align256(sizeof(u64) * (n + 1));
     G.o_pre = G.o_roots + align256(sizeof(fj::GroupRoot) * n);
-    G.o_fill = G.o_pre + align256(sizeof(uint32_t) * 2 * n);
+    G.o_pmem = G.o_pre + align256(sizeof(uint32_t) * 2 * n);
+    G.o_fill = G.o_pmem + align256(sizeof(fj::PartMember) * std::max<size_t>(pm.size(), 1));
     G.meta_bytes = G.o_fill + align256(sizeof(fj::FillBlock) * std::max<size_t>(fb.size(), 1));
-    G.w_cntv = align256(sizeof(uint32_t) * (wcap + 1));
-    G.w_ex = G.w_cntv + align256(sizeof(u64) * (wcap + 1));
-    G.w_bsum = G.w_ex + align256(sizeof(u64) * (wcap + 2));
-    G.w_total = G.w_bsum + align256(sizeof(u64) * (wcap / 1024 + 2));
     FJ_TRY(G.meta.ensure(G.meta_bytes, c->stream));
-    FJ_TRY(G.work.ensure(G.w_total + 256, c->stream));
     char *meta = G.meta.as<char>();
     uint32_t *wslot = G.work.as<uint32_t>();
     u64 *cntv = G.work.as<u64>(G.w_cntv), *ex = G.work.as<u64>(G.w_ex);
@@ -687,6 +768,7 @@ fj_status group_prepare(fj_ctx *c, ColtGroup &G, fj_colt *const *colts, int n, u
         g.nroot = t->nroot;
         g.built = t->root_built ? 1 : 0;
     }
+    if (!pm.empty()) memcpy(h + G.o_pmem, pm.data(), sizeof(fj::PartMember) * pm.size());
     if (!fb.empty()) memcpy(h + G.o_fill, fb.data(), sizeof(fj::FillBlock) * fb.size());
     if (G.stage != G.last) {
         FJ_HIP(hipStreamSynchronize(c->stream));   // the pinned source may still be in use
@@ -713,17 +795,68 @@ fj_status group_launch(fj_ctx *c, ColtGroup &G) {
     Timer tm(c, FJ_T_BUILD);
     FJ_HIP(fj::launch_group_fill((const fj::FillBlock *)(meta + G.o_fill), G.nfill,
                                  (const fj::GroupRoot *)(meta + G.o_roots), G.n, c->stream));
-    if (G.wtot == 0) return FJ_OK;
-    FJ_HIP(fj::launch_group_force(0, descs, wpre, G.n, G.wtot, c->stream));   // insert and count
-    FJ_HIP(fj::launch_group_force(1, descs, wpre, G.n, G.wtot, c->stream));   // (1, count) per new key
-    FJ_HIP(fj::launch_scan_u64(G.work.as<u64>(G.w_cntv), G.work.as<u64>(G.w_ex), G.wtot, G.work.as<u64>(G.w_bsum),
-                               G.work.as<u64>(G.w_total), c->stream));       // ranks and child starts
-    FJ_HIP(fj::launch_group_force(2, descs, wpre, G.n, G.wtot, c->stream));   // publish children
-    FJ_HIP(fj::launch_group_force(3, descs, wpre, G.n, G.wtot, c->stream));   // scatter offsets
+    if (G.wtot > 0) {
+        FJ_HIP(fj::launch_group_force(0, descs, wpre, G.n, G.wtot, c->stream));   // insert and count
+        FJ_HIP(fj::launch_group_force(1, descs, wpre, G.n, G.wtot, c->stream));   // (1, count) per new key
+        FJ_HIP(fj::launch_scan_u64(G.work.as<u64>(G.w_cntv), G.work.as<u64>(G.w_ex), G.wtot,
+                                   G.work.as<u64>(G.w_bsum), G.work.as<u64>(G.w_total), c->stream));
+        FJ_HIP(fj::launch_group_force(2, descs, wpre, G.n, G.wtot, c->stream));   // publish children
+        FJ_HIP(fj::launch_group_force(3, descs, wpre, G.n, G.wtot, c->stream));   // scatter offsets
+    }
+    if (G.nparts > 0) {
+        // KM_K32 roots range by range: count, group by range, build, rank
+        fj::PartArgs pa;
+        memset(&pa, 0, sizeof(pa));
+        pa.descs = descs;
+        pa.mem = (const fj::PartMember *)(meta + G.o_pmem);
+        pa.n = G.npm;
+        pa.nblocks = G.nblocks;
+        pa.nparts = G.nparts;
+        pa.ipart = G.work.as<uint16_t>(G.w_ipart);
+        pa.irow = G.work.as<uint32_t>(G.w_irow);
+        pa.ikey = G.work.as<uint32_t>(G.w_ikey);
+        pa.ikv = G.work.as<uint32_t>(G.w_ikv);
+        pa.prow = G.work.as<uint32_t>(G.w_prow);
+        pa.pkey = G.work.as<uint32_t>(G.w_pkey);
+        pa.pkv = G.work.as<uint32_t>(G.w_pkv);
+        pa.scnt = G.work.as<uint32_t>(G.w_scnt);
+        pa.pcnt = G.work.as<uint32_t>(G.w_pcnt);
+        pa.pcur = G.work.as<uint32_t>(G.w_pcur);
+        pa.pstart = G.work.as<uint32_t>(G.w_pstart);
+        pa.pdist = G.work.as<uint32_t>(G.w_pdist);
+        pa.rstart = G.work.as<uint32_t>(G.w_rstart);
+        pa.status = c->status_d;
+        uint32_t *pbsum = G.work.as<uint32_t>(G.w_pbsum);
+        // few ranges: the passes sum the counts they need (no scan
+        // launches); more: the scans run in one workgroup, or in three
+        // launches beyond 32,768 ranges
+        pa.inline_scan = G.nparts <= 2048 ? 1 : 0;
+        auto scan = [&](const uint32_t *in, uint32_t *out) -> hipError_t {
+            if (pa.inline_scan) return hipSuccess;
+            return G.nparts <= 32768 ? fj::launch_scan_small_u32(in, out, G.nparts, c->stream)
+                                     : fj::launch_scan_u32(in, out, G.nparts, pbsum, out + G.nparts, c->stream);
+        };
+        FJ_HIP(fj::launch_part_phase(0, pa, c->stream));
+        FJ_HIP(scan(pa.pcnt, pa.pstart));
+        FJ_HIP(fj::launch_part_phase(1, pa, c->stream));
+        FJ_HIP(fj::launch_part_phase(2, pa, c->stream));
+        FJ_HIP(scan(pa.pdist, pa.rstart));
+        FJ_HIP(fj::launch_part_phase(3, pa, c->stream));
+    }
     return FJ_OK;
 }
 
 }  // namespace
+
+// One COLT's root built range by range, through the grouped path (its own
+// group, so that fj_colt_rebuild_many's cached descriptors stay valid).
+static fj_status colt_rebuild_group(fj_ctx *c, fj_colt *t) {
+    if (!c->group1) c->group1 = new ColtGroup();
+    fj_colt *one[1] = {t};
+    FJ_TRY(group_prepare(c, *c->group1, one, 1, 0));
+    FJ_TRY(group_launch(c, *c->group1));
+    return colt_force_all(c, t);
+}
 
 static fj_status check_relation(const fj_relation *r, int arity) {
     if (!r) return fail(FJ_ERR_ARG, "null relation");
@@ -841,6 +974,7 @@ void fj_ctx_destroy(fj_ctx *c) {
     c->sketch.release();
     if (c->sketch_h) hipHostFree(c->sketch_h);
     destroy_group(c->group);
+    destroy_group(c->group1);
     if (c->desc_h) hipHostFree(c->desc_h);
     if (c->desc_done) hipEventDestroy(c->desc_done);
     for (auto &p : c->pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }

@@ -53,7 +53,7 @@ __device__ __forceinline__ uint32_t root_get(const BLookup &L, const Lane &ln, u
             return T[w] ? T[w + 4] : ~0u;
         }
         u64 i = (bmix32(key) & L.mask) & ~(u64)(kK32Bucket - 1);
-        for (u64 n = 0; n <= L.mask; n += kK32Bucket) {
+        for (u64 n = 0; n <= k32_part_mask(L.mask); n += kK32Bucket) {
             const u64 w = k32_key_word(i);
             const uint4 q = *(const uint4 *)(T + w);
             const uint32_t ks[4] = {q.x, q.y, q.z, q.w};
@@ -62,7 +62,7 @@ __device__ __forceinline__ uint32_t root_get(const BLookup &L, const Lane &ln, u
                 if (ks[s] == key) return T[w + 4 + s];
                 if (ks[s] == kEmpty32) return ~0u;
             }
-            i = (i + kK32Bucket) & L.mask;
+            i = k32_next(i, L.mask);
         }
     } else {
         const Slot64 *T = (const Slot64 *)L.table;

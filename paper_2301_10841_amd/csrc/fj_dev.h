@@ -41,6 +41,18 @@ __host__ __device__ inline unsigned long long k32_key_word(unsigned long long i)
     return ((i >> 2) << 3) + (i & 3);
 }
 __host__ __device__ inline unsigned long long k32_table_words(unsigned long long cap) { return 2 * cap + 8; }
+// A KM_K32 map is probed within ranges of kK32Part slots (the whole map when
+// it is smaller): a key's walk starts at its bucket and wraps at the end of
+// the bucket's range.  So the keys of one range can be placed by one
+// workgroup in LDS (the grouped root build) and found by the same walk.
+constexpr unsigned long long kK32Part = 2048;
+__host__ __device__ inline unsigned long long k32_part_mask(unsigned long long mask) {
+    return mask < kK32Part ? mask : kK32Part - 1;
+}
+__host__ __device__ inline unsigned long long k32_next(unsigned long long b, unsigned long long mask) {
+    const unsigned long long pm = k32_part_mask(mask);
+    return (b & ~pm) | ((b + kK32Bucket) & pm);
+}
 struct alignas(16) Slot64 { unsigned long long key; uint32_t val; uint32_t pad; };
 struct alignas(16) SlotRep { unsigned long long hr; uint32_t val; uint32_t pad; };  // hr = row << 32 | handle
 
@@ -230,6 +242,41 @@ struct GroupRoot {
     uint32_t *len, *st, *fq, *pre;
     uint32_t nroot;
     int built;
+};
+
+// Grouped root builds by key range (KM_K32 roots): a member COLT whose map
+// of np ranges (kK32Part slots each, or the whole map when smaller) is
+// built range by range, each range by one workgroup in LDS.
+constexpr uint32_t kMaxParts = 4096;       // ranges per map on this path
+constexpr uint32_t kPartItems = 1024;      // items per block of the count and scatter passes
+struct PartMember {
+    int desc;                 // the member's ForceArgs in the group
+    uint32_t np;              // ranges of its map
+    uint32_t plog;            // log2 of the slots per range
+    uint32_t part_base;       // its first range in the group's range space
+    uint32_t block_base;      // its first block of the count and scatter passes
+    uint32_t item_base;       // its first item in the group's item space
+    uint32_t W;               // its root rows
+    unsigned long long slot_base;  // its first slot in the group's slot space (scnt)
+};
+struct PartArgs {
+    const ForceArgs *descs;
+    const PartMember *mem;
+    int n;
+    uint32_t nblocks;         // blocks of the count and scatter passes
+    uint32_t nparts;          // ranges of every member
+    int inline_scan;          // few ranges: the passes sum the per-range counts they need themselves
+                              // (the scatter pass's block 0 writes pstart), no scan launches
+    uint16_t *ipart;          // per item: its range within its member
+    uint32_t *irow, *ikey, *ikv;   // per item: its row, root key and child-level key (ikv: if kept)
+    uint32_t *pcnt;           // per range: items (counted)
+    uint32_t *pcur;           // per range: scatter cursor
+    uint32_t *pstart;         // nparts + 1: exclusive scan of pcnt (items grouped by range)
+    uint32_t *prow, *pkey, *pkv;   // the items' row, key and child key, grouped by range
+    uint32_t *scnt;           // per slot of every range (ranges at slot_base): its key's offset count
+    uint32_t *pdist;          // per range: distinct keys
+    uint32_t *rstart;         // nparts + 1: exclusive scan of pdist (ranks)
+    struct StatusDev *status;
 };
 
 // Result counts are added to kCountParts partial counters, each on its own

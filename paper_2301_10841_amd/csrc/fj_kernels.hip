@@ -95,7 +95,7 @@ __device__ __forceinline__ u64 table_find(const LevelDev &L, const int32_t *cons
         if (key == kEmpty32) return T[k32_key_word(mask + 1)] ? mask + 1 : ~0ull;
         // a bucket's four keys in one 16-byte load, then the next bucket
         u64 b = k32_bucket(mix32(key), mask);
-        for (u64 n = 0; n <= mask; n += kK32Bucket) {
+        for (u64 n = 0; n <= k32_part_mask(mask); n += kK32Bucket) {
             const uint4 q = *(const uint4 *)(T + k32_key_word(b));
             const uint32_t ks[kK32Bucket] = {q.x, q.y, q.z, q.w};
 #pragma unroll
@@ -103,7 +103,7 @@ __device__ __forceinline__ u64 table_find(const LevelDev &L, const int32_t *cons
                 if (ks[s] == key) return b + s;
                 if (ks[s] == kEmpty32) return ~0ull;
             }
-            b = (b + kK32Bucket) & mask;
+            b = k32_next(b, mask);
         }
     } else if (L.mode == KM_K64) {
         const Slot64 *T = (const Slot64 *)L.table;
@@ -187,7 +187,7 @@ __device__ __forceinline__ u64 table_insert(const LevelDev &L, const int32_t *co
         // only ever go from empty to a key and the swap returns the true
         // occupant, so a lost race just moves on in slot order
         u64 b = k32_bucket(mix32(key), mask);
-        for (u64 n = 0; n <= mask; n += kK32Bucket) {
+        for (u64 n = 0; n <= k32_part_mask(mask); n += kK32Bucket) {
             const uint4 q = *(const uint4 *)(T + k32_key_word(b));
             const uint32_t ks[kK32Bucket] = {q.x, q.y, q.z, q.w};
 #pragma unroll
@@ -199,7 +199,7 @@ __device__ __forceinline__ u64 table_insert(const LevelDev &L, const int32_t *co
                 }
                 if (c == key) return b + s;
             }
-            b = (b + kK32Bucket) & mask;
+            b = k32_next(b, mask);
         }
     } else if (L.mode == KM_K64) {
         Slot64 *T = (Slot64 *)L.table;
@@ -837,7 +837,17 @@ __global__ void __launch_bounds__(256) k_group_force(const ForceArgs *__restrict
 // One block per FillBlock: a chunk of one region set to its periodic
 // pattern (period 1, 2 or 4 words), in 16-byte stores from a 16-byte
 // aligned chunk start.
-__global__ void __launch_bounds__(256) k_group_fill(const FillBlock *__restrict__ fb) {
+__device__ __forceinline__ void group_root_words(const GroupRoot &g);
+
+// Blocks [0, nfill): one FillBlock each; the blocks after them: the COLTs'
+// root words (which no fill region covers), 256 COLTs per block.
+__global__ void __launch_bounds__(256) k_group_fill(const FillBlock *__restrict__ fb, uint32_t nfill,
+                                                    const GroupRoot *__restrict__ roots, int n) {
+    if (blockIdx.x >= nfill) {
+        const int k = (int)(blockIdx.x - nfill) * 256 + threadIdx.x;
+        if (k < n) group_root_words(roots[k]);
+        return;
+    }
     const FillBlock &b = fb[blockIdx.x];
     const u64 m = (u64)b.period - 1;   // 1, 2, 4 or 8 words; b.start % 8 == 0
     uint32_t *p = b.p + b.start;
@@ -850,14 +860,378 @@ __global__ void __launch_bounds__(256) k_group_fill(const FillBlock *__restrict_
 
 // Per COLT: the root handle spans every root row; a built root with no rows
 // is forced with no keys; the root's force queue holds the root handle.
-__global__ void k_group_roots(const GroupRoot *__restrict__ r, int n) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const GroupRoot &g = r[k];
+__device__ __forceinline__ void group_root_words(const GroupRoot &g) {
     g.len[0] = g.nroot;
     g.st[0] = (g.built && g.nroot == 0) ? 1u : 0u;
     if (g.fq) g.fq[0] = 0;
     if (g.pre) { g.pre[0] = 0; g.pre[1] = g.nroot; }
+}
+
+// ------------------------------------------- grouped root builds by range
+// A KM_K32 root map is probed within ranges of kK32Part slots (k32_next), so
+// the keys of one range can all be placed by one workgroup: the group's
+// items are counted per range and grouped by range (two passes with one
+// global atomic per block and range, not per item), then each range is
+// built in LDS and written out whole, table words, child segments and
+// offsets, with plain stores; a last pass numbers the keys across ranges.
+// The map needs no clearing beforehand and no per-key device atomics,
+// which on this GPU are performed past the L2 and are slow.
+
+__device__ __forceinline__ int part_member_of_block(const PartArgs &a, uint32_t b) {
+    int lo = 0, hi = a.n;   // mem[lo].block_base <= b
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a.mem[mid].block_base <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int part_member_of_part(const PartArgs &a, uint32_t P) {
+    int lo = 0, hi = a.n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a.mem[mid].part_base <= P) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// The range of a root key: its bucket's range, or the last range for the
+// key equal to the empty marker (kept in the reserved slot).
+__device__ __forceinline__ uint32_t key_part(const LevelDev &L, uint32_t key, uint32_t np, uint32_t plog) {
+    if (key == kEmpty32) return np - 1;
+    return (uint32_t)(k32_bucket(mix32(key), L.mask) >> plog);
+}
+
+// Pass 1: items per range.  One block takes kPartItems items of one member.
+__global__ void __launch_bounds__(256) k_part_count(PartArgs a) {
+    __shared__ uint32_t hist[kMaxParts];
+    StatusDev *status = a.status;
+    const int k = part_member_of_block(a, blockIdx.x);
+    const PartMember &m = a.mem[k];
+    const ForceArgs &f = a.descs[m.desc];
+    for (uint32_t p = threadIdx.x; p < m.np; p += 256) hist[p] = 0;
+    __syncthreads();
+    const uint32_t w0 = (blockIdx.x - m.block_base) * kPartItems;
+    const int32_t *kc = f.cols[f.L.kcol[0]];
+    const int32_t *kvc = f.C.kv ? f.cols[f.C.kcol[0]] : nullptr;
+    constexpr int R = (int)(kPartItems / 256);
+    uint32_t row[R], key[R], kv[R];
+    bool ok[R];
+    // the gathers of all the thread's items in flight together
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const uint32_t w = w0 + r * 256 + threadIdx.x;
+        ok[r] = w < m.W;
+        row[r] = ok[r] ? (f.L.offs ? f.L.offs[w] : w) : 0u;
+        ok[r] = ok[r] && CK(row[r] < f.L.nrows);
+    }
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        key[r] = ok[r] ? (uint32_t)kc[row[r]] : 0u;
+        kv[r] = (ok[r] && kvc) ? (uint32_t)kvc[row[r]] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        if (!ok[r]) continue;
+        const uint32_t w = w0 + r * 256 + threadIdx.x;
+        const uint32_t part = key_part(f.L, key[r], m.np, m.plog);
+        if (!CK(part < m.np)) continue;
+        const u64 it = (u64)m.item_base + w;
+        a.ipart[it] = (uint16_t)part;
+        a.irow[it] = row[r];
+        a.ikey[it] = key[r];
+        if (kvc) a.ikv[it] = kv[r];
+        atomicAdd(&hist[part], 1u);
+    }
+    __syncthreads();
+    for (uint32_t p = threadIdx.x; p < m.np; p += 256)
+        if (hist[p]) atomicAdd(&a.pcnt[m.part_base + p], hist[p]);
+}
+
+// Sum of in[lo, hi) by the whole block (every thread gets it).
+__device__ __forceinline__ uint32_t block_sum_u32(const uint32_t *in, uint32_t lo, uint32_t hi, uint32_t *red) {
+    uint32_t v = 0;
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) v += in[i];
+    uint32_t tot;
+    block_excl_scan<uint32_t>(v, red, tot);
+    return tot;
+}
+
+// out[i] = add + in[0] + ... + in[i - 1] for i <= n, by the whole block.
+__device__ __forceinline__ void block_scan_u32(const uint32_t *in, uint32_t n, uint32_t add, uint32_t *out,
+                                               uint32_t *red) {
+    uint32_t carry = add;
+    for (uint32_t c = 0; c < n; c += blockDim.x) {
+        const uint32_t i = c + threadIdx.x;
+        const uint32_t v = i < n ? in[i] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<uint32_t>(v, red, tot);
+        if (i < n) out[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
+// Pass 2 (after the scan of the counts): items grouped by range, each
+// block reserving its share of every range with one atomic.  With few
+// ranges the block takes its member's range starts from the counts
+// itself, and block 0 writes every range's start for the build pass.
+__global__ void __launch_bounds__(256) k_part_scatter(PartArgs a) {
+    __shared__ uint32_t hist[kMaxParts];
+    __shared__ uint32_t pst[kMaxParts + 1];
+    __shared__ uint32_t red[17];
+    StatusDev *status = a.status;
+    const int k = part_member_of_block(a, blockIdx.x);
+    const PartMember &m = a.mem[k];
+    for (uint32_t p = threadIdx.x; p < m.np; p += 256) hist[p] = 0;
+    const uint32_t *pstart = a.pstart + m.part_base;
+    if (a.inline_scan) {
+        if (blockIdx.x == 0) block_scan_u32(a.pcnt, a.nparts, 0u, a.pstart, red);
+        const uint32_t before = block_sum_u32(a.pcnt, 0, m.part_base, red);
+        block_scan_u32(a.pcnt + m.part_base, m.np, before, pst, red);
+        pstart = pst;
+    }
+    __syncthreads();
+    const uint32_t w0 = (blockIdx.x - m.block_base) * kPartItems;
+    constexpr int R = (int)(kPartItems / 256);
+    uint32_t part[R], loc[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const uint32_t w = w0 + r * 256 + threadIdx.x;
+        part[r] = w < m.W ? a.ipart[m.item_base + w] : 0xFFFFFFFFu;
+        if (part[r] < m.np) loc[r] = atomicAdd(&hist[part[r]], 1u);
+    }
+    __syncthreads();
+    for (uint32_t p = threadIdx.x; p < m.np; p += 256)
+        if (hist[p]) hist[p] = atomicAdd(&a.pcur[m.part_base + p], hist[p]);
+    __syncthreads();
+    const bool has_kv = a.descs[m.desc].C.kv != nullptr;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        if (part[r] >= m.np) continue;
+        const uint32_t w = w0 + r * 256 + threadIdx.x;
+        const u64 it = (u64)m.item_base + w;
+        const u64 pos = (u64)pstart[part[r]] + hist[part[r]] + loc[r];
+        if (!CK(pos < pstart[part[r] + 1])) continue;
+        a.prow[pos] = a.irow[it];
+        a.pkey[pos] = a.ikey[it];
+        if (has_kv) a.pkv[pos] = a.ikv[it];
+    }
+}
+
+// Find (or, inserting, claim) key's slot in an LDS range of n slots
+// (n a power of two, at least a bucket): the walk of k32_next within it.
+__device__ __forceinline__ uint32_t lds_slot(uint32_t *keys, uint32_t n, uint32_t start, uint32_t key, bool insert) {
+    uint32_t b = start;
+    for (uint32_t i = 0; i < n; i++) {
+        const uint32_t c = keys[b];
+        if (c == key) return b;
+        if (c == kEmpty32) {
+            if (!insert) return 0xFFFFFFFFu;
+            const uint32_t old = atomicCAS(&keys[b], kEmpty32, key);
+            if (old == kEmpty32 || old == key) return b;
+        }
+        b = (b + 1) & (n - 1);
+    }
+    return 0xFFFFFFFFu;   // the range is full
+}
+
+// Lanes of a wave holding the same LDS slot as the wave's first remaining
+// lane add their number to its counter with one atomic (up to two rounds,
+// so that a heavy key under skew does not serialize a wave on one LDS
+// word).  A lane so served gets todo = false and, in old, the counter's
+// value before the group's addition plus its rank in the group; lanes left
+// with todo make their own atomic.
+__device__ __forceinline__ bool wave_slot_add(bool &todo, uint32_t s, uint32_t *ctr, uint32_t &old) {
+    const int lane = __lane_id();
+    for (int round = 0; round < 2; round++) {
+        const u64 act = __ballot(todo);
+        if (act == 0) return false;
+        const int leader = __ffsll((long long)act) - 1;
+        const uint32_t ls = __shfl(s, leader, 64);
+        const bool same = todo && s == ls;
+        const u64 grp = __ballot(same);
+        const int m = __popcll(grp);
+        if (m < 2) return false;
+        uint32_t b = 0;
+        if (lane == leader) b = atomicAdd(&ctr[ls], (uint32_t)m);
+        b = __shfl(b, leader, 64);
+        if (same) {
+            todo = false;
+            old = b + (uint32_t)__popcll(grp & ((1ull << lane) - 1ull));
+            return true;
+        }
+    }
+    return false;
+}
+
+// Pass 3: one workgroup per range builds it in LDS: keys and their offset
+// counts, child segments laid out in the range's own item positions (the
+// empty marker's first), then the range's table words, child lengths,
+// offsets (and the keys beside them) and per-slot counts are written.  The
+// items' rows and keys were gathered by the count pass and moved into range
+// order by the scatter pass, so they are read here contiguously.
+constexpr int kPartBuildThreads = 1024;
+__global__ void __launch_bounds__(kPartBuildThreads) k_part_build(PartArgs a) {
+    __shared__ uint32_t keys[kK32Part];
+    __shared__ uint32_t cnt[kK32Part];
+    __shared__ uint32_t red[17];
+    __shared__ uint32_t emp;
+    StatusDev *status = a.status;
+    const uint32_t P = blockIdx.x;
+    const int k = part_member_of_part(a, P);
+    const PartMember &m = a.mem[k];
+    const ForceArgs &f = a.descs[m.desc];
+    const uint32_t lp = P - m.part_base;
+    const uint32_t n = 1u << m.plog;                  // slots of the range
+    const u64 s0 = (u64)lp << m.plog;                 // its first slot in the map
+    for (uint32_t s = threadIdx.x; s < n; s += kPartBuildThreads) { keys[s] = kEmpty32; cnt[s] = 0; }
+    if (threadIdx.x == 0) emp = 0;
+    __syncthreads();
+    const uint32_t i0 = a.pstart[P], i1 = a.pstart[P + 1];
+    const uint32_t base = i0 - a.pstart[m.part_base];  // the range's first position in the member
+    const bool has_kv = f.C.kv != nullptr;
+    // (the loops run whole waves, so that lanes can pool their atomics)
+    const uint32_t i1w = i0 + ((i1 - i0 + kPartBuildThreads - 1) / kPartBuildThreads) * kPartBuildThreads;
+    for (uint32_t i = i0 + threadIdx.x; i < i1w; i += kPartBuildThreads) {
+        const bool live = i < i1;
+        const uint32_t key = live ? a.pkey[i] : kEmpty32;
+        if (live && key == kEmpty32) atomicAdd(&emp, 1u);
+        uint32_t s = 0xFFFFFFFFu;
+        if (live && key != kEmpty32) {
+            s = lds_slot(keys, n, (uint32_t)(k32_bucket(mix32(key), f.L.mask) - s0), key, true);
+            CK(s < n);
+        }
+        bool todo = s < n;
+        uint32_t old;
+        wave_slot_add(todo, s, cnt, old);
+        if (todo) atomicAdd(&cnt[s], 1u);
+    }
+    __syncthreads();
+    // child starts in slot order, the empty marker's child first
+    constexpr int SPT = (int)(kK32Part / kPartBuildThreads);   // slots per thread
+    uint32_t sum = 0, nk = 0;
+#pragma unroll
+    for (int j = 0; j < SPT; j++) {
+        const uint32_t s = threadIdx.x * SPT + j;
+        if (s < n) { sum += cnt[s]; nk += keys[s] != kEmpty32; }
+    }
+    uint32_t tot;
+    uint32_t pre = block_excl_scan<uint32_t>(sum, red, tot) + emp;
+    uint32_t ktot;
+    block_excl_scan<uint32_t>(nk, red, ktot);
+    uint32_t *T = (uint32_t *)f.L.table;
+    uint32_t *sc = a.scnt + m.slot_base + s0;
+#pragma unroll
+    for (int j = 0; j < SPT; j++) {
+        const uint32_t s = threadIdx.x * SPT + j;
+        if (s >= n) continue;
+        const uint32_t c = cnt[s];
+        const u64 w = k32_key_word(s0 + s);
+        T[w] = keys[s];
+        T[w + 4] = c ? base + pre : 0u;
+        sc[s] = c;
+        if (c && CK((u64)base + pre < f.C.npos)) f.C.len[base + pre] = c;
+        cnt[s] = base + pre;                          // from here on: the slot's scatter cursor
+        pre += c;
+    }
+    const bool last = lp + 1 == m.np;
+    if (threadIdx.x == 0) {
+        if (last) {
+            // the reserved slot: claimed when the empty marker is a key
+            const u64 w = k32_key_word(f.L.mask + 1);
+            T[w] = emp ? 1u : 0u;
+            T[w + 4] = emp ? base : 0u;
+            if (emp && CK(base < f.C.npos)) f.C.len[base] = emp;
+        }
+        a.pdist[P] = ktot + (emp ? 1u : 0u);
+        emp = base;                                   // the empty marker's scatter cursor
+    }
+    __syncthreads();
+    for (uint32_t i = i0 + threadIdx.x; i < i1w; i += kPartBuildThreads) {
+        const bool live = i < i1;
+        const uint32_t key = live ? a.pkey[i] : kEmpty32;
+        uint32_t pos = 0xFFFFFFFFu;
+        if (live && key == kEmpty32) pos = atomicAdd(&emp, 1u);
+        uint32_t s = 0xFFFFFFFFu;
+        if (live && key != kEmpty32) {
+            s = lds_slot(keys, n, (uint32_t)(k32_bucket(mix32(key), f.L.mask) - s0), key, false);
+            CK(s < n);
+        }
+        bool todo = s < n;
+        wave_slot_add(todo, s, cnt, pos);
+        if (todo) pos = atomicAdd(&cnt[s], 1u);
+        if (!live || pos == 0xFFFFFFFFu) continue;
+        if (!CK(pos < f.C.npos && pos >= base)) continue;
+        f.C.offs[pos] = a.prow[i];
+        if (has_kv) f.C.kv[pos] = (int32_t)a.pkv[i];
+    }
+}
+
+// Pass 4 (after the scan of the distinct counts): the keys of each range
+// take their ranks in slot order (the empty marker's first) and are listed
+// in the root's key list; a member's first range records its key count.
+__global__ void __launch_bounds__(256) k_part_ranks(PartArgs a) {
+    __shared__ uint32_t red[17];
+    StatusDev *status = a.status;
+    const uint32_t P = blockIdx.x;
+    const int k = part_member_of_part(a, P);
+    const PartMember &m = a.mem[k];
+    const ForceArgs &f = a.descs[m.desc];
+    const uint32_t lp = P - m.part_base;
+    const uint32_t n = 1u << m.plog;
+    const u64 s0 = (u64)lp << m.plog;
+    const uint32_t *T = (const uint32_t *)f.L.table;
+    const uint32_t *sc = a.scnt + m.slot_base + s0;
+    const bool last = lp + 1 == m.np;
+    const u64 wr = k32_key_word(f.L.mask + 1);
+    const uint32_t has_emp = (last && T[wr]) ? 1u : 0u;
+    uint32_t r;
+    if (a.inline_scan) {
+        // the distinct keys of the member's earlier ranges (and, for its
+        // first range, of all of them), summed here
+        r = block_sum_u32(a.pdist, m.part_base, P, red);
+        if (lp == 0) {
+            const uint32_t nk = block_sum_u32(a.pdist, m.part_base, m.part_base + m.np, red);
+            if (threadIdx.x == 0) { f.L.st[0] = nk + 1; f.L.rank_ctr[0] = nk; }
+        }
+    } else {
+        r = a.rstart[P] - a.rstart[m.part_base];
+        if (threadIdx.x == 0 && lp == 0) {
+            const uint32_t nk = a.rstart[m.part_base + m.np] - a.rstart[m.part_base];
+            f.L.st[0] = nk + 1;
+            f.L.rank_ctr[0] = nk;
+        }
+    }
+    if (has_emp && threadIdx.x == 0 && CK(r < f.L.npos)) {
+        const uint32_t c = T[wr + 4];
+        f.L.kl[r] = c;
+        if (f.L.kk) { f.L.kk[r] = (int32_t)kEmpty32; f.L.kn[r] = f.C.len[c]; }
+    }
+    r += has_emp;
+    constexpr int SPT = (int)(kK32Part / 256);
+    uint32_t key[SPT], val[SPT];
+    uint32_t nk = 0;
+#pragma unroll
+    for (int j = 0; j < SPT; j++) {
+        const uint32_t s = threadIdx.x * SPT + j;
+        const u64 w = k32_key_word(s0 + (s < n ? s : 0));
+        key[j] = s < n ? T[w] : kEmpty32;
+        val[j] = s < n ? T[w + 4] : 0u;
+        nk += key[j] != kEmpty32;
+    }
+    uint32_t ktot;
+    r += block_excl_scan<uint32_t>(nk, red, ktot);
+#pragma unroll
+    for (int j = 0; j < SPT; j++) {
+        const uint32_t s = threadIdx.x * SPT + j;
+        if (key[j] == kEmpty32) continue;
+        if (CK(r < f.L.npos)) {
+            f.L.kl[r] = val[j];
+            if (f.L.kk) { f.L.kk[r] = (int32_t)key[j]; f.L.kn[r] = sc[s]; }
+        }
+        r++;
+    }
 }
 
 // ----------------------------------------------------------- cover choice
@@ -1333,8 +1707,8 @@ __device__ __forceinline__ bool probe_resolve(const ScanLookup &L, RowProbe &rp,
         if (rp.empty) return T[k32_key_word(L.mask + 1)] != 0u;
         int s = 0;
         int st = scan_keys32(rp.q0, (uint32_t)rp.key, s);
-        for (u64 n = kK32Bucket; st == 0 && n <= L.mask; n += kK32Bucket) {   // a full bucket (rare)
-            rp.idx = (rp.idx + kK32Bucket) & L.mask;
+        for (u64 n = kK32Bucket; st == 0 && n <= k32_part_mask(L.mask); n += kK32Bucket) {   // a full bucket (rare)
+            rp.idx = k32_next(rp.idx, L.mask);
             rp.q0 = *(const uint4 *)(T + k32_key_word(rp.idx));
             st = scan_keys32(rp.q0, (uint32_t)rp.key, s);
         }
@@ -2107,8 +2481,8 @@ hipError_t launch_force_phase(int phase, const ForceLaunch &f, hipStream_t s) {
 }
 
 hipError_t launch_group_fill(const FillBlock *fb, uint32_t nblocks, const GroupRoot *roots, int n, hipStream_t s) {
-    if (nblocks) hipLaunchKernelGGL(k_group_fill, dim3(nblocks), dim3(256), 0, s, fb);
-    if (n) hipLaunchKernelGGL(k_group_roots, dim3((n + 255) / 256), dim3(256), 0, s, roots, n);
+    const uint32_t g = nblocks + (uint32_t)((n + 255) / 256);
+    if (g) hipLaunchKernelGGL(k_group_fill, dim3(g), dim3(256), 0, s, fb, nblocks, roots, n);
     return hipGetLastError();
 }
 
@@ -2120,6 +2494,49 @@ hipError_t launch_group_force(int phase, const ForceArgs *descs, const u64 *wpre
         case 1: hipLaunchKernelGGL(k_group_force<1>, g, b, 0, s, descs, wpre, n, wtot); break;
         case 2: hipLaunchKernelGGL(k_group_force<2>, g, b, 0, s, descs, wpre, n, wtot); break;
         case 3: hipLaunchKernelGGL(k_group_force<3>, g, b, 0, s, descs, wpre, n, wtot); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Exclusive scan of n u32 values by one workgroup (n up to a few hundred
+// thousand; for the grouped builds' per-range counts), out[n] = total.
+__global__ void __launch_bounds__(1024) k_scan_small_u32(const uint32_t *in, uint32_t *out, uint32_t n) {
+    __shared__ uint32_t lds[17];
+    uint32_t carry = 0;
+    for (uint32_t c = 0; c < n; c += 1024 * 4) {
+        uint32_t v[4], sum = 0;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint32_t i = c + threadIdx.x * 4 + j;
+            v[j] = i < n ? in[i] : 0u;
+            sum += v[j];
+        }
+        uint32_t tot;
+        uint32_t ex = carry + block_excl_scan<uint32_t>(sum, lds, tot);
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint32_t i = c + threadIdx.x * 4 + j;
+            if (i < n) out[i] = ex;
+            ex += v[j];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
+hipError_t launch_scan_small_u32(const uint32_t *in, uint32_t *out, uint32_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan_small_u32, dim3(1), dim3(1024), 0, s, in, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_part_phase(int phase, const PartArgs &a, hipStream_t s) {
+    if (a.n <= 0 || a.nparts == 0) return hipSuccess;
+    switch (phase) {
+        case 0: if (a.nblocks) hipLaunchKernelGGL(k_part_count, dim3(a.nblocks), dim3(256), 0, s, a); break;
+        case 1: if (a.nblocks) hipLaunchKernelGGL(k_part_scatter, dim3(a.nblocks), dim3(256), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(k_part_build, dim3(a.nparts), dim3(kPartBuildThreads), 0, s, a); break;
+        case 3: hipLaunchKernelGGL(k_part_ranks, dim3(a.nparts), dim3(256), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
