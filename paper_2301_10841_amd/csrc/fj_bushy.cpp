@@ -93,6 +93,12 @@ struct DevBufs {
     }
 };
 
+// A factorized intermediate, freed (before its plan's COLTs) on scope exit.
+struct ResultGuard {
+    fj_result *r = nullptr;
+    ~ResultGuard() { fj_result_free(r); }
+};
+
 struct PlanColts {
     fj_plan *plan = nullptr;
     std::vector<fj_colt *> colts;
@@ -198,10 +204,12 @@ extern "C" fj_status fj_execute_bushy(fj_ctx *ctx, const fj_query *q, const fj_b
             if (st != FJ_OK) return st;
         }
         if (last) return fj_execute(ctx, &qk, pc.plan, pc.colts.data(), count, out, cap, written, nullptr);
-        // an intermediate: count, then materialize its rows and lay them out
-        // as columns
-        uint64_t n = 0;
-        st = fj_execute(ctx, &qk, pc.plan, pc.colts.data(), &n, nullptr, 0, nullptr, nullptr);
+        // an intermediate: one run that keeps its result factorized (its
+        // exact count known), then its rows expanded into a row-major
+        // buffer and laid out as columns
+        uint64_t n = 0, nbind = 0;
+        ResultGuard rg;
+        st = fj_execute_factorized(ctx, &qk, pc.plan, pc.colts.data(), &rg.r, &n, &nbind);
         if (st != FJ_OK) return st;
         if (n >= (uint64_t(1) << 31)) return fj::set_error(FJ_ERR_UNSUPPORTED, "an intermediate has 2^31 rows or more");
         const int m = qk.nvars;
@@ -221,12 +229,10 @@ extern "C" fj_status fj_execute_bushy(fj_ctx *ctx, const fj_query *q, const fj_b
         void *rows = nullptr;
         st = mem.alloc(&rows, n * (size_t)m * sizeof(int32_t));
         if (st != FJ_OK) return st;
-        st = fj_colt_rebuild_many(ctx, (int32_t)in.size(), pc.colts.data(), rk.data());
+        uint64_t w = 0;
+        st = fj_result_expand(ctx, rg.r, 0, (int32_t *)rows, n, &w);
         if (st != FJ_OK) return st;
-        uint64_t n2 = 0, w = 0;
-        st = fj_execute(ctx, &qk, pc.plan, pc.colts.data(), &n2, (int32_t *)rows, n, &w, nullptr);
-        if (st != FJ_OK) return st;
-        if (n2 != n || w != n) return fj::set_error(FJ_ERR_HIP, "an intermediate's count changed between runs");
+        if (w != n) return fj::set_error(FJ_ERR_INTERNAL, "an intermediate's expansion wrote fewer rows than its count");
         if (fj::launch_rows_to_cols((const int32_t *)rows, n, m, colp, s) != hipSuccess)
             return fj::set_error(FJ_ERR_HIP, "row to column launch failed");
         // the rows buffer is freed with the others when the call returns;
