@@ -20,6 +20,7 @@ host (the ``cpu_baseline`` leg, the only part that runs the oracle).
 """
 
 import argparse
+import gc
 import json
 import os
 import statistics
@@ -60,6 +61,12 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
+    # Python's cyclic garbage collector stays off: one collection of this
+    # process's heap (torch's objects) takes tens of milliseconds and lands
+    # inside whichever timed step triggers it (reference counting still
+    # frees everything the steps create)
+    gc.collect()
+    gc.disable()
     if args.calibrate_copy:
         return calibrate_copy()
     if args.gpus != 1:
@@ -282,7 +289,8 @@ def chooser_leg(ctx, n):
     from paper_2301_10841_amd import learn
     t0 = time.time()
     m, info = learn.load(ctx)
-    rows = learn.evaluate(ctx, m, learn.QuerySupply(0), datagen.seed_for(5, 3), n, reps=5)
+    rows = learn.evaluate(ctx, m, learn.QuerySupply(0), datagen.seed_for(5, 3), n, reps=5,
+                          gate_rows=int(info.get("gate_rows", 0)))
     s = learn.summarize(rows)
     m.free()
     log(f"chooser leg: {n} queries in {time.time() - t0:.1f}s")
@@ -291,6 +299,7 @@ def chooser_leg(ctx, n):
             "learned_mean_regret": s["learned_mean_regret_vs_best"],
             "plain_mean_regret": s["plain_mean_regret_vs_best"],
             "choose_learned_ms": s["choose_learned_ms_mean"], "choose_plain_ms": s["choose_plain_ms_mean"],
+            "gate_rows": int(info.get("gate_rows", 0)),
             "weights": "paper_2301_10841_amd/weights/chooser.npz"}
 
 

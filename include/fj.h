@@ -450,10 +450,14 @@ void fj_mlp_free(fj_mlp *m);
    predicted time, unless it beats the plain plan (candidate 0) by less than
    `margin` in the model's output units, or q has more atoms than the
    features describe (6), or m is NULL: then the plain converted plan is
-   returned.  *chosen (host, nullable) receives the candidate index, scores
-   (host, nullable, FJ_CAND_MAX floats) the predictions.  Synchronizes. */
+   returned.  A query whose atoms hold fewer than gate_rows rows in all (by
+   the sketches) gets the plain plan without enumeration or scoring: where
+   every plan is fast, choosing costs more than it can gain (0: no gate).
+   *chosen (host, nullable) receives the candidate index (0 when gated),
+   scores (host, nullable, FJ_CAND_MAX floats) the predictions (untouched
+   when gated).  Synchronizes when it scores. */
 fj_status fj_choose_plan(fj_ctx *ctx, fj_mlp *m, const fj_query *q, const fj_sketch *sk, float margin,
-                         fj_plan **out, int32_t *chosen, float *scores);
+                         uint64_t gate_rows, fj_plan **out, int32_t *chosen, float *scores);
 
 #ifdef __cplusplus
 }

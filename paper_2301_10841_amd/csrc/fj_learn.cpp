@@ -653,11 +653,29 @@ fj_status fj_candidate_plan(const fj_query *q, const fj_candidate *c, fj_plan **
 }
 
 fj_status fj_choose_plan(fj_ctx *ctx, fj_mlp *m, const fj_query *q, const fj_sketch *sk, float margin,
-                         fj_plan **out, int32_t *chosen, float *scores) {
+                         uint64_t gate_rows, fj_plan **out, int32_t *chosen, float *scores) {
     if (!ctx || !out) return set_error(FJ_ERR_ARG, "null argument");
     FJ_TRY(check_sketches(q, sk));
     *out = nullptr;
     if (m && m->D != FJ_FEATURES) return set_error(FJ_ERR_ARG, "the perceptron's input is not FJ_FEATURES wide");
+    uint64_t rows = 0;
+    for (int a = 0; a < q->natoms; a++) rows += (uint64_t)std::max<int64_t>(sk[a].rows, 0);
+    if (rows < gate_rows) {
+        // the plain plan alone: the greedy order, converted and factored
+        std::string err;
+        FJ_TRY(fj::check_query(*q, err) == FJ_OK ? FJ_OK : set_error(FJ_ERR_ARG, err));
+        std::vector<int> ord;
+        greedy(*q, sk, -1, ord);
+        fj_plan *p = new fj_plan();
+        fj_status st = fj::plan_from_binary(*q, ord.data(), (int)ord.size(), true, p, err);
+        if (st != FJ_OK) {
+            delete p;
+            return set_error(st, err);
+        }
+        if (chosen) *chosen = 0;
+        *out = p;
+        return FJ_OK;
+    }
     Candidates C;
     FJ_TRY(enumerate(*q, sk, FJ_CAND_MAX, C, true));
     const int nc = (int)C.c.size();

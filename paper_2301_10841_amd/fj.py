@@ -192,7 +192,7 @@ def lib():
         L.fj_mlp_train_step.argtypes = [vp, vp, vp, C.c_int32, C.c_float, vp]
         L.fj_mlp_free.argtypes = [vp]
         L.fj_mlp_free.restype = None
-        L.fj_choose_plan.argtypes = [vp, vp, P(QueryS), vp, C.c_float, P(vp), P(C.c_int32), vp]
+        L.fj_choose_plan.argtypes = [vp, vp, P(QueryS), vp, C.c_float, C.c_uint64, P(vp), P(C.c_int32), vp]
         for name in ("fj_ctx_create", "fj_timings", "fj_timings_reset", "fj_plan_from_binary",
                      "fj_plan_from_nodes", "fj_plan_get", "fj_filter_lt", "fj_filter_lt_batch", "fj_build_colt",
                      "fj_colt_rebuild", "fj_colt_rebuild_many", "fj_execute", "fj_execute_factorized",
@@ -429,14 +429,15 @@ class Context:
         _check(lib().fj_sketch_relation(self.h, C.byref(rel), C.byref(sk)))
         return sk
 
-    def choose_plan(self, q: QueryS, sketches: Sequence[Sketch], mlp: Optional["Mlp"], margin: float = 0.0):
+    def choose_plan(self, q: QueryS, sketches: Sequence[Sketch], mlp: Optional["Mlp"], margin: float = 0.0,
+                    gate_rows: int = 0):
         """Returns (Plan, chosen candidate index, scores or None)."""
         arr = _sketch_array(sketches)
         h = C.c_void_p()
         chosen = C.c_int32(0)
         scores = (C.c_float * CAND_MAX)()
         _check(lib().fj_choose_plan(self.h, mlp.h if mlp is not None else None, C.byref(q), arr,
-                                    float(margin), C.byref(h), C.byref(chosen), scores))
+                                    float(margin), int(gate_rows), C.byref(h), C.byref(chosen), scores))
         return Plan(h.value, q), int(chosen.value), [float(x) for x in scores]
 
 

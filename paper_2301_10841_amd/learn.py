@@ -145,7 +145,8 @@ def collect(ctx, supply: QuerySupply, seed: int, n: int, reps: int = 5, max_rows
         if len(counts) != 1:
             raise RuntimeError(f"{tag} query {qi}: candidate plans disagree on the count: {counts}")
         qinfo.append({"kind": dq.kind, "ncand": len(cands), "count": counts.pop(),
-                      "rows": [r.nrows for r in dq.relations]})
+                      "rows": [r.nrows for r in dq.relations],
+                      "atom_rows": int(sum(dq.atom_rows(a) for a in range(len(dq.atoms))))})
         del d
         if (qi + 1) % 64 == 0 or qi + 1 == n:
             log(f"[{tag}] {qi + 1}/{n} queries, {len(secs)} timed plans, {skipped} skipped, "
@@ -204,7 +205,57 @@ def train(ctx, data: Dict, epochs: int = 60, batch: int = 256, lr: float = 1e-3,
                 f"val time ratio {vr['val_time_ratio']:.3f}")
     info = {"mu": mu, "sd": sd, "epochs": epochs, "batch": batch, "lr": lr, "train_rows": int(n),
             "val_queries": len(val_q), "history": hist, "train_seconds": time.time() - t0}
+    info["val_mask_queries"] = sorted(int(q) for q in val_q)
+    info["_pred"] = m.forward(x_all).cpu().numpy()
     return m, info
+
+
+def fit_gate(data: Dict, pred: np.ndarray, val_queries, oh_plain: float, oh_learn: float) -> Dict:
+    """The row gate of fj_choose_plan fitted on the validation queries: with
+    the choice overheads measured live (oh_plain: the plain plan alone;
+    oh_learn: enumeration, features and inference), a query with fewer than
+    G rows takes the plain plan at oh_plain and any other the predicted best
+    at oh_learn; G minimizes the validation queries' total end-to-end time."""
+    q = data["q"]
+    per = []
+    for qi in val_queries:
+        rows = np.flatnonzero(q == qi)
+        if rows.size == 0:
+            continue
+        s = data["sec"][rows]
+        k = int(np.argmin(pred[rows]))
+        per.append((data["queries"][qi]["atom_rows"], s[0] + oh_plain, s[k] + oh_learn))
+    if not per:
+        return {"gate_rows": 0}
+    per.sort()
+    cands = [0] + [r + 1 for r, _, _ in per]
+    best_g, best_t = 0, None
+    for g in cands:
+        t = sum(p if r < g else l for r, p, l in per)
+        if best_t is None or t < best_t:
+            best_g, best_t = g, t
+    t0 = sum(l for _, _, l in per)
+    return {"gate_rows": int(best_g), "val_total_gated_s": best_t, "val_total_ungated_s": t0,
+            "oh_plain_s": oh_plain, "oh_learn_s": oh_learn, "val_queries": len(per)}
+
+
+def choice_overheads(ctx, m, supply, seed: int, n: int, reps: int, max_rows: int):
+    """Median seconds of the plain choice and of the ungated learned choice
+    over n queries (sketches computed beforehand, as a catalog's)."""
+    from . import fj, runner
+    tp, tl = [], []
+    for dq in supply.queries(seed, n, max_rows):
+        d = runner.DeviceQuery(ctx, dq)
+        sks = d.sketches()
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fj.plan_from_binary(d.q, fj.greedy_order(d.q, sks), True)
+            tp.append(time.perf_counter() - t0)
+            t0 = time.perf_counter()
+            d.choose(m, sks)
+            tl.append(time.perf_counter() - t0)
+        del d
+    return statistics.median(tp), statistics.median(tl)
 
 
 def selection_quality(data: Dict, pred: np.ndarray, mask: np.ndarray) -> Dict:
@@ -243,7 +294,8 @@ def load(ctx, path: str = DEFAULT_WEIGHTS):
 # -------------------------------------------------------------- evaluation
 
 def evaluate(ctx, m, supply: QuerySupply, seed: int, n: int, reps: int = 5, margin: float = 0.0,
-             max_rows: int = 2_000_000, tag: str = "heldout", out_npz: Optional[str] = None):
+             max_rows: int = 2_000_000, tag: str = "heldout", out_npz: Optional[str] = None,
+             gate_rows: int = 0):
     """Per held-out query: every candidate timed (root builds + join, median
     of reps), the choice overheads of the plain and the learned choosers
     timed live (median of reps), and the learned chooser's pick.  End-to-end
@@ -275,9 +327,10 @@ def evaluate(ctx, m, supply: QuerySupply, seed: int, n: int, reps: int = 5, marg
             fj.plan_from_binary(d.q, fj.greedy_order(d.q, sks), True)
             tc_plain.append(time.perf_counter() - t0)
             t0 = time.perf_counter()
-            _, k, _ = d.choose(m, sks, margin)
+            _, k, _ = d.choose(m, sks, margin, gate_rows)
             tc_learn.append(time.perf_counter() - t0)
         rows.append({"kind": dq.kind, "chosen": k, "ncand": len(cands), "count": counts.pop(),
+                     "atom_rows": int(sum(dq.atom_rows(a) for a in range(len(dq.atoms)))),
                      "choose_plain_s": statistics.median(tc_plain), "choose_learned_s": statistics.median(tc_learn),
                      "run_plain_s": times[0], "run_learned_s": times[k], "best_s": min(times)})
         for ci in range(len(cands)):
@@ -351,13 +404,20 @@ def main(argv=None):
             data = collect(ctx, supply, train_seed, args.train, args.reps, args.max_rows,
                            checkpoint=os.path.join(args.out, "train_data.npz"))
             m, info = train(ctx, data, epochs=args.epochs)
+            pred = info.pop("_pred")
+            val_queries = info.pop("val_mask_queries")
+            oh_p, oh_l = choice_overheads(ctx, m, supply, datagen.seed_for(5, 4), 32, args.reps, args.max_rows)
+            info["gate"] = fit_gate(data, pred, val_queries, oh_p, oh_l)
             info.update({"train_queries": args.train, "train_seed": train_seed, "features": fj.FEATURES,
-                         "hidden": HIDDEN, "target": "standardized ln(microseconds)"})
+                         "hidden": HIDDEN, "target": "standardized ln(microseconds)",
+                         "gate_rows": info["gate"]["gate_rows"]})
+            log(f"gate: {info['gate']}")
             save(m, info, os.path.join(args.out, "chooser.npz"))
         report["train"] = {k: v for k, v in info.items() if k != "history"}
         report["train_history"] = info.get("history")
         rows = evaluate(ctx, m, supply, held_seed, args.heldout, args.reps, args.margin, args.max_rows,
-                        out_npz=os.path.join(args.out, "heldout_data.npz"))
+                        out_npz=os.path.join(args.out, "heldout_data.npz"),
+                        gate_rows=int(info.get("gate_rows", 0)))
         report["heldout"] = summarize(rows)
         with open(os.path.join(args.out, "heldout_rows.json"), "w") as f:
             json.dump(rows, f)

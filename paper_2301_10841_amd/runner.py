@@ -71,9 +71,9 @@ class DeviceQuery:
     def candidate_plan(self, cand) -> fj.Plan:
         return fj.candidate_plan(self.q, cand)
 
-    def choose(self, mlp, sketches, margin: float = 0.0):
+    def choose(self, mlp, sketches, margin: float = 0.0, gate_rows: int = 0):
         """(plan, candidate index, scores) chosen by the learned chooser."""
-        return self.ctx.choose_plan(self.q, sketches, mlp, margin)
+        return self.ctx.choose_plan(self.q, sketches, mlp, margin, gate_rows)
 
     def build(self, plan: fj.Plan):
         return [self.ctx.build_colt(self.q, plan, a, self.atom_cols(a), self.sel[a], self.nsel[a])

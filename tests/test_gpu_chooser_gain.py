@@ -50,7 +50,7 @@ def test_learned_choice_beats_plain_plan(env):
             p_plain = fj.plan_from_binary(d.q, fj.greedy_order(d.q, sks), True)
             tp.append(time.perf_counter() - t0)
             t0 = time.perf_counter()
-            p_learn, k, _ = d.choose(m, sks)
+            p_learn, k, _ = d.choose(m, sks, gate_rows=int(info.get("gate_rows", 0)))
             tl.append(time.perf_counter() - t0)
         s_plain, c_plain = learn.time_plan(ctx, d, p_plain, 5)
         if k == 0:

@@ -193,4 +193,11 @@ def test_choice_and_fallback(env):
     # a margin no prediction can reach keeps the plain plan
     p, k, _ = d.choose(m, sks, margin=1e30)
     assert k == 0 and p.nodes() == plain.nodes()
+    # a query below the row gate gets the plain plan unscored; at the gate
+    # it is scored as without one
+    rows = sum(int(s.rows) for s in sks)
+    p, k, _ = d.choose(m, sks, gate_rows=rows + 1)
+    assert k == 0 and p.nodes() == plain.nodes()
+    p, k2, _ = d.choose(m, sks, gate_rows=rows)
+    assert scores[k2] == min(scores[:len(cands)])
     m.free()
