@@ -6,7 +6,7 @@ line per scale: ``S edges count``.  The count is the closed form of
 ``oracle.closed`` computed in row blocks (A^2 is too large to hold at once
 beyond S = 16).  Only ``datagen`` and ``oracle`` are used.
 
-    python tests/golden/make_rmat_cycle4.py [16 18]
+    python tests/golden/make_rmat_cycle4.py [16 18 20]
 """
 
 import os
@@ -27,12 +27,12 @@ def edges_for(scale):
 
 
 def main():
-    scales = [int(a) for a in sys.argv[1:]] or [16, 18]
+    scales = [int(a) for a in sys.argv[1:]] or [16, 18, 20]
     lines = []
     for S in scales:
         t = time.perf_counter()
         src, dst = datagen.rmat_edges(datagen.seed_for(3, 1), S, edges_for(S))
-        n = closed.cycle4_count_blocked(src, dst, 1 << max(10, S - 4))
+        n = closed.cycle4_count_blocked(src, dst, 1 << max(10, S - 8))
         print(f"scale {S}: {src.size} edges, {n} 4-cycles in {time.perf_counter() - t:.0f}s", flush=True)
         lines.append(f"{S} {src.size} {n}\n")
     with open(OUT, "w") as f:
