@@ -49,7 +49,7 @@ def main():
     ap.add_argument("--workload", choices=("star", "batch", "rmat", "bushy", "ablation", "factorized"), default="star")
     ap.add_argument("--rmat-scale", type=int, default=22)
     ap.add_argument("--rmat-edges", type=int, default=50_000_000)
-    ap.add_argument("--cycle4-scale", type=int, default=16, help="rmat workload: scale of the 4-cycle run")
+    ap.add_argument("--cycle4-scale", type=int, default=20, help="rmat workload: scale of the 4-cycle run")
     ap.add_argument("--rmat-cache", default=None, help="rmat workload: directory keeping the drawn graph")
     ap.add_argument("--queries", type=int, default=256, help="batch workload: number of queries")
     ap.add_argument("--tune-queries", type=int, default=48, help="batch workload: calibration batch size")
@@ -58,6 +58,8 @@ def main():
                          "triangle steps only (profiling)")
     ap.add_argument("--chooser-queries", type=int, default=48,
                     help="star workload: held-out queries for the learned-vs-plain leg (0: skip)")
+    ap.add_argument("--no-filter", action="store_true",
+                    help="star: the node-0 scan without the first lookup's key filter (for comparison)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -96,7 +98,7 @@ def main():
     n_fact = dq.relations[0].nrows
     log(f"generated star workload in {time.time() - t0:.1f}s")
 
-    ctx = fj.Context(0, timing=2)   # events around the node-0 probe only
+    ctx = fj.Context(0, timing=2, no_filter=args.no_filter)   # events around the node-0 probe only
     d = runner.DeviceQuery(ctx, dq)
     plan = d.plan_binary([0, 1, 2, 3, 4], True)
     colts = d.build(plan)
@@ -109,6 +111,12 @@ def main():
 
     for _ in range(args.warmup):
         step()
+    # which node-0 kernel runs: the key filter's count says
+    d.apply_filters()
+    d.rebuild(colts)
+    _, _, st0 = ctx.execute(d.q, plan, colts, out=out, stats=True)
+    filtered = int(st0.filtered)
+    probe0_lookups = int(st0.per_node()[0]["probe"])
     torch.cuda.synchronize()
     ctx.timings_reset()
     torch.cuda.synchronize()
@@ -219,7 +227,11 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes,
                      "traffic_note": traffic_note,
-                     "kernel": "k_scan_probe (node 0)", "avg_launch_ms": avg_probe0_ms,
+                     "kernel": ("k_scan_filter + k_scan_rounds (node 0 in two launches: the first lookup's "
+                                "key filter in LDS, then the later lookups over the rows that pass it)" if filtered
+                                else "k_scan_probe (node 0)"),
+                     "first_lookup_filtered": filtered, "node0_lookups": probe0_lookups,
+                     "avg_launch_ms": avg_probe0_ms,
                      "launches": "cold: a 512 MiB buffer rewritten before each step",
                      "alg_bytes_per_launch": alg_bytes,
                      "warm": {"avg_launch_ms": warm_probe0_ms, "achieved": achieved_warm,
@@ -889,7 +901,17 @@ def bench_rmat(args):
     cyc_s = time.perf_counter() - t2
     for c in c4:
         c.free()
-    want4 = trace_power4(s4, d4)
+    # the check: trace(A^4), stored for the scales whose closed form takes
+    # the CPU minutes (tests/golden/make_rmat_cycle4.py), else computed here
+    want4, check4 = None, "trace(A^4)"
+    if args.seed_rep == 0:
+        gold = os.path.join(ROOT, "tests", "golden", "rmat_cycle4_counts.txt")
+        for ln in open(gold):
+            f = ln.split()
+            if f and not ln.startswith("#") and int(f[0]) == args.cycle4_scale and int(f[1]) == s4.size:
+                want4, check4 = int(f[2]), "trace(A^4), stored by tests/golden/make_rmat_cycle4.py"
+    if want4 is None:
+        want4 = trace_power4(s4, d4)
     assert cyc == want4, (cyc, want4)
     probes4 = sum(n["probe"] for n in st4.per_node())
     res = {
@@ -912,7 +934,7 @@ def bench_rmat(args):
         "converted_plan_s": conv_s,
         "sampled_x": int(xs.size), "sampled_triangles": want,
         "cycle4": {"scale": args.cycle4_scale, "edges": int(s4.size), "count": cyc, "seconds": cyc_s,
-                   "probes": probes4, "probes_per_s": probes4 / cyc_s, "check": "trace(A^4)"},
+                   "probes": probes4, "probes_per_s": probes4 / cyc_s, "check": check4},
         "cpu_baseline": cpu,
     }
     ctx.close()

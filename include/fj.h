@@ -102,7 +102,10 @@ typedef struct {
                             built ahead, inner levels lazily; 2: simple trie: every
                             level of every COLT is built when it is (re)built.
                             Batches take 0 only. */
-    int32_t reserved[2];
+    int32_t no_filter;   /* 1: the first-node scan never uses a root map's key filter
+                            (the membership filter a range-by-range root build
+                            writes beside its map) [0] */
+    int32_t reserved[1];
 } fj_options;
 
 /* Per-execution counters (fj_execute fills them when stats is non-null).
@@ -118,6 +121,8 @@ typedef struct {
     int32_t nnodes;
     uint64_t tiles;                      /* probe launches */
     uint64_t deferred;                   /* tuples re-run after a lazy force */
+    uint64_t filtered;                   /* first-node probes settled as misses by the
+                                            first lookup's key filter (counted in probe) */
 } fj_stats;
 
 /* Kernel-class timings accumulated since the last fj_timings_reset. */

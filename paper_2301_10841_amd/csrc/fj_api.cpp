@@ -109,6 +109,7 @@ struct fj_ctx {
     DevBuf scanb;                   // block sums for scans
     DevBuf desc;                    // node + emit descriptors
     DevBuf emitbuf;                 // emit counts and starts
+    DevBuf l0buf;                   // a two-launch first node's list of first-lookup hits
     DevBuf chunkb;                  // per-block binding bounds of a probe launch
     DevBuf sketch;                  // column sketch table and results
     struct ColtGroup *group = nullptr;  // fj_colt_rebuild_many's descriptors and scratch
@@ -210,6 +211,7 @@ struct fj_colt {
     bool root_built = false;
     bool root_lazy = false;  // unbuilt root that a probe may force (its map is allocated)
     bool root_part = false;  // root map (KM_K32) built range by range by the grouped path
+    uint32_t *bloom_buf = nullptr;   // the root map's key filter (kBloomWords), if it may have one
     int lev_nk[fj::kMaxLevels] = {0};
     int lev_var[fj::kMaxLevels][FJ_MAX_COLS] = {{0}};
     LevelDev lev[fj::kMaxLevels + 1];
@@ -264,6 +266,7 @@ fj_status colt_alloc(fj_colt *t, T **p, size_t n) {
 // Device buffers for every level; contents are initialised by colt_reset.
 fj_status colt_allocate(fj_colt *t) {
     const size_t n = std::max<uint32_t>(t->cap_rows, 1);
+    t->bloom_buf = nullptr;
     for (int l = 0; l <= t->nlev; l++) {
         LevelDev &L = t->lev[l];
         memset(&L, 0, sizeof(L));
@@ -306,6 +309,7 @@ fj_status colt_allocate(fj_colt *t) {
             FJ_TRY(colt_alloc(t, &tb, L.mode == fj::KM_K32 ? fj::k32_table_words(cap) * sizeof(uint32_t)
                                                            : (cap + 1) * slot_bytes(L.mode)));
             L.table = tb;
+            if (l == 0 && L.mode == fj::KM_K32 && t->root_built) FJ_TRY(colt_alloc(t, &t->bloom_buf, fj::kBloomWords));
         }
     }
     return FJ_OK;
@@ -463,6 +467,19 @@ static fj_status colt_size(fj_colt *t) {
         const u64 cap = R.mask + 1, psz = std::min<u64>(cap, fj::kK32Part);
         t->root_part = t->root_built && t->nroot > 0 && t->nlev >= 1 && R.table && R.mode == fj::KM_K32 &&
                        cap / psz <= fj::kMaxParts;
+        // its key filter: at most kBloomWords words of 2^s buckets each,
+        // and at least one word per build range
+        LevelDev &Rw = t->lev[0];
+        Rw.bloom = nullptr;
+        Rw.bloom_shift = 0;
+        if (t->root_part && t->bloom_buf) {
+            uint32_t sh = 0;
+            while (((cap / fj::kK32Bucket) >> sh) > fj::kBloomWords) sh++;
+            if (((psz / fj::kK32Bucket) >> sh) >= 1) {
+                Rw.bloom = t->bloom_buf;
+                Rw.bloom_shift = sh;
+            }
+        }
     }
     if (rows == t->sized_rows && part_was == t->root_part) return FJ_OK;   // as the last sizing left them
     const fj::FillList old = t->fill_h;
@@ -970,6 +987,7 @@ void fj_ctx_destroy(fj_ctx *c) {
     c->scanb.release();
     c->desc.release();
     c->emitbuf.release();
+    c->l0buf.release();
     c->chunkb.release();
     c->sketch.release();
     if (c->sketch_h) hipHostFree(c->sketch_h);
@@ -1656,6 +1674,29 @@ fj_status exec_scan_node(Exec &x, int cover_sub, u64 T, uint32_t) {
         L.hcol = -1;
         for (size_t h = 0; h < LN.in_hatom.size(); h++)
             if (LN.in_hatom[h] == a) L.hcol = (int)h;
+        L.bloom = nullptr;
+        L.bloom_shift = 0;
+        L.bloom_words = 0;
+        if (sl.nl == 1 && !c->opt.no_filter && L.mode == fj::KM_K32 && t->lev[0].bloom) {
+            // the first lookup's key filter, when its words hold few keys
+            // (two bits each of 32: at most 12 keys a word on average)
+            const u64 words = (L.mask + 1) >> (2 + t->lev[0].bloom_shift);
+            if (words >= 1 && words <= fj::kBloomWords && (u64)t->nroot <= 12 * words) {
+                L.bloom = t->lev[0].bloom;
+                L.bloom_shift = t->lev[0].bloom_shift;
+                L.bloom_words = (uint32_t)words;
+            }
+        }
+    }
+    if (sl.nl >= 1 && sl.lk[0].bloom) {
+        // the list of first-lookup hits the filter pass hands to the rounds
+        const u64 ent = fj::scan_list_entries(std::min<u64>(x.C, T));
+        const size_t rb = align256(sizeof(uint32_t) * ent);
+        FJ_TRY(c->l0buf.ensure(2 * rb + sizeof(uint32_t) * fj::kScanListGroups * fj::kScanListWaves, c->stream));
+        sl.l0_row = c->l0buf.as<uint32_t>();
+        sl.l0_key = c->l0buf.as<uint32_t>(rb);
+        sl.l0_cnt = c->l0buf.as<uint32_t>(2 * rb);
+        sl.l0_cap = ent;
     }
     sl.nout = (int)LN.in_var.size();
     for (int j = 0; j < sl.nout; j++) sl.out_col[j] = cover_col(LN.in_var[j]);
@@ -1978,6 +2019,7 @@ static fj_status execute_impl(fj_ctx *c, const fj_query *q, const fj_plan *p, fj
             stats->hit[k] = c->status_h->hit[k];
         }
         if (x.tail_from > 0) stats->survivors[x.tail_from - 1] = 0;
+        stats->filtered = c->status_h->filtered;
     }
     return (x.out && *count > x.cap) ? FJ_TRUNCATED : FJ_OK;
 }

@@ -53,6 +53,12 @@ __host__ __device__ inline unsigned long long k32_next(unsigned long long b, uns
     const unsigned long long pm = k32_part_mask(mask);
     return (b & ~pm) | ((b + kK32Bucket) & pm);
 }
+// A KM_K32 root built range by range also gets a membership filter of its
+// keys: each key sets two bits (from its hash's top ten bits) of one 32-bit
+// word, the word being its home bucket shifted right by the filter's shift,
+// so the keys of one build range set bits of that range's words only.  At
+// most kBloomWords words (64 KB), the size one workgroup keeps in LDS.
+constexpr uint32_t kBloomWords = 16384;
 struct alignas(16) Slot64 { unsigned long long key; uint32_t val; uint32_t pad; };
 struct alignas(16) SlotRep { unsigned long long hr; uint32_t val; uint32_t pad; };  // hr = row << 32 | handle
 
@@ -79,6 +85,9 @@ struct LevelDev {
     unsigned long long nslots;  // hash slots including the reserved one (0: no map)
     int local;           // per-trie maps (levels below the root, KM_K64 / KM_REP): the trie at
                          // position p with len[p] offsets owns slots [2p, 2p + 2 len[p])
+    uint32_t *bloom;     // KM_K32 root built range by range: its keys' filter (written by the
+                         // build), or null
+    uint32_t bloom_shift;   // filter word of a key = its home bucket >> bloom_shift
 };
 
 struct SubDev {
@@ -150,6 +159,9 @@ struct ScanLookup {
     const uint32_t *clen;  // child level lengths
     uint32_t cnpos;        // child level positions
     int hcol;              // output handle column of this atom, or -1
+    const uint32_t *bloom; // the map's key filter, used by the first lookup, or null
+    uint32_t bloom_shift;
+    uint32_t bloom_words;  // words of the filter in use
 };
 
 // Batched counting of plans that probe only root maps (see fj_batch_create).
@@ -296,6 +308,7 @@ struct StatusDev {
     unsigned long long emit_rows;  // the current emit's rows (within the output capacity)
     unsigned long long probe[FJ_MAX_NODES];
     unsigned long long hit[FJ_MAX_NODES];
+    unsigned long long filtered;   // first-lookup probes the key filter settled
     uint32_t fq_n[FJ_MAX_ATOMS * kMaxLevels];  // force-queue lengths per (atom, level)
     uint32_t pending;              // entries whose cover had to be forced first
     uint32_t total32;              // 32-bit scan totals

@@ -66,6 +66,13 @@ template <typename SlotT> __device__ __forceinline__ u64 bucket_start(u64 h, u64
 }
 __device__ __forceinline__ u64 k32_bucket(uint32_t h, u64 mask) { return (h & mask) & ~(u64)(kK32Bucket - 1); }
 
+// A KM_K32 key's membership-filter bits (two, from its hash's top ten bits;
+// the bucket takes the low bits) and filter word (its home bucket, shifted).
+__device__ __forceinline__ uint32_t bloom_bits(uint32_t h) { return (1u << (h >> 27)) | (1u << ((h >> 22) & 31u)); }
+__device__ __forceinline__ uint32_t bloom_word(uint32_t h, u64 mask, uint32_t shift) {
+    return (uint32_t)(k32_bucket(h, mask) >> (2 + shift));
+}
+
 __device__ __forceinline__ u64 pack64(const LevelDev &L, const Key &k) {
     // root with two key columns: (v0, v1); below the root: (handle, v0)
     return L.nk == 2 ? ((u64)(uint32_t)k.v[0] << 32) | (uint32_t)k.v[1]
@@ -1075,6 +1082,7 @@ constexpr int kPartBuildThreads = 1024;
 __global__ void __launch_bounds__(kPartBuildThreads) k_part_build(PartArgs a) {
     __shared__ uint32_t keys[kK32Part];
     __shared__ uint32_t cnt[kK32Part];
+    __shared__ uint32_t fw[kK32Part / kK32Bucket];   // the range's filter words
     __shared__ uint32_t red[17];
     __shared__ uint32_t emp;
     StatusDev *status = a.status;
@@ -1086,6 +1094,11 @@ __global__ void __launch_bounds__(kPartBuildThreads) k_part_build(PartArgs a) {
     const uint32_t n = 1u << m.plog;                  // slots of the range
     const u64 s0 = (u64)lp << m.plog;                 // its first slot in the map
     for (uint32_t s = threadIdx.x; s < n; s += kPartBuildThreads) { keys[s] = kEmpty32; cnt[s] = 0; }
+    // the filter's words of this range (the host keeps at least one per range)
+    const uint32_t fsh = 2 + f.L.bloom_shift;
+    const uint32_t nfw = f.L.bloom ? n >> fsh : 0u;
+    const uint32_t fw0 = (uint32_t)(s0 >> fsh);
+    for (uint32_t w = threadIdx.x; w < nfw; w += kPartBuildThreads) fw[w] = 0;
     if (threadIdx.x == 0) emp = 0;
     __syncthreads();
     const uint32_t i0 = a.pstart[P], i1 = a.pstart[P + 1];
@@ -1130,6 +1143,11 @@ __global__ void __launch_bounds__(kPartBuildThreads) k_part_build(PartArgs a) {
         const u64 w = k32_key_word(s0 + s);
         T[w] = keys[s];
         T[w + 4] = c ? base + pre : 0u;
+        if (nfw && keys[s] != kEmpty32) {
+            const uint32_t h = mix32(keys[s]);
+            const uint32_t fi = bloom_word(h, f.L.mask, f.L.bloom_shift) - fw0;
+            if (CK(fi < nfw)) atomicOr(&fw[fi], bloom_bits(h));
+        }
         sc[s] = c;
         if (c && CK((u64)base + pre < f.C.npos)) f.C.len[base + pre] = c;
         cnt[s] = base + pre;                          // from here on: the slot's scatter cursor
@@ -1148,6 +1166,7 @@ __global__ void __launch_bounds__(kPartBuildThreads) k_part_build(PartArgs a) {
         emp = base;                                   // the empty marker's scatter cursor
     }
     __syncthreads();
+    for (uint32_t w = threadIdx.x; w < nfw; w += kPartBuildThreads) f.L.bloom[fw0 + w] = fw[w];
     for (uint32_t i = i0 + threadIdx.x; i < i1w; i += kPartBuildThreads) {
         const bool live = i < i1;
         const uint32_t key = live ? a.pkey[i] : kEmpty32;
@@ -1603,6 +1622,26 @@ constexpr int kRoundRows = FJ_ROUND_ROWS;   // batch entries per thread in fligh
 static_assert(kBatch <= 65536, "batch entries are 16-bit");
 constexpr int kScanMaxLookups = 8;
 
+// The filter pass of a two-launch first node (k_scan_filter, below): tiles
+// of kFiltRows rows per thread of one kFiltThreads workgroup per CU, dealt
+// round robin; each wave writes its first-lookup hits to its own region of
+// the list, which holds the rows the wave sees (kFiltRows x 64 per tile).
+constexpr int kFiltThreads = 1024;
+constexpr int kFiltRows = 8;
+constexpr int kFiltTile = kFiltThreads * kFiltRows;
+constexpr int kFiltWaves = kFiltThreads / 64;
+constexpr int kFiltWaveTile = kFiltRows * 64;
+static_assert(kFiltWaves == kScanListWaves, "list counters per filter-pass workgroup");
+// Region of wave w of workgroup g (its first entry and capacity).
+__host__ __device__ inline unsigned long long list_region(uint32_t g, uint32_t w, uint32_t ntiles, uint32_t G,
+                                                          uint32_t &cap) {
+    const unsigned long long full = ntiles / G, rem = ntiles % G;
+    const unsigned long long tiles = full + (g < rem ? 1u : 0u);
+    cap = (uint32_t)(tiles * kFiltWaveTile);
+    return ((unsigned long long)g * full + (g < rem ? g : rem)) * (unsigned long long)kFiltTile +
+           (unsigned long long)w * tiles * kFiltWaveTile;
+}
+
 struct ScanArgs {
     const int32_t *cols[FJ_MAX_COLS];
     int ncols;
@@ -1633,6 +1672,12 @@ struct ScanArgs {
     int direct;
     const EmitDev *ed;        // head mapping, tails and output of the execution
     u64 cap;                  // output capacity in rows
+    // two-launch first node: the filter pass writes the rows that pass the
+    // first lookup's filter, and their keys, of wave w of workgroup g to its
+    // region of l0_row / l0_key and their number to l0_cnt[g * kFiltWaves +
+    // w]; k_scan_rounds probes them (l0_per consecutive regions a workgroup)
+    uint32_t *l0_row, *l0_key, *l0_cnt;
+    uint32_t l0_groups, l0_per;
 };
 
 // One row's probe of a root map in two steps, so that several rows' loads
@@ -1753,12 +1798,13 @@ __device__ __forceinline__ uint32_t list_slot(bool pred, uint32_t *cnt) {
 // Rows of a tile taken with positions strided by the workgroup size (a
 // ragged tile, or a selection), and which are live; dead ones read row 0
 // (the launch has nrows >= 1).
+template <int NT, int ROWS>
 __device__ __forceinline__ void round0_rows(const ScanArgs &a, uint32_t tile0, uint32_t tn, uint32_t *row,
                                             bool *alive) {
     StatusDev *status = a.status;
 #pragma unroll
-    for (int r = 0; r < kTileRows; r++) {
-        const uint32_t p = r * 256 + threadIdx.x;
+    for (int r = 0; r < ROWS; r++) {
+        const uint32_t p = r * NT + threadIdx.x;
         alive[r] = p < tn;
         row[r] = tile_row(a, tile0, alive[r] ? p : 0u);   // position 0 of the tile exists
         alive[r] = alive[r] && CK(row[r] < a.nrows);
@@ -1770,10 +1816,11 @@ __device__ __forceinline__ void round0_rows(const ScanArgs &a, uint32_t tile0, u
 // rows and, per lookup, their hits) and the lists of batch entries that
 // passed each later round.
 struct ScanLds {
-    uint32_t *bh;       // bh[j * kBatch + b]: lookup j's hit for batch entry b (dynamic LDS)
+    uint32_t *bh;       // bh[j * nb + b]: lookup j's hit for batch entry b (dynamic LDS)
     uint32_t *brow;     // brow[b]: the entry's row of the cover relation
-    uint16_t *lists;    // two lists of kBatch: entries alive after rounds 1, 2, ... (alternating)
+    uint16_t *lists;    // two lists of nb: entries alive after rounds 1, 2, ... (alternating)
     uint32_t *cnt;      // cnt[0]: batch entries; cnt[j]: entries alive after round j
+    uint32_t nb;        // batch capacity in entries
 };
 
 // Direct emit of one chunk of final bindings, wave by wave (the thread's
@@ -1783,8 +1830,10 @@ struct ScanLds {
 // wave's rows in the output, then the wave writes them together, each row
 // finding its lane by a search over the lanes' starts and its tail rows by
 // mixed radix.  No LDS, so the kernel's occupancy is unchanged.
+constexpr int kEmitFastTails = 4;   // up to this many tails, a row's loads are issued together
+template <bool FAST>
 __device__ __forceinline__ void scan_emit_wave(const ScanArgs &a, const uint32_t *bh, const uint32_t *brow,
-                                            const uint16_t *fin, uint32_t i, uint32_t nf, u64 e) {
+                                            uint32_t nbs, const uint16_t *fin, uint32_t i, uint32_t nf, u64 e) {
     StatusDev *status = a.status;
     const EmitDev &d = *a.ed;
     const int lane = __lane_id();
@@ -1819,11 +1868,51 @@ __device__ __forceinline__ void scan_emit_wave(const ScanArgs &a, const uint32_t
         u64 idx = r - ex_t;
         uint32_t rows[FJ_MAX_NODES];
         bool ok = true;
+        if (FAST && d.ntail <= kEmitFastTails) {
+            // few tails: each tail's length, then its row, all loaded before
+            // any check (a check that reports keeps later loads behind it)
+            uint32_t tp[kEmitFastTails], tn[kEmitFastTails], tps[kEmitFastTails];
+            bool in = true;
+#pragma unroll
+            for (int q = 0; q < kEmitFastTails; q++) {
+                tp[q] = 0;
+                tn[q] = 1;
+                if (q >= d.ntail) continue;
+                tn[q] = a.tail_root_len[q];
+                if (a.tail_lk[q] >= 0) {
+                    tp[q] = bh[a.tail_lk[q] * nbs + eb];
+                    const bool p_in = tp[q] < d.tail[q].L.npos;
+                    tn[q] = p_in ? d.tail[q].L.len[tp[q]] : 0u;
+                    in = in && p_in;
+                }
+            }
+#pragma unroll
+            for (int q = kEmitFastTails - 1; q >= 0; q--) {
+                tps[q] = 0;
+                if (q >= d.ntail) continue;
+                in = in && tn[q] > 0;
+                const uint32_t len = tn[q] > 0 ? tn[q] : 1u;
+                tps[q] = tp[q] + (uint32_t)(idx % len);
+                idx /= len;
+                const TailDev &T = d.tail[q];
+                in = in && (tps[q] < T.L.npos || (T.level == 0 && tps[q] < T.root_len));
+            }
+#pragma unroll
+            for (int q = 0; q < kEmitFastTails; q++) {
+                if (q >= d.ntail) continue;
+                const TailDev &T = d.tail[q];
+                const bool kv = T.nk == 1 && T.L.kv;
+                const uint32_t x = in ? (kv ? (uint32_t)T.L.kv[tps[q]] : (T.L.offs ? T.L.offs[tps[q]] : tps[q])) : 0u;
+                rows[q] = x;
+                in = in && (kv || x < T.L.nrows);
+            }
+            ok = CK(in);
+        } else {
         for (int q = d.ntail - 1; q >= 0 && ok; q--) {
             const TailDev &T = d.tail[q];
             uint32_t p = 0, len = a.tail_root_len[q];
             if (a.tail_lk[q] >= 0) {
-                p = bh[a.tail_lk[q] * kBatch + eb];
+                p = bh[a.tail_lk[q] * nbs + eb];
                 ok = CK(p < T.L.npos);
                 len = ok ? T.L.len[p] : 0u;
             }
@@ -1832,21 +1921,41 @@ __device__ __forceinline__ void scan_emit_wave(const ScanArgs &a, const uint32_t
             const uint32_t pos = p + (uint32_t)(idx % len);
             idx /= len;
             ok = CK(pos < T.L.npos || (T.level == 0 && pos < T.root_len));
+            if (ok && T.nk == 1 && T.L.kv) {
+                rows[q] = (uint32_t)T.L.kv[pos];   // the key kept beside the offset
+                continue;
+            }
             rows[q] = ok ? (T.L.offs ? T.L.offs[pos] : pos) : 0u;
             ok = ok && CK(rows[q] < T.L.nrows);
+        }
         }
         if (!ok) continue;
         const uint32_t crow = brow[eb];
         int32_t *dst = d.out + (base + r) * (u64)d.nhead;
-        for (int j = 0; j < d.nhead; j++) {
-            const int src = d.head_src[j];
-            if (src >= 0) {
-                dst[j] = a.cols[a.out_col[src]][crow];
-            } else {
-                const int z = -src - 1;
-                const TailDev &T = d.tail[z / FJ_MAX_COLS];
-                dst[j] = T.cols[T.kcol[z % FJ_MAX_COLS]][rows[z / FJ_MAX_COLS]];
+        // the row's values (FAST: eight columns' loads at a time before their
+        // stores; the output may alias the columns, so a store keeps the next
+        // load behind it)
+        for (int j0 = 0; j0 < d.nhead; j0 += FAST ? 8 : 1) {
+            constexpr int U = FAST ? 8 : 1;
+            int32_t v[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int j = j0 + u;
+                v[u] = 0;
+                if (j >= d.nhead) continue;
+                const int src = d.head_src[j];
+                if (src >= 0) {
+                    v[u] = a.cols[a.out_col[src]][crow];
+                } else {
+                    const int z = -src - 1;
+                    const TailDev &T = d.tail[z / FJ_MAX_COLS];
+                    v[u] = (T.nk == 1 && T.L.kv) ? (int32_t)rows[z / FJ_MAX_COLS]
+                                                 : T.cols[T.kcol[z % FJ_MAX_COLS]][rows[z / FJ_MAX_COLS]];
+                }
             }
+#pragma unroll
+            for (int u = 0; u < U; u++)
+                if (j0 + u < d.nhead) dst[j0 + u] = v[u];
         }
     }
 }
@@ -1894,31 +2003,31 @@ __device__ __forceinline__ void tile_keys(const int32_t *c, uint32_t row0, uint3
 
 // Round j >= 1: lookup L over the n batch entries the previous round left
 // (round 1: the whole batch), kRoundRows entries per thread in flight.
-template <int MODE, bool STATS>
+template <int NT, int MODE, bool STATS, int RR = kRoundRows>
 __device__ __forceinline__ void scan_round(const ScanArgs &a, const ScanLookup &L, int j, uint32_t n,
                                            const ScanLds &S, uint32_t &nprobe, uint32_t &nhit) {
     StatusDev *status = a.status;
-    const uint16_t *in = j == 1 ? nullptr : S.lists + ((j - 1) & 1) * kBatch;
-    uint16_t *out = S.lists + (j & 1) * kBatch;
+    const uint16_t *in = j == 1 ? nullptr : S.lists + ((j - 1) & 1) * S.nb;
+    uint16_t *out = S.lists + (j & 1) * S.nb;
     const int32_t *c0 = a.cols[L.kc[0]];
     const int32_t *c1 = a.cols[MODE != KM_K32 ? L.kc[1] : L.kc[0]];
-    for (uint32_t i0 = 0; i0 < n; i0 += 256 * kRoundRows) {
-        uint32_t b[kRoundRows], k0[kRoundRows], k1[kRoundRows];
-        bool live[kRoundRows];
+    for (uint32_t i0 = 0; i0 < n; i0 += NT * RR) {
+        uint32_t b[RR], k0[RR], k1[RR];
+        bool live[RR];
 #pragma unroll
-        for (int r = 0; r < kRoundRows; r++) {
-            const uint32_t i = i0 + r * 256 + threadIdx.x;
+        for (int r = 0; r < RR; r++) {
+            const uint32_t i = i0 + r * NT + threadIdx.x;
             live[r] = i < n;
             b[r] = live[r] ? (in ? in[i] : i) : 0u;   // entry 0 exists (n > 0)
             const uint32_t row = S.brow[b[r]];
             k0[r] = (uint32_t)c0[row];
             k1[r] = MODE != KM_K32 ? (uint32_t)c1[row] : 0u;
         }
-        RowProbe pr[kRoundRows];
+        RowProbe pr[RR];
 #pragma unroll
-        for (int r = 0; r < kRoundRows; r++) probe_issue<MODE>(L, k0[r], k1[r], live[r], pr[r]);
+        for (int r = 0; r < RR; r++) probe_issue<MODE>(L, k0[r], k1[r], live[r], pr[r]);
 #pragma unroll
-        for (int r = 0; r < kRoundRows; r++) {
+        for (int r = 0; r < RR; r++) {
             bool hit = false;
             if (live[r]) {
                 if (STATS) nprobe++;
@@ -1926,7 +2035,7 @@ __device__ __forceinline__ void scan_round(const ScanArgs &a, const ScanLookup &
                 hit = probe_resolve<MODE>(L, pr[r], v) && (MODE == KM_K32 || CK(v < L.cnpos));
                 if (hit) {
                     if (STATS) nhit++;
-                    S.bh[j * kBatch + b[r]] = v;
+                    S.bh[j * S.nb + b[r]] = v;
                 }
             }
             const uint32_t o = list_slot(hit, &S.cnt[j]);
@@ -1938,68 +2047,125 @@ __device__ __forceinline__ void scan_round(const ScanArgs &a, const ScanLookup &
 // Rounds 1..nl-1 over the batch, then the batch's results: counts (emit)
 // and/or frontier rows (materialize, or a node that is not the last).  Every
 // thread of the workgroup calls it; it leaves the batch empty.
-template <bool STATS>
+template <int NT, bool STATS, bool FAST = false>
 __device__ __forceinline__ void scan_flush(const ScanArgs &a, const ScanLds &S, uint32_t nb, u64 &tot,
                                            uint32_t &nprobe, uint32_t &nhit, u64 *red) {
     StatusDev *status = a.status;
     uint32_t nf = nb;
     int last = 0;
     for (int j = 1; j < a.nl && nf > 0; j++) {
-        if (a.lk[j].mode == KM_K32) scan_round<KM_K32, STATS>(a, a.lk[j], j, nf, S, nprobe, nhit);
-        else scan_round<KM_K64, STATS>(a, a.lk[j], j, nf, S, nprobe, nhit);
+        // (FAST: more entries a thread in flight, for batches flushed once)
+        constexpr int RR = FAST ? 2 * kRoundRows : kRoundRows;
+        if (a.lk[j].mode == KM_K32) scan_round<NT, KM_K32, STATS, RR>(a, a.lk[j], j, nf, S, nprobe, nhit);
+        else scan_round<NT, KM_K64, STATS, RR>(a, a.lk[j], j, nf, S, nprobe, nhit);
         __syncthreads();
         nf = S.cnt[j];
         last = j;
     }
     if (nf > 0) {
-        const uint16_t *fin = last == 0 ? nullptr : S.lists + (last & 1) * kBatch;
+        const uint16_t *fin = last == 0 ? nullptr : S.lists + (last & 1) * S.nb;
         const bool write = (!a.emit || a.materialize) && !a.direct;
         if (write) {
             if (threadIdx.x == 0) red[16] = atomicAdd(&a.status->survivors, (u64)nf);
             __syncthreads();
         }
         const u64 base = write ? red[16] - a.surv_base : 0;
-        // chunks of 256 entries, one per thread (all threads take part in
+        // chunks of NT entries, one per thread (all threads take part in
         // every chunk: the direct emit scans each chunk)
-        for (uint32_t i0 = 0; i0 < nf; i0 += 256) {
+        for (uint32_t i0 = 0; i0 < nf; i0 += NT) {
             const uint32_t i = i0 + threadIdx.x;
             const bool live = i < nf;
             const uint32_t b = live ? (fin ? fin[i] : i) : 0u;
-            // slots of KM_K32 maps become their values (the child handles)
-            bool ok = live;
-            for (int j = 0; j < a.nl && live; j++) {
-                const ScanLookup &L = a.lk[j];
-                if (L.mode != KM_K32) continue;
-                const uint32_t v = ((const uint32_t *)L.table)[k32_key_word(S.bh[j * kBatch + b]) + 4];
-                ok = ok && CK(v < L.cnpos);
-                S.bh[j * kBatch + b] = v;
-            }
-            u64 e = 0;
-            if (ok) {
-                u64 m = 1;
-                for (int j = 0; j < a.nl; j++)
-                    if (a.lk[j].child_leaf) m *= a.lk[j].clen[S.bh[j * kBatch + b]];
-                if (a.emit) {
-                    e = m;
-                    for (int q = 0; q < a.ntail; q++) {
-                        if (a.tail_lk[q] < 0) { e *= a.tail_root_len[q]; continue; }
-                        const uint32_t th = S.bh[a.tail_lk[q] * kBatch + b];
-                        if (!CK(th < a.tail_npos[q])) { e = 0; break; }
-                        e *= a.tail_len[q][th];
+            bool ok;
+            u64 e = 0, m = 1;
+            if constexpr (FAST) {
+                // slots of KM_K32 maps become their values (the child handles).
+                // Here and below every load of an entry is issued before any of
+                // its checks: a check that fails reports to the status block, so
+                // the compiler keeps later loads behind it.
+                uint32_t hv[kScanMaxLookups];
+#pragma unroll
+                for (int j = 0; j < kScanMaxLookups; j++) {
+                    hv[j] = 0;
+                    if (j < a.nl && live) {
+                        const uint32_t x = S.bh[j * S.nb + b];
+                        hv[j] = a.lk[j].mode == KM_K32 ? ((const uint32_t *)a.lk[j].table)[k32_key_word(x) + 4] : x;
                     }
-                    tot += e;
                 }
+                bool in = live;
+#pragma unroll
+                for (int j = 0; j < kScanMaxLookups; j++)
+                    if (j < a.nl) in = in && (a.lk[j].mode != KM_K32 || hv[j] < a.lk[j].cnpos);
+                ok = live && CK(in);
+                if (ok) {
+#pragma unroll
+                    for (int j = 0; j < kScanMaxLookups; j++)
+                        if (j < a.nl) S.bh[j * S.nb + b] = hv[j];
+                    uint32_t cl[kScanMaxLookups];
+#pragma unroll
+                    for (int j = 0; j < kScanMaxLookups; j++)
+                        cl[j] = (j < a.nl && a.lk[j].child_leaf) ? a.lk[j].clen[hv[j]] : 1u;
+                    uint32_t tl[FJ_MAX_NODES];
+                    bool tin = true;
+                    if (a.emit) {
+#pragma unroll
+                        for (int q = 0; q < FJ_MAX_NODES; q++) {
+                            tl[q] = 1;
+                            if (q >= a.ntail) continue;
+                            if (a.tail_lk[q] < 0) { tl[q] = a.tail_root_len[q]; continue; }
+                            const uint32_t th = hv[a.tail_lk[q] & (kScanMaxLookups - 1)];
+                            const bool t_in = th < a.tail_npos[q];
+                            tl[q] = t_in ? a.tail_len[q][th] : 0u;
+                            tin = tin && t_in;
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < kScanMaxLookups; j++) m *= cl[j];
+                    if (a.emit) {
+                        e = m;
+#pragma unroll
+                        for (int q = 0; q < FJ_MAX_NODES; q++) e *= tl[q];
+                        if (!CK(tin)) e = 0;
+                        tot += e;
+                    }
+                }
+            } else {
+                // slots of KM_K32 maps become their values (the child handles)
+                ok = live;
+                for (int j = 0; j < a.nl && live; j++) {
+                    const ScanLookup &L = a.lk[j];
+                    if (L.mode != KM_K32) continue;
+                    const uint32_t v = ((const uint32_t *)L.table)[k32_key_word(S.bh[j * S.nb + b]) + 4];
+                    ok = ok && CK(v < L.cnpos);
+                    S.bh[j * S.nb + b] = v;
+                }
+                if (ok) {
+                    for (int j = 0; j < a.nl; j++)
+                        if (a.lk[j].child_leaf) m *= a.lk[j].clen[S.bh[j * S.nb + b]];
+                    if (a.emit) {
+                        e = m;
+                        for (int q = 0; q < a.ntail; q++) {
+                            if (a.tail_lk[q] < 0) { e *= a.tail_root_len[q]; continue; }
+                            const uint32_t th = S.bh[a.tail_lk[q] * S.nb + b];
+                            if (!CK(th < a.tail_npos[q])) { e = 0; break; }
+                            e *= a.tail_len[q][th];
+                        }
+                        tot += e;
+                    }
+                }
+            }
+            if (ok) {
                 const u64 pos = base + i;
                 if (write && CK(pos < a.out.cap)) {
                     const FrontierDev &O = a.out;
                     const uint32_t row = S.brow[b];
                     for (int j = 0; j < a.nout; j++) O.vals[(u64)j * O.cap + pos] = a.cols[a.out_col[j]][row];
                     for (int j = 0; j < a.nl; j++)
-                        if (a.lk[j].hcol >= 0) O.hdl[(u64)a.lk[j].hcol * O.cap + pos] = S.bh[j * kBatch + b];
+                        if (a.lk[j].hcol >= 0) O.hdl[(u64)a.lk[j].hcol * O.cap + pos] = S.bh[j * S.nb + b];
                     if (O.mult) O.mult[pos] = m;
                 }
             }
-            if (a.direct) scan_emit_wave(a, S.bh, S.brow, fin, i, nf, e);
+            if (a.direct) scan_emit_wave<FAST>(a, S.bh, S.brow, S.nb, fin, i, nf, e);
         }
     }
     __syncthreads();   // every entry of the batch is read: empty it
@@ -2051,7 +2217,7 @@ __device__ __forceinline__ void scan_tiles(const ScanArgs &a, const ScanLds &S, 
                 probe_issue<MODE>(L, k0[r], MODE != KM_K32 ? k1[r] : 0u, true, pr[r]);
             prefetch(t + gridDim.x, n0, n1);
         } else {
-            round0_rows(a, tile0, tn, row, alive);
+            round0_rows<256, kTileRows>(a, tile0, tn, row, alive);
             uint32_t s0[kTileRows], s1[kTileRows];
 #pragma unroll
             for (int r = 0; r < kTileRows; r++) {
@@ -2063,9 +2229,10 @@ __device__ __forceinline__ void scan_tiles(const ScanArgs &a, const ScanLds &S, 
         }
         round0_finish<MODE, STATS>(a, L, row, alive, pr, S, nprobe, nhit);
         __syncthreads();
-        const uint32_t nb = S.cnt[0];   // block-uniform
+        const uint32_t nb = S.cnt[0];
+        __syncthreads();   // read by every thread before the next tile adds to it: block-uniform
         if (nb > 0 && (nb > (uint32_t)(kBatch - kTile) || t + gridDim.x >= ntiles))
-            scan_flush<STATS>(a, S, nb, tot, nprobe, nhit, red);
+            scan_flush<256, STATS>(a, S, nb, tot, nprobe, nhit, red);
     };
     prefetch(blockIdx.x, ka0, ka1);
     for (uint32_t t = blockIdx.x; t < ntiles; t += 2 * gridDim.x) {
@@ -2084,7 +2251,7 @@ __device__ __forceinline__ void scan_all(const ScanArgs &a, const ScanLds &S, u6
         const uint32_t tn = min((uint32_t)kTile, a.n - tile0);
         uint32_t row[kTileRows];
         bool alive[kTileRows];
-        round0_rows(a, tile0, tn, row, alive);
+        round0_rows<256, kTileRows>(a, tile0, tn, row, alive);
 #pragma unroll
         for (int r = 0; r < kTileRows; r++) {
             const uint32_t b = list_slot(alive[r], &S.cnt[0]);
@@ -2092,8 +2259,116 @@ __device__ __forceinline__ void scan_all(const ScanArgs &a, const ScanLds &S, u6
         }
         __syncthreads();
         const uint32_t nb = S.cnt[0];
+        __syncthreads();   // read by every thread before the next tile adds to it
         if (nb > 0 && (nb > (uint32_t)(kBatch - kTile) || t + gridDim.x >= ntiles))
-            scan_flush<STATS>(a, S, nb, tot, nprobe, nhit, red);
+            scan_flush<256, STATS>(a, S, nb, tot, nprobe, nhit, red);
+    }
+}
+
+// A KM_K32 probe in two steps with only the key and the loaded bucket's
+// keys held between them (the bucket is hashed again to resolve).
+struct Probe32 {
+    uint4 q;
+    uint32_t key;
+};
+
+__device__ __forceinline__ void probe32_issue(const ScanLookup &L, uint32_t key, bool alive, Probe32 &rp) {
+    rp.key = key;
+    const u64 b = (alive && key != kEmpty32) ? k32_bucket(mix32(key), L.mask) : 0ull;
+    rp.q = *(const uint4 *)((const uint32_t *)L.table + k32_key_word(b));
+}
+
+// true on a hit; out = its slot
+__device__ __forceinline__ bool probe32_resolve(const ScanLookup &L, const Probe32 &rp, uint32_t &out) {
+    const uint32_t *T = (const uint32_t *)L.table;
+    out = (uint32_t)(L.mask + 1);
+    if (rp.key == kEmpty32) return T[k32_key_word(L.mask + 1)] != 0u;
+    u64 idx = k32_bucket(mix32(rp.key), L.mask);
+    uint4 q = rp.q;
+    int s = 0;
+    int st = scan_keys32(q, rp.key, s);
+    for (u64 n = kK32Bucket; st == 0 && n <= k32_part_mask(L.mask); n += kK32Bucket) {   // a full bucket (rare)
+        idx = k32_next(idx, L.mask);
+        q = *(const uint4 *)(T + k32_key_word(idx));
+        st = scan_keys32(q, rp.key, s);
+    }
+    out = (uint32_t)(idx + s);
+    return st == 1;
+}
+
+// The rounds pass of a two-launch first node: workgroup b takes the filter
+// pass's regions [b l0_per, (b + 1) l0_per) as one sequence of rows, probes
+// the first lookup for kListRows rows per thread at a time (every load in
+// flight together), and the rows that hit join the batch; the later
+// lookups run as rounds over each batch.  The first lookup's probes were
+// counted by the filter pass (each row once); its hits are counted here.
+constexpr int kListRows = 4;
+constexpr int kListChunk = 256 * kListRows;
+constexpr int kListPerMax = 8;   // regions a workgroup takes at most
+static_assert(kListChunk <= kBatch, "a chunk's hits fit an empty batch");
+template <bool STATS>
+__device__ __forceinline__ void scan_list(const ScanArgs &a, const ScanLds &S, u64 &tot, uint32_t &nprobe,
+                                          uint32_t &nhit, u64 *red) {
+    StatusDev *status = a.status;
+    const ScanLookup &L = a.lk[0];
+    const uint32_t ftiles = (a.n + kFiltTile - 1) / kFiltTile;
+    const uint32_t items = a.l0_groups * kFiltWaves;
+    const uint32_t it0 = blockIdx.x * a.l0_per;
+    const uint32_t nit = it0 < items ? min(a.l0_per, items - it0) : 0u;
+    uint32_t cn[kListPerMax], total = 0;
+#pragma unroll
+    for (int k = 0; k < kListPerMax; k++) cn[k] = k < (int)nit ? a.l0_cnt[it0 + k] : 0u;
+#pragma unroll
+    for (int k = 0; k < kListPerMax; k++) total += cn[k];
+    for (uint32_t c0 = 0; c0 < total; c0 += kListChunk) {
+        uint32_t row[kListRows];
+        bool live[kListRows];
+        Probe32 pr[kListRows];
+#pragma unroll
+        for (int r = 0; r < kListRows; r++) {
+            // entry e of the workgroup's sequence: its region and place
+            uint32_t e = c0 + r * 256 + threadIdx.x;
+            live[r] = e < total;
+            uint32_t k = 0;
+            bool found = false;
+#pragma unroll
+            for (int q = 0; q < kListPerMax; q++) {
+                const bool here = !found && e < cn[q];
+                k = here ? (uint32_t)q : k;
+                found = found || here;
+                e -= found ? 0u : cn[q];
+            }
+            uint32_t cap = 0;
+            const u64 rs = live[r] ? list_region((it0 + k) / kFiltWaves, (it0 + k) % kFiltWaves, ftiles, a.l0_groups,
+                                                 cap)
+                                   : 0ull;
+            live[r] = live[r] && CK(k < nit && e < cap);
+            row[r] = live[r] ? a.l0_row[rs + e] : 0u;
+            pr[r].key = live[r] ? a.l0_key[rs + e] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < kListRows; r++) {
+            live[r] = live[r] && CK(row[r] < a.nrows);
+            probe32_issue(L, pr[r].key, live[r], pr[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < kListRows; r++) {
+            uint32_t v = 0;
+            const bool hit = live[r] && probe32_resolve(L, pr[r], v);
+            if (STATS && hit) nhit++;
+            const uint32_t b = list_slot(hit, &S.cnt[0]);
+            if (hit) {
+                S.brow[b] = row[r];
+                S.bh[b] = v;
+            }
+        }
+        __syncthreads();
+        const uint32_t nb = S.cnt[0];
+        __syncthreads();   // read by every thread before the next chunk adds to it
+        // flushed when the next chunk's hits might not fit, or at the end
+        const uint32_t next = c0 + kListChunk < total ? min((uint32_t)kListChunk, total - c0 - kListChunk) : 0u;
+        if (nb > 0 && (next == 0 || nb + next > (uint32_t)kBatch))
+            scan_flush<256, STATS, true>(a, S, nb, tot, nprobe, nhit, red);
     }
 }
 
@@ -2105,7 +2380,7 @@ __global__ void __launch_bounds__(256, FJ_SCAN_WAVES) k_scan_probe(ScanArgs a) {
     __shared__ uint16_t lists[2 * kBatch];
     __shared__ uint32_t cnt[kScanMaxLookups + 1];
     __shared__ u64 red[17];
-    const ScanLds S{bh, brow, lists, cnt};
+    const ScanLds S{bh, brow, lists, cnt, (uint32_t)kBatch};
     if (threadIdx.x <= kScanMaxLookups) cnt[threadIdx.x] = 0;
     __syncthreads();
     uint32_t nprobe = 0, nhit = 0;
@@ -2121,6 +2396,177 @@ __global__ void __launch_bounds__(256, FJ_SCAN_WAVES) k_scan_probe(ScanArgs a) {
         }
     }
     if (a.emit) block_add_count(tot, status, red);
+}
+
+// The rounds pass of a two-launch first node (its own kernel, so that the
+// one-launch kernel's registers are not sized for both).
+template <bool STATS>
+__global__ void __launch_bounds__(256, FJ_SCAN_WAVES) k_scan_rounds(ScanArgs a) {
+    StatusDev *status = a.status;
+    extern __shared__ uint32_t bh[];
+    __shared__ uint32_t brow[kBatch];
+    __shared__ uint16_t lists[2 * kBatch];
+    __shared__ uint32_t cnt[kScanMaxLookups + 1];
+    __shared__ u64 red[17];
+    const ScanLds S{bh, brow, lists, cnt, (uint32_t)kBatch};
+    if (threadIdx.x <= kScanMaxLookups) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t nprobe = 0, nhit = 0;
+    u64 tot = 0;
+    scan_list<STATS>(a, S, tot, nprobe, nhit, red);
+    if (STATS) {
+        u64 np = wave_sum_u64(nprobe), nh = wave_sum_u64(nhit);
+        if (__lane_id() == 0 && (np | nh)) {
+            atomicAdd(&a.status->probe[a.node], np);
+            atomicAdd(&a.status->hit[a.node], nh);
+        }
+    }
+    if (a.emit) block_add_count(tot, status, red);
+}
+
+// ---------------------------------------------- filter pass of the scan
+// The first node in two launches when its first lookup's map carries a
+// membership filter (written with the map).  This pass streams the cover's
+// first key column and tests each key against the filter held in LDS: a
+// row whose key lacks one of its two bits misses the first lookup without
+// touching the map.  On a selective join most rows leave here.  The others
+// are written with their keys to the wave's own region of a list (placed by
+// a scan over the wave's lanes: no atomics, no barriers), and k_scan_rounds
+// probes them, many per thread at once, and runs the later lookups.  What
+// bounds such a node is the chain of dependent memory round trips each
+// wave makes; this pass makes none beyond its stream, which it keeps one
+// tile ahead.  The filter (64 KB) leaves LDS for one 1,024-thread workgroup
+// per CU; tiles are 8 rows per thread.
+
+__device__ __forceinline__ bool bloom_pass(const uint32_t *filt, const ScanLookup &L, uint32_t key) {
+    if (key == kEmpty32) return true;   // kept in the reserved slot, not in the filter
+    const uint32_t h = mix32(key);
+    const uint32_t bits = bloom_bits(h);
+    return (filt[bloom_word(h, L.mask, L.bloom_shift)] & bits) == bits;
+}
+
+// Row r of the thread in filter-pass tile t (whole tiles: the thread's
+// kFiltRows consecutive rows; a ragged tile or a selection: strided
+// positions).
+__device__ __forceinline__ uint32_t filt_row(const ScanArgs &a, uint32_t tile0, uint32_t tn, bool whole, int r,
+                                             bool &alive) {
+    StatusDev *status = a.status;
+    if (whole) {
+        alive = true;
+        return a.r0 + tile0 + threadIdx.x * kFiltRows + r;
+    }
+    const uint32_t p = r * kFiltThreads + threadIdx.x;
+    alive = p < tn;
+    uint32_t row = tile_row(a, tile0, alive ? p : 0u);
+    alive = alive && CK(row < a.nrows);
+    return alive ? row : 0u;
+}
+
+template <bool STATS>
+__global__ void __launch_bounds__(kFiltThreads, 1) k_scan_filter(ScanArgs a) {
+    StatusDev *status = a.status;
+    __shared__ uint4 filt4[kBloomWords / 4];
+    const uint32_t *filt = (const uint32_t *)filt4;
+    const ScanLookup &L = a.lk[0];
+    {
+        // the filter's words (a multiple of four), every load in flight at once
+        constexpr int V = kBloomWords / 4 / kFiltThreads;
+        const uint4 *src = (const uint4 *)L.bloom;
+        const uint32_t nv = L.bloom_words / 4;
+        uint4 v[V];
+#pragma unroll
+        for (int k = 0; k < V; k++) {
+            const uint32_t i = k * kFiltThreads + threadIdx.x;
+            v[k] = i < nv ? src[i] : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < V; k++) {
+            const uint32_t i = k * kFiltThreads + threadIdx.x;
+            if (i < nv) filt4[i] = v[k];
+        }
+    }
+    __syncthreads();
+    uint32_t nprobe = 0, nfilt = 0;
+    const int32_t *c0 = a.cols[L.kc[0]];
+    const uint32_t ntiles = (a.n + kFiltTile - 1) / kFiltTile;
+    const uint32_t nfull = a.vec ? a.n / kFiltTile : 0;
+    const int lane = __lane_id(), wid = threadIdx.x >> 6;
+    uint32_t wcap;
+    const u64 rs = list_region(blockIdx.x, wid, ntiles, gridDim.x, wcap);
+    uint32_t *orow = a.l0_row + rs, *okey = a.l0_key + rs;
+    uint32_t cnt = 0;   // hits the wave has written (wave-uniform)
+    uint32_t ka[kFiltRows], kb[kFiltRows];
+    auto prefetch = [&](uint32_t t, uint32_t *k) {
+        if (t < nfull) {
+            const int32_t *c = c0 + a.r0 + t * kFiltTile + threadIdx.x * kFiltRows;
+#pragma unroll
+            for (int r = 0; r < kFiltRows; r += 4) {
+                const int4 x = *(const int4 *)(c + r);
+                k[r] = x.x; k[r + 1] = x.y; k[r + 2] = x.z; k[r + 3] = x.w;
+            }
+        }
+    };
+    auto tile = [&](uint32_t t, const uint32_t *k, uint32_t *nk) {
+        const uint32_t tile0 = t * (uint32_t)kFiltTile;
+        const uint32_t tn = min((uint32_t)kFiltTile, a.n - tile0);
+        const bool whole = t < nfull;
+        uint32_t alive = 0, pass = 0;   // bit r: row r of the thread
+        struct { uint32_t key; } pr[kFiltRows];
+        if (whole) {
+            alive = (1u << kFiltRows) - 1u;
+#pragma unroll
+            for (int r = 0; r < kFiltRows; r++) pr[r].key = k[r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < kFiltRows; r++) {
+                bool al;
+                const uint32_t rw = filt_row(a, tile0, tn, false, r, al);
+                pr[r].key = al ? (uint32_t)c0[rw] : 0u;
+                alive |= al ? 1u << r : 0u;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kFiltRows; r++)
+            pass |= (((alive >> r) & 1u) && bloom_pass(filt, L, pr[r].key)) ? 1u << r : 0u;
+        prefetch(t + gridDim.x, nk);
+        if (STATS) {
+            nprobe += (uint32_t)__popc(alive);
+            nfilt += (uint32_t)__popc(alive & ~pass);
+        }
+        // the wave's passing rows of the tile in (lane, row) order after its
+        // earlier tiles' (a scan over the lanes, no barrier)
+        const uint32_t h = (uint32_t)__popc(pass);
+        uint32_t x = h;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        uint32_t off = cnt + x - h;
+#pragma unroll
+        for (int r = 0; r < kFiltRows; r++) {
+            if (!((pass >> r) & 1u)) continue;
+            bool al;
+            if (CK(off < wcap)) {
+                orow[off] = filt_row(a, tile0, tn, whole, r, al);
+                okey[off] = pr[r].key;
+            }
+            off++;
+        }
+        cnt += __shfl(x, 63, 64);
+    };
+    prefetch(blockIdx.x, ka);
+    for (uint32_t t = blockIdx.x; t < ntiles; t += 2 * gridDim.x) {
+        tile(t, ka, kb);
+        if (t + gridDim.x < ntiles) tile(t + gridDim.x, kb, ka);
+    }
+    if (lane == 0) a.l0_cnt[blockIdx.x * kFiltWaves + wid] = cnt;
+    if (STATS) {
+        u64 np = wave_sum_u64(nprobe), nf = wave_sum_u64(nfilt);
+        if (__lane_id() == 0 && (np | nf)) {
+            atomicAdd(&a.status->probe[a.node], np);
+            atomicAdd(&a.status->filtered, nf);
+        }
+    }
 }
 
 // ------------------------------------------------------- emit (launches)
@@ -2211,6 +2657,12 @@ __device__ __forceinline__ void emit_row_at(const EmitDev &d, uint32_t E, uint32
         idx /= len;
         uint32_t pos = p + i;
         if (!CK(pos < T.L.npos || (T.level == 0 && pos < T.root_len))) return;
+        if (T.nk == 1 && T.L.kv) {
+            // a one-variable level keeps its key beside the offset: the
+            // value is read there, with no gather through the row
+            rows[q] = (uint32_t)T.L.kv[pos];
+            continue;
+        }
         rows[q] = T.L.offs ? T.L.offs[pos] : pos;
         if (!CK(rows[q] < T.L.nrows)) return;
     }
@@ -2223,7 +2675,7 @@ __device__ __forceinline__ void emit_row_at(const EmitDev &d, uint32_t E, uint32
             int z = -s - 1;
             int q = z / FJ_MAX_COLS, c = z % FJ_MAX_COLS;
             const TailDev &T = d.tail[q];
-            dst[j] = T.cols[T.kcol[c]][rows[q]];
+            dst[j] = (T.nk == 1 && T.L.kv) ? (int32_t)rows[q] : T.cols[T.kcol[c]][rows[q]];
         }
     }
 }
@@ -2658,13 +3110,13 @@ hipError_t launch_scan_probe(const ScanLaunch &l, hipStream_t s) {
     // persistent workgroups: as many as are resident at once, at most one
     // per tile
     constexpr int kMaxDevices = 64;
-    const size_t lds = (size_t)l.nl * kBatch * sizeof(uint32_t);
-    const void *fn = l.count_stats ? (const void *)k_scan_probe<true> : (const void *)k_scan_probe<false>;
-    static int resident[2][kScanMaxLookups + 1][kMaxDevices];   // 0: not known yet
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    const size_t lds = (size_t)l.nl * kBatch * sizeof(uint32_t);
+    const void *fn = l.count_stats ? (const void *)k_scan_probe<true> : (const void *)k_scan_probe<false>;
+    static int resident[2][kScanMaxLookups + 1][kMaxDevices];   // 0: not known yet
     int &res = resident[l.count_stats ? 1 : 0][l.nl][dev];
     if (res == 0) {
         int per_cu = 0, cus = 0;
@@ -2673,6 +3125,49 @@ hipError_t launch_scan_probe(const ScanLaunch &l, hipStream_t s) {
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return e;
         res = std::max(1, per_cu) * std::max(1, cus);
+    }
+    const ScanLookup &L0 = l.lk[0];
+    if (l.nl >= 1 && L0.bloom && L0.mode == KM_K32 && l.l0_row && l.l0_key && l.l0_cnt &&
+        scan_list_entries(l.n) <= l.l0_cap) {
+        // the filter must be the map's: one word per 2^shift buckets
+        if (L0.bloom_words < 4 || L0.bloom_words % 4 || L0.bloom_words > kBloomWords || L0.bloom_shift > 30 ||
+            ((L0.mask + 1) >> (2 + L0.bloom_shift)) != L0.bloom_words)
+            return hipErrorInvalidValue;
+        const void *ffn = l.count_stats ? (const void *)k_scan_filter<true> : (const void *)k_scan_filter<false>;
+        static int fres[2][kMaxDevices];   // 0: not known yet; -1: not launchable
+        int &fr = fres[l.count_stats ? 1 : 0][dev];
+        if (fr == 0) {
+            int per_cu = 0, cus = 0;
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ffn, kFiltThreads, 0);
+            if (e != hipSuccess) return e;
+            e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            if (e != hipSuccess) return e;
+            fr = per_cu >= 1 ? per_cu * std::max(1, cus) : -1;
+        }
+        if (fr > 0) {
+            const u64 ftiles = blocks_for(l.n, kFiltTile);
+            const unsigned G = (unsigned)std::min<u64>(std::min<u64>(ftiles, (u64)fr), kScanListGroups);
+            a.l0_row = l.l0_row;
+            a.l0_key = l.l0_key;
+            a.l0_cnt = l.l0_cnt;
+            a.l0_groups = G;
+            // the rounds pass: as many workgroups as are resident, each
+            // taking l0_per consecutive regions
+            const u64 items = (u64)G * kFiltWaves;
+            a.l0_per = (uint32_t)std::min<u64>((items + res - 1) / res, kListPerMax);
+            if (l.count_stats)
+                hipLaunchKernelGGL(k_scan_filter<true>, dim3(G), dim3(kFiltThreads), 0, s, a);
+            else
+                hipLaunchKernelGGL(k_scan_filter<false>, dim3(G), dim3(kFiltThreads), 0, s, a);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            const unsigned grid = (unsigned)((items + a.l0_per - 1) / a.l0_per);
+            if (l.count_stats)
+                hipLaunchKernelGGL(k_scan_rounds<true>, dim3(grid), dim3(256), lds, s, a);
+            else
+                hipLaunchKernelGGL(k_scan_rounds<false>, dim3(grid), dim3(256), lds, s, a);
+            return hipGetLastError();
+        }
     }
     const unsigned grid = (unsigned)std::min<u64>(blocks_for(l.n, kTile), (u64)res);
     if (l.count_stats)
@@ -2683,6 +3178,8 @@ hipError_t launch_scan_probe(const ScanLaunch &l, hipStream_t s) {
 }
 
 int scan_max_lookups() { return kScanMaxLookups; }
+
+unsigned long long scan_list_entries(unsigned long long n) { return blocks_for(n, kFiltTile) * (u64)kFiltTile; }
 
 size_t emit_dev_size() { return sizeof(EmitDev); }
 

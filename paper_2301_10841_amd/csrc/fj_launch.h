@@ -71,7 +71,19 @@ struct ScanLaunch {
     int direct;                // the kernel writes result rows itself (the first node emits)
     const void *ed;            // the execution's device emit descriptor (direct)
     unsigned long long cap;    // output capacity in rows (direct)
+    // list of the first lookup's hits for a two-launch node (lk[0].bloom):
+    // l0_cap entries of rows and of keys, kScanListGroups x kScanListWaves
+    // counters; null: one launch without the filter
+    uint32_t *l0_row, *l0_key, *l0_cnt;
+    unsigned long long l0_cap;
 };
+
+// The most filter-pass workgroups of a two-launch first node, the list's
+// counters per workgroup (one per wave), and the list entries one over n
+// cover positions needs.
+constexpr uint32_t kScanListGroups = 4096;
+constexpr uint32_t kScanListWaves = 16;
+unsigned long long scan_list_entries(unsigned long long n);
 
 hipError_t launch_scan_probe(const ScanLaunch &l, hipStream_t s);
 int scan_max_lookups();

@@ -53,7 +53,8 @@ class QueryS(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("tile", C.c_int64), ("block", C.c_int32), ("timing", C.c_int32),
-                ("tail", C.c_int32), ("generic", C.c_int32), ("trie", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("tail", C.c_int32), ("generic", C.c_int32), ("trie", C.c_int32), ("no_filter", C.c_int32),
+                ("reserved", C.c_int32 * 1)]
 
 
 class Stats(C.Structure):
@@ -61,7 +62,7 @@ class Stats(C.Structure):
                 ("hit", C.c_uint64 * MAX_NODES), ("survivors", C.c_uint64 * MAX_NODES),
                 ("forced", C.c_uint64 * MAX_NODES), ("forced_offsets", C.c_uint64 * MAX_NODES),
                 ("tail_from", C.c_int32), ("nnodes", C.c_int32), ("tiles", C.c_uint64),
-                ("deferred", C.c_uint64)]
+                ("deferred", C.c_uint64), ("filtered", C.c_uint64)]
 
     def per_node(self):
         n = self.nnodes
@@ -286,7 +287,7 @@ class Context:
     """A libfj context bound to a device and a torch stream."""
 
     def __init__(self, device: int = 0, stream=None, tile: int = 0, block: int = 0,
-                 timing=False, tail: int = 0, generic: bool = False, trie: int = 0):
+                 timing=False, tail: int = 0, generic: bool = False, trie: int = 0, no_filter: bool = False):
         import torch
         self.device = device
         if stream is None:
@@ -299,6 +300,7 @@ class Context:
         opt.tail = tail
         opt.generic = 1 if generic else 0
         opt.trie = int(trie)
+        opt.no_filter = 1 if no_filter else 0
         h = C.c_void_p()
         _check(lib().fj_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(opt), C.byref(h)))
         self.h = h.value
