@@ -302,7 +302,7 @@ def chooser_leg(ctx, n):
     t0 = time.time()
     m, info = learn.load(ctx)
     rows = learn.evaluate(ctx, m, learn.QuerySupply(0), datagen.seed_for(5, 3), n, reps=5,
-                          gate_rows=int(info.get("gate_rows", 0)))
+                          margin=float(info.get("margin", 0.0)), gate_rows=int(info.get("gate_rows", 0)))
     s = learn.summarize(rows)
     m.free()
     log(f"chooser leg: {n} queries in {time.time() - t0:.1f}s")
@@ -311,7 +311,7 @@ def chooser_leg(ctx, n):
             "learned_mean_regret": s["learned_mean_regret_vs_best"],
             "plain_mean_regret": s["plain_mean_regret_vs_best"],
             "choose_learned_ms": s["choose_learned_ms_mean"], "choose_plain_ms": s["choose_plain_ms_mean"],
-            "gate_rows": int(info.get("gate_rows", 0)),
+            "gate_rows": int(info.get("gate_rows", 0)), "margin": float(info.get("margin", 0.0)),
             "weights": "paper_2301_10841_amd/weights/chooser.npz"}
 
 

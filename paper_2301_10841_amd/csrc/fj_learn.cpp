@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <limits>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -356,13 +358,9 @@ fj_status make_plan(const fj_query &q, const fj_candidate &c, fj_plan *p) {
 struct Candidates {
     std::vector<fj_candidate> c;
     std::vector<float> feat;
-    std::vector<fj_plan *> plans;  // owned; kept when keep_plans
-    ~Candidates() {
-        for (fj_plan *p : plans) delete p;
-    }
 };
 
-fj_status enumerate(const fj_query &q, const fj_sketch *sk, int cap, Candidates &out, bool keep_plans = false) {
+fj_status enumerate(const fj_query &q, const fj_sketch *sk, int cap, Candidates &out) {
     std::string err;
     FJ_TRY(fj::check_query(q, err) == FJ_OK ? FJ_OK : set_error(FJ_ERR_ARG, err));
     out.c.clear();
@@ -401,23 +399,19 @@ fj_status enumerate(const fj_query &q, const fj_sketch *sk, int cap, Candidates 
         std::copy(vo.begin(), vo.end(), c.order);
         cands.push_back(c);
     }
+    // one plan object serves every candidate (its vectors keep their
+    // storage); the caller builds the chosen candidate's plan again
+    fj_plan scratch;
     for (const auto &c : cands) {
         if ((int)out.c.size() >= cap) break;
-        fj_plan *p = new fj_plan();
-        fj_status st = make_plan(q, c, p);
+        fj_status st = make_plan(q, c, &scratch);
         if (st != FJ_OK) {
-            delete p;
             if (out.c.empty()) return st;  // the plain plan must exist
             continue;
         }
         out.c.push_back(c);
         out.feat.resize(out.c.size() * FJ_FEATURES);
-        featurize(q, sk, *p, c.kind, is_cyclic, out.feat.data() + (out.c.size() - 1) * FJ_FEATURES);
-        if (keep_plans) {
-            out.plans.push_back(p);
-        } else {
-            delete p;
-        }
+        featurize(q, sk, scratch, c.kind, is_cyclic, out.feat.data() + (out.c.size() - 1) * FJ_FEATURES);
     }
     return FJ_OK;
 }
@@ -677,26 +671,45 @@ fj_status fj_choose_plan(fj_ctx *ctx, fj_mlp *m, const fj_query *q, const fj_ske
         return FJ_OK;
     }
     Candidates C;
-    FJ_TRY(enumerate(*q, sk, FJ_CAND_MAX, C, true));
+    FJ_TRY(enumerate(*q, sk, FJ_CAND_MAX, C));
     const int nc = (int)C.c.size();
     int pick = 0;
     if (m && q->natoms <= kSlots && nc > 1) {
         // one launch reads the features from and writes the scores to
-        // pinned host memory
+        // pinned host memory; the scores start as NaN and the host spins
+        // until every one is written, which skips the runtime's completion
+        // wait (a spin that runs out falls back to a stream synchronize,
+        // which also reports a failed kernel)
         FJ_HIP(hipSetDevice(m->dev));
         std::copy(C.feat.begin(), C.feat.end(), m->feat_h);
+        volatile float *sc = m->score_h;
+        for (int i = 0; i < nc; i++) sc[i] = std::numeric_limits<float>::quiet_NaN();
         const int64_t off[6] = {m->oW1, m->ob1, m->oW2, m->ob2, m->oW3, m->ob3};
         FJ_HIP(fj::mlp_rows(m->feat_h, nc, m->D, m->H, m->w, off, m->score_h, m->s));
-        FJ_HIP(hipStreamSynchronize(m->s));
+        auto written = [&]() {
+            for (int i = 0; i < nc; i++)
+                if (std::isnan(sc[i])) return false;
+            return true;
+        };
+        const auto t0 = std::chrono::steady_clock::now();
+        while (!written() && std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(2)) {
+        }
+        if (!written()) FJ_HIP(hipStreamSynchronize(m->s));
         int best = 0;
         for (int i = 1; i < nc; i++)
-            if (m->score_h[i] < m->score_h[best]) best = i;
-        if (m->score_h[0] - m->score_h[best] >= margin) pick = best;
-        if (scores) std::copy(m->score_h, m->score_h + nc, scores);
+            if (sc[i] < sc[best]) best = i;
+        if (sc[0] - sc[best] >= margin) pick = best;
+        if (scores)
+            for (int i = 0; i < nc; i++) scores[i] = sc[i];
     }
     if (chosen) *chosen = pick;
-    *out = C.plans[pick];
-    C.plans[pick] = nullptr;
+    fj_plan *p = new fj_plan();
+    fj_status st = make_plan(*q, C.c[pick], p);
+    if (st != FJ_OK) {
+        delete p;
+        return st;
+    }
+    *out = p;
     return FJ_OK;
 }
 

@@ -97,6 +97,84 @@ __global__ void k_mlp_rows(const float *__restrict__ x, int D, int H, const floa
     }
 }
 
+// Inference for the chooser's candidates (D, H <= 128, at most 32 rows) in
+// one workgroup of 1,024 threads, so that one launch costs one round of
+// memory latency: every global load (W1 and W2 as 16-byte vectors, the rows
+// from pinned host memory, the biases) is issued at the start, W1 and the
+// rows are kept in LDS for layer 1, and W2 replaces W1 there for layer 2.
+// Thread (g, j) computes hidden unit j of rows g, g + 8, ...; each dot
+// product still runs in index order in one thread, so the scores equal
+// k_mlp_rows' bit for bit.
+constexpr int kScoreThreads = 1024;
+constexpr int kScoreMaxD = 128, kScoreMaxH = 128, kScoreMaxB = 32;
+constexpr int kScoreVec = kScoreMaxD * kScoreMaxH / 4 / kScoreThreads;   // float4 of a weight matrix per thread
+
+__global__ void __launch_bounds__(kScoreThreads) k_mlp_score(const float *__restrict__ x, int B, int D, int H,
+                                                             const float *__restrict__ w, int64_t oW1, int64_t ob1,
+                                                             int64_t oW2, int64_t ob2, int64_t oW3, int64_t ob3,
+                                                             float *__restrict__ y) {
+    __shared__ float ws[kScoreMaxD * kScoreMaxH];
+    __shared__ float xs[kScoreMaxB * kScoreMaxD];
+    __shared__ float h1[kScoreMaxB * kScoreMaxH];
+    __shared__ float h2[kScoreMaxB * kScoreMaxH];
+    const int t = threadIdx.x;
+    const int nw1 = D * H / 4, nw2 = H * H / 4, nx = B * D;
+    const float4 *W1 = (const float4 *)(w + oW1), *W2 = (const float4 *)(w + oW2);
+    float4 a1[kScoreVec], a2[kScoreVec];
+#pragma unroll
+    for (int v = 0; v < kScoreVec; v++) {
+        const int i = v * kScoreThreads + t;
+        a1[v] = i < nw1 ? W1[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+        a2[v] = i < nw2 ? W2[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    float xv[(kScoreMaxB * kScoreMaxD + kScoreThreads - 1) / kScoreThreads];
+#pragma unroll
+    for (int v = 0; v < (kScoreMaxB * kScoreMaxD + kScoreThreads - 1) / kScoreThreads; v++) {
+        const int i = v * kScoreThreads + t;
+        xv[v] = i < nx ? x[i] : 0.f;
+    }
+    const int j = t % kScoreMaxH, g = t / kScoreMaxH;
+    constexpr int kGroups = kScoreThreads / kScoreMaxH;
+    const bool unit = j < H;
+    const float bj1 = unit ? w[ob1 + j] : 0.f, bj2 = unit ? w[ob2 + j] : 0.f;
+#pragma unroll
+    for (int v = 0; v < kScoreVec; v++) {
+        const int i = v * kScoreThreads + t;
+        if (i < nw1) ((float4 *)ws)[i] = a1[v];
+    }
+#pragma unroll
+    for (int v = 0; v < (kScoreMaxB * kScoreMaxD + kScoreThreads - 1) / kScoreThreads; v++) {
+        const int i = v * kScoreThreads + t;
+        if (i < nx) xs[i] = xv[v];
+    }
+    __syncthreads();
+    if (unit)
+        for (int r = g; r < B; r += kGroups) {
+            float a = 0.f;
+            for (int i = 0; i < D; i++) a = fmaf(xs[r * D + i], ws[i * H + j], a);
+            h1[r * H + j] = fmaxf(a + bj1, 0.f);
+        }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < kScoreVec; v++) {
+        const int i = v * kScoreThreads + t;
+        if (i < nw2) ((float4 *)ws)[i] = a2[v];
+    }
+    __syncthreads();
+    if (unit)
+        for (int r = g; r < B; r += kGroups) {
+            float a = 0.f;
+            for (int k = 0; k < H; k++) a = fmaf(h1[r * H + k], ws[k * H + j], a);
+            h2[r * H + j] = fmaxf(a + bj2, 0.f);
+        }
+    __syncthreads();
+    if (t < B) {
+        float a = 0.f;
+        for (int k = 0; k < H; k++) a = fmaf(h2[t * H + k], w[oW3 + k], a);
+        y[t] = a + w[ob3];
+    }
+}
+
 // dY = 2 (y - t) / B, and the loss terms
 __global__ void k_mse_grad(const float *y, const float *t, float *dy, float *sq, int B) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -325,6 +403,15 @@ hipError_t mlp_gemm(const float *A, const float *B, const float *bias, float *C,
 
 hipError_t mlp_rows(const float *x, int B, int D, int H, const float *w, const int64_t off[6], float *y,
                     hipStream_t s) {
+    // the one-workgroup kernel: small shapes, 16-byte aligned weight matrices
+    const bool one = B >= 1 && B <= kScoreMaxB && D >= 1 && D <= kScoreMaxD && H >= 1 && H <= kScoreMaxH &&
+                     D % 4 == 0 && H % 4 == 0 && off[0] % 4 == 0 && off[2] % 4 == 0 &&
+                     ((uintptr_t)w % 16) == 0;
+    if (one) {
+        hipLaunchKernelGGL(k_mlp_score, dim3(1), dim3(kScoreThreads), 0, s, x, B, D, H, w, off[0], off[1], off[2],
+                           off[3], off[4], off[5], y);
+        return hipGetLastError();
+    }
     const int block = ((H + 63) / 64) * 64;
     const size_t lds = (size_t)(D + 2 * H) * sizeof(float);
     hipLaunchKernelGGL(k_mlp_rows, dim3(B), dim3(block), lds, s, x, D, H, w, off[0], off[1], off[2], off[3], off[4],

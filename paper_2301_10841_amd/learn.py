@@ -211,11 +211,13 @@ def train(ctx, data: Dict, epochs: int = 60, batch: int = 256, lr: float = 1e-3,
 
 
 def fit_gate(data: Dict, pred: np.ndarray, val_queries, oh_plain: float, oh_learn: float) -> Dict:
-    """The row gate of fj_choose_plan fitted on the validation queries: with
-    the choice overheads measured live (oh_plain: the plain plan alone;
-    oh_learn: enumeration, features and inference), a query with fewer than
-    G rows takes the plain plan at oh_plain and any other the predicted best
-    at oh_learn; G minimizes the validation queries' total end-to-end time."""
+    """The row gate and the score margin of fj_choose_plan fitted on the
+    validation queries: with the choice overheads measured live (oh_plain:
+    the plain plan alone; oh_learn: enumeration, features and inference), a
+    query with fewer than G rows takes the plain plan at oh_plain; any other
+    takes the predicted best at oh_learn when its predicted score is at least
+    M below the plain plan's, else the plain plan.  (G, M) minimizes the
+    validation queries' total end-to-end time."""
     q = data["q"]
     per = []
     for qi in val_queries:
@@ -223,20 +225,46 @@ def fit_gate(data: Dict, pred: np.ndarray, val_queries, oh_plain: float, oh_lear
         if rows.size == 0:
             continue
         s = data["sec"][rows]
-        k = int(np.argmin(pred[rows]))
-        per.append((data["queries"][qi]["atom_rows"], s[0] + oh_plain, s[k] + oh_learn))
+        pr = pred[rows]
+        k = int(np.argmin(pr))
+        per.append((data["queries"][qi]["atom_rows"], s[0], s[k], float(pr[0] - pr[k])))
     if not per:
-        return {"gate_rows": 0}
+        return {"gate_rows": 0, "margin": 0.0}
     per.sort()
-    cands = [0] + [r + 1 for r, _, _ in per]
-    best_g, best_t = 0, None
-    for g in cands:
-        t = sum(p if r < g else l for r, p, l in per)
-        if best_t is None or t < best_t:
-            best_g, best_t = g, t
-    t0 = sum(l for _, _, l in per)
-    return {"gate_rows": int(best_g), "val_total_gated_s": best_t, "val_total_ungated_s": t0,
-            "oh_plain_s": oh_plain, "oh_learn_s": oh_learn, "val_queries": len(per)}
+    best = None
+    for margin in [0.0, 0.05, 0.1, 0.15, 0.2, 0.3, 0.4, 0.6, 0.8]:
+        learned = [(r, p + oh_plain, (l if d >= margin else p) + oh_learn) for r, p, l, d in per]
+        for g in [0] + [r + 1 for r, _, _ in learned]:
+            t = sum(p if r < g else l for r, p, l in learned)
+            if best is None or t < best[0]:
+                best = (t, g, margin)
+    t0 = sum(l + oh_learn for _, _, l, _ in per)
+    return {"gate_rows": int(best[1]), "margin": float(best[2]), "val_total_gated_s": best[0],
+            "val_total_ungated_s": t0, "oh_plain_s": oh_plain, "oh_learn_s": oh_learn, "val_queries": len(per)}
+
+
+# Choice overheads are a few to a few tens of microseconds of host time, so
+# each is timed over many alternating repetitions after one untimed call of
+# each (first calls pay for cold caches), and the median is taken.
+CHOICE_REPS = 15
+
+
+def choice_times(fj, d, m, sks, margin: float, gate_rows: int, reps: int):
+    """Seconds of each repetition of the plain choice (greedy order,
+    converted and factored) and of the learned one, alternating."""
+    fj.plan_from_binary(d.q, fj.greedy_order(d.q, sks), True)
+    d.choose(m, sks, margin, gate_rows)
+    tp, tl = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        p = fj.plan_from_binary(d.q, fj.greedy_order(d.q, sks), True)
+        del p
+        tp.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        r = d.choose(m, sks, margin, gate_rows)
+        del r
+        tl.append(time.perf_counter() - t0)
+    return tp, tl
 
 
 def choice_overheads(ctx, m, supply, seed: int, n: int, reps: int, max_rows: int):
@@ -247,13 +275,9 @@ def choice_overheads(ctx, m, supply, seed: int, n: int, reps: int, max_rows: int
     for dq in supply.queries(seed, n, max_rows):
         d = runner.DeviceQuery(ctx, dq)
         sks = d.sketches()
-        for _ in range(reps):
-            t0 = time.perf_counter()
-            fj.plan_from_binary(d.q, fj.greedy_order(d.q, sks), True)
-            tp.append(time.perf_counter() - t0)
-            t0 = time.perf_counter()
-            d.choose(m, sks)
-            tl.append(time.perf_counter() - t0)
+        a, b = choice_times(fj, d, m, sks, 0.0, 0, max(reps, CHOICE_REPS))
+        tp += a
+        tl += b
         del d
     return statistics.median(tp), statistics.median(tl)
 
@@ -321,14 +345,8 @@ def evaluate(ctx, m, supply: QuerySupply, seed: int, n: int, reps: int = 5, marg
             if cnt is not None:
                 counts.add(cnt)
         assert len(counts) == 1, (qi, counts)
-        tc_plain, tc_learn = [], []
-        for _ in range(reps):
-            t0 = time.perf_counter()
-            fj.plan_from_binary(d.q, fj.greedy_order(d.q, sks), True)
-            tc_plain.append(time.perf_counter() - t0)
-            t0 = time.perf_counter()
-            _, k, _ = d.choose(m, sks, margin, gate_rows)
-            tc_learn.append(time.perf_counter() - t0)
+        tc_plain, tc_learn = choice_times(fj, d, m, sks, margin, gate_rows, CHOICE_REPS)
+        _, k, _ = d.choose(m, sks, margin, gate_rows)
         rows.append({"kind": dq.kind, "chosen": k, "ncand": len(cands), "count": counts.pop(),
                      "atom_rows": int(sum(dq.atom_rows(a) for a in range(len(dq.atoms)))),
                      "choose_plain_s": statistics.median(tc_plain), "choose_learned_s": statistics.median(tc_learn),
@@ -380,7 +398,7 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--workers", type=int, default=12)
     ap.add_argument("--max-rows", type=int, default=2_000_000)
-    ap.add_argument("--margin", type=float, default=0.0)
+    ap.add_argument("--margin", type=float, default=None, help="score margin (default: the fitted one)")
     ap.add_argument("--train-seed", type=int, default=None)
     ap.add_argument("--heldout-seed", type=int, default=None)
     ap.add_argument("--out", default="chooser_report")
@@ -410,12 +428,13 @@ def main(argv=None):
             info["gate"] = fit_gate(data, pred, val_queries, oh_p, oh_l)
             info.update({"train_queries": args.train, "train_seed": train_seed, "features": fj.FEATURES,
                          "hidden": HIDDEN, "target": "standardized ln(microseconds)",
-                         "gate_rows": info["gate"]["gate_rows"]})
+                         "gate_rows": info["gate"]["gate_rows"], "margin": info["gate"]["margin"]})
             log(f"gate: {info['gate']}")
             save(m, info, os.path.join(args.out, "chooser.npz"))
         report["train"] = {k: v for k, v in info.items() if k != "history"}
         report["train_history"] = info.get("history")
-        rows = evaluate(ctx, m, supply, held_seed, args.heldout, args.reps, args.margin, args.max_rows,
+        margin = args.margin if args.margin is not None else float(info.get("margin", 0.0))
+        rows = evaluate(ctx, m, supply, held_seed, args.heldout, args.reps, margin, args.max_rows,
                         out_npz=os.path.join(args.out, "heldout_data.npz"),
                         gate_rows=int(info.get("gate_rows", 0)))
         report["heldout"] = summarize(rows)
