@@ -211,6 +211,8 @@ struct fj_colt {
     bool root_built = false;
     bool root_lazy = false;  // unbuilt root that a probe may force (its map is allocated)
     bool root_part = false;  // root map (KM_K32) built range by range by the grouped path
+    bool root_keys = true;   // a built root also lists its keys (some node iterates it, or the
+                             // simple trie forces its children up front); else it is only probed
     uint32_t *bloom_buf = nullptr;   // the root map's key filter (kBloomWords), if it may have one
     int lev_nk[fj::kMaxLevels] = {0};
     int lev_var[fj::kMaxLevels][FJ_MAX_COLS] = {{0}};
@@ -587,6 +589,7 @@ struct ColtGroup {
     uint32_t nfill = 0;
     // members whose KM_K32 root maps are built range by range
     int npm = 0;
+    bool part_keys = false;   // some such member lists its root's keys (the rank pass runs)
     uint32_t nparts = 0, nblocks = 0;
     u64 wp = 0;
     DevBuf meta;   // descs | wpre | roots | pre | part members | fill blocks
@@ -649,6 +652,7 @@ fj_status group_prepare(fj_ctx *c, ColtGroup &G, fj_colt *const *colts, int n, u
         key_put(key, t->nroot);
         key_put(key, t->root_built);
         key_put(key, t->root_part);
+        key_put(key, t->root_keys);
         key_put(key, t->nrows);
         key_put(key, t->sel);
         key_put(key, t->cols);
@@ -688,6 +692,8 @@ fj_status group_prepare(fj_ctx *c, ColtGroup &G, fj_colt *const *colts, int n, u
     }
     G.wtot = wpre[n];
     G.npm = (int)pm.size();
+    G.part_keys = false;
+    for (int k = 0; k < n; k++) G.part_keys = G.part_keys || (colts[k]->root_part && colts[k]->root_keys);
     G.nparts = nparts;
     G.nblocks = nblocks;
     G.wp = wp;
@@ -848,6 +854,9 @@ fj_status group_launch(fj_ctx *c, ColtGroup &G) {
         // launches); more: the scans run in one workgroup, or in three
         // launches beyond 32,768 ranges
         pa.inline_scan = G.nparts <= 2048 ? 1 : 0;
+        // roots that are only probed need no key list: no rank pass, the
+        // build pass marks each root forced
+        pa.set_st = G.part_keys ? 0 : 1;
         auto scan = [&](const uint32_t *in, uint32_t *out) -> hipError_t {
             if (pa.inline_scan) return hipSuccess;
             return G.nparts <= 32768 ? fj::launch_scan_small_u32(in, out, G.nparts, c->stream)
@@ -857,8 +866,10 @@ fj_status group_launch(fj_ctx *c, ColtGroup &G) {
         FJ_HIP(scan(pa.pcnt, pa.pstart));
         FJ_HIP(fj::launch_part_phase(1, pa, c->stream));
         FJ_HIP(fj::launch_part_phase(2, pa, c->stream));
-        FJ_HIP(scan(pa.pdist, pa.rstart));
-        FJ_HIP(fj::launch_part_phase(3, pa, c->stream));
+        if (G.part_keys) {
+            FJ_HIP(scan(pa.pdist, pa.rstart));
+            FJ_HIP(fj::launch_part_phase(3, pa, c->stream));
+        }
     }
     return FJ_OK;
 }
@@ -1227,6 +1238,17 @@ fj_status fj_sketch_relation(fj_ctx *c, const fj_relation *rel, fj_sketch *out) 
     return FJ_OK;
 }
 
+// Whether a node of the plan iterates atom a's root (its level-0 subatom is
+// a pure cover of the node), or the simple trie forces the root's children
+// up front: then a built root lists its keys by rank as well as its map.
+static bool root_needs_keys(const fj_ctx *c, const fj_plan *p, int a) {
+    if (c->opt.trie == 2 && p->nlev[a] > 1) return true;
+    for (size_t k = 0; k < p->nodes.size(); k++)
+        for (int i : p->layout[k].pure)
+            if (p->nodes[k][i].atom == a && p->sub_level[k][i] == 0) return true;
+    return false;
+}
+
 fj_status fj_build_colt(fj_ctx *c, const fj_query *q, const fj_plan *p, int32_t atom, const fj_relation *rel,
                         fj_colt **out) {
     if (!c || !q || !p || !out) return fail(FJ_ERR_ARG, "null argument");
@@ -1246,6 +1268,7 @@ fj_status fj_build_colt(fj_ctx *c, const fj_query *q, const fj_plan *p, int32_t 
     // the ablation's tries build every root map ahead
     t->root_built = p->root_built[atom] || c->opt.trie >= 1;
     t->root_lazy = !t->root_built && p->root_lazy[atom];
+    t->root_keys = root_needs_keys(c, p, atom);
     t->nlev = p->nlev[atom];
     for (int l = 0; l < t->nlev; l++) {
         const fj::Subatom &s = p->lev[atom][l];
@@ -1766,7 +1789,7 @@ fj_status exec_scan_node(Exec &x, int cover_sub, u64 T, uint32_t) {
     return FJ_OK;
 }
 
-fj_status check_exec_args(const fj_query *q, const fj_plan *p, fj_colt *const *colts) {
+fj_status check_exec_args(const fj_ctx *c, const fj_query *q, const fj_plan *p, fj_colt *const *colts) {
     if (q->natoms != p->q.natoms || q->nvars != p->q.nvars) return fail(FJ_ERR_ARG, "query does not match the plan");
     for (int a = 0; a < q->natoms; a++) {
         if (q->atoms[a].arity != p->q.atoms[a].arity ||
@@ -1783,6 +1806,8 @@ fj_status check_exec_args(const fj_query *q, const fj_plan *p, fj_colt *const *c
         if (p->root_built[a] && !t->root_built) return fail(FJ_ERR_ARG, "COLT root rule does not match the plan");
         if (p->root_lazy[a] && !t->root_built && !t->root_lazy)
             return fail(FJ_ERR_ARG, "COLT root rule does not match the plan");
+        if (t->root_built && !t->root_keys && root_needs_keys(c, p, a))
+            return fail(FJ_ERR_ARG, "COLT was built for a plan that only probes its root; this plan iterates it");
     }
     std::string err;
     return fj::check_query(*q, err) == FJ_OK ? FJ_OK : fail(FJ_ERR_ARG, err);
@@ -1794,7 +1819,7 @@ static fj_status execute_impl(fj_ctx *c, const fj_query *q, const fj_plan *p, fj
                               uint64_t *count, int32_t *out, uint64_t cap, uint64_t *written, fj_stats *stats,
                               fj_result *res) {
     if (!c || !q || !p || !colts || !count) return fail(FJ_ERR_ARG, "null argument");
-    FJ_TRY(check_exec_args(q, p, colts));
+    FJ_TRY(check_exec_args(c, q, p, colts));
     FJ_HIP(hipSetDevice(c->device));
     if (stats) memset(stats, 0, sizeof(*stats));
     Exec x;
@@ -2263,7 +2288,7 @@ extern "C" fj_status fj_batch_create(fj_ctx *c, int32_t n, const fj_query *const
     u64 max_rows = 0;
     for (int i = 0; i < n; i++) {
         if (!qs[i] || !plans[i] || !colts[i]) { batch_release(b); return fail(FJ_ERR_ARG, "null query"); }
-        fj_status st = check_exec_args(qs[i], plans[i], colts[i]);
+        fj_status st = check_exec_args(c, qs[i], plans[i], colts[i]);
         if (st == FJ_OK) st = batch_query(qs[i], plans[i], colts[i], hq[i]);
         if (st != FJ_OK) {
             std::string m = g_err;

@@ -277,6 +277,7 @@ struct PartArgs {
     int n;
     uint32_t nblocks;         // blocks of the count and scatter passes
     uint32_t nparts;          // ranges of every member
+    int set_st;               // no rank pass: the build pass marks each root forced (st = 1, no key list)
     int inline_scan;          // few ranges: the passes sum the per-range counts they need themselves
                               // (the scatter pass's block 0 writes pstart), no scan launches
     uint16_t *ipart;          // per item: its range within its member

@@ -1163,6 +1163,7 @@ __global__ void __launch_bounds__(kPartBuildThreads) k_part_build(PartArgs a) {
             if (emp && CK(base < f.C.npos)) f.C.len[base] = emp;
         }
         a.pdist[P] = ktot + (emp ? 1u : 0u);
+        if (a.set_st && lp == 0) f.L.st[0] = 1u;      // a root only probed: forced, its keys not listed
         emp = base;                                   // the empty marker's scatter cursor
     }
     __syncthreads();
