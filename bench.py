@@ -50,6 +50,7 @@ def main():
     ap.add_argument("--rmat-scale", type=int, default=22)
     ap.add_argument("--rmat-edges", type=int, default=50_000_000)
     ap.add_argument("--cycle4-scale", type=int, default=20, help="rmat workload: scale of the 4-cycle run")
+    ap.add_argument("--cycle4-parts", type=int, default=16, help="rmat workload: the 4-cycle counted in parts by w")
     ap.add_argument("--rmat-cache", default=None, help="rmat workload: directory keeping the drawn graph")
     ap.add_argument("--queries", type=int, default=256, help="batch workload: number of queries")
     ap.add_argument("--tune-queries", type=int, default=48, help="batch workload: calibration batch size")
@@ -800,6 +801,7 @@ def bench_rmat(args):
     tim = ctx.timings()
     assert len(set(counts)) == 1, counts
     tri = counts[0]
+    log(f"triangles: {tri}, {elapsed / args.steps * 1e3:.1f} ms per step")
     d.rebuild(colts)
     _, _, st = ctx.execute(d.q, gj, colts, stats=True)
     nodes = st.per_node()
@@ -838,6 +840,7 @@ def bench_rmat(args):
     for c in r["colts"]:
         c.free()
     assert r["count"] == tri, (r["count"], tri)
+    log(f"converted plan: same count in {conv_s:.2f} s")
     # sampled parity: the triangles through 2048 random x vertices.  The
     # sampled query keeps the R rows with x in the sample, the S rows whose
     # y such an R row reaches and the T rows that close back to the sample:
@@ -886,21 +889,41 @@ def bench_rmat(args):
                          f"one run including its COLT builds; all cores: the sample split over {procs} "
                          f"processes by x mod {procs}, wall time once every process holds its part",
                "s_per_run": wall, "host_cpus": os.cpu_count(), "single_core": one}
+    log("sampled triangles and CPU oracle legs done")
     # 4-cycle at a reduced scale against trace(A^4)
     s4, d4 = datagen.rmat_edges(datagen.seed_for(3, 1 + args.seed_rep), args.cycle4_scale,
                                 int(round(11.92 * (1 << args.cycle4_scale))))
-    q4 = synth.four_cycle_query((s4, d4))
-    dc = runner.DeviceQuery(ctx, q4)
-    gj4 = dc.plan_nodes([[(0, (0,)), (3, (0,))], [(0, (1,)), (1, (1,))], [(1, (2,)), (2, (2,))],
-                         [(2, (3,)), (3, (3,))]])
-    c4 = dc.build(gj4)
-    dc.rebuild(c4)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    cyc, _, st4 = ctx.execute(dc.q, gj4, c4, stats=True)
-    cyc_s = time.perf_counter() - t2
-    for c in c4:
-        c.free()
+    # Counted in parts by ranges of w (every cycle has one w): part i keeps
+    # the E(w,x) and E(z,w) rows whose w falls in its range and all of
+    # E(x,y) and E(y,z); the parts' counts add up to the count, and each part
+    # reports when it is done.  Each part's COLT builds are in its time.
+    nv = int(max(s4.max(), d4.max())) + 1
+    parts = args.cycle4_parts
+    cyc, cyc_s, probes4 = 0, 0.0, 0
+    e_all = synth.Relation("E", [s4, d4])
+    for i in range(parts):
+        lo, hi = nv * i // parts, nv * (i + 1) // parts
+        k0 = (s4 >= lo) & (s4 < hi)
+        k3 = (d4 >= lo) & (d4 < hi)
+        q4 = synth.make_query(["w", "x", "y", "z"],
+                              [synth.Relation("E0", [s4[k0], d4[k0]]), e_all,
+                               synth.Relation("E3", [s4[k3], d4[k3]])],
+                              [(0, (0, 1)), (1, (1, 2)), (1, (2, 3)), (2, (3, 0))])
+        dc = runner.DeviceQuery(ctx, q4)
+        gj4 = dc.plan_nodes([[(0, (0,)), (3, (0,))], [(0, (1,)), (1, (1,))], [(1, (2,)), (2, (2,))],
+                             [(2, (3,)), (3, (3,))]])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        c4 = dc.build(gj4)
+        n4, _, st4 = ctx.execute(dc.q, gj4, c4, stats=True)
+        torch.cuda.synchronize()
+        cyc_s += time.perf_counter() - t2
+        cyc += n4
+        probes4 += sum(n["probe"] for n in st4.per_node())
+        for c in c4:
+            c.free()
+        del dc
+        log(f"4-cycles at 2^{args.cycle4_scale}, part {i + 1}/{parts}: {n4} ({cyc_s:.1f} s so far)")
     # the check: trace(A^4), stored for the scales whose closed form takes
     # the CPU minutes (tests/golden/make_rmat_cycle4.py), else computed here
     want4, check4 = None, "trace(A^4)"
@@ -913,7 +936,6 @@ def bench_rmat(args):
     if want4 is None:
         want4 = trace_power4(s4, d4)
     assert cyc == want4, (cyc, want4)
-    probes4 = sum(n["probe"] for n in st4.per_node())
     res = {
         "metric": "probe tuples/sec + output tuples/sec, achieved HBM GB/s; learned vs plain plan time",
         "value": probe_tuples / per,
@@ -934,6 +956,7 @@ def bench_rmat(args):
         "converted_plan_s": conv_s,
         "sampled_x": int(xs.size), "sampled_triangles": want,
         "cycle4": {"scale": args.cycle4_scale, "edges": int(s4.size), "count": cyc, "seconds": cyc_s,
+                   "parts": parts,
                    "probes": probes4, "probes_per_s": probes4 / cyc_s, "check": check4},
         "cpu_baseline": cpu,
     }

@@ -260,7 +260,11 @@ struct GroupRoot {
 // of np ranges (kK32Part slots each, or the whole map when smaller) is
 // built range by range, each range by one workgroup in LDS.
 constexpr uint32_t kMaxParts = 4096;       // ranges per map on this path
-constexpr uint32_t kPartItems = 1024;      // items per block of the count and scatter passes
+#ifndef FJ_PART_ITEMS
+#define FJ_PART_ITEMS 1024
+#endif
+constexpr uint32_t kPartItems = FJ_PART_ITEMS;   // items per block of the count and scatter passes
+static_assert(kPartItems % 256 == 0, "items per block: a multiple of the block's threads");
 struct PartMember {
     int desc;                 // the member's ForceArgs in the group
     uint32_t np;              // ranges of its map
