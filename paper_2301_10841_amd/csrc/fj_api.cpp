@@ -596,8 +596,7 @@ struct ColtGroup {
     DevBuf work;   // wslot | cntv | ex | block sums | total | range arrays
     size_t o_wpre = 0, o_roots = 0, o_pre = 0, o_pmem = 0, o_fill = 0, meta_bytes = 0;
     size_t w_cntv = 0, w_ex = 0, w_bsum = 0, w_total = 0;
-    size_t w_ipart = 0, w_irow = 0, w_ikey = 0, w_ikv = 0, w_pcnt = 0, w_pcur = 0, w_pstart = 0;
-    size_t w_prow = 0, w_pkey = 0, w_pkv = 0, w_scnt = 0, w_pdist = 0, w_rstart = 0, w_pbsum = 0;
+    size_t w_prow = 0, w_pkey = 0, w_pkv = 0, w_scnt = 0, w_poff = 0, w_pdist = 0, w_rstart = 0, w_pbsum = 0;
     std::vector<char> stage, last;   // host image of meta, and the last one uploaded
     std::vector<char> last_key;      // the inputs that image was made from
     char *stage_h = nullptr;         // pinned copy source
@@ -666,7 +665,7 @@ fj_status group_prepare(fj_ctx *c, ColtGroup &G, fj_colt *const *colts, int n, u
     // the general path takes the built roots not built range by range
     std::vector<u64> wpre(n + 1, 0);
     std::vector<fj::PartMember> pm;
-    u64 wp = 0, nslots = 0;
+    u64 wp = 0, nslots = 0, noff = 0;
     uint32_t nparts = 0, nblocks = 0;
     for (int k = 0; k < n; k++) {
         const fj_colt *t = colts[k];
@@ -685,8 +684,15 @@ fj_status group_prepare(fj_ctx *c, ColtGroup &G, fj_colt *const *colts, int n, u
         m.slot_base = nslots;
         nslots += (u64)m.np << m.plog;
         if (wp + t->nroot > 0xFFFFFFFFull) return fail(FJ_ERR_UNSUPPORTED, "grouped roots of 2^32 rows or more");
+        // place slices: whole chunks, at most kMaxPlaceBlocks of them
+        const u64 W = t->nroot, chunks = (W + fj::kPlaceChunk - 1) / fj::kPlaceChunk;
+        const u64 cpb = (chunks + fj::kMaxPlaceBlocks - 1) / fj::kMaxPlaceBlocks;   // chunks per block
+        m.ipb = (uint32_t)(cpb * fj::kPlaceChunk);
+        m.nb = (uint32_t)((W + m.ipb - 1) / m.ipb);
+        m.off_base = noff;
+        noff += (u64)(m.np + 1) * m.nb;
         nparts += m.np;
-        nblocks += (uint32_t)((t->nroot + fj::kPartItems - 1) / fj::kPartItems);
+        nblocks += m.nb;
         wp += t->nroot;
         pm.push_back(m);
     }
@@ -704,38 +710,17 @@ fj_status group_prepare(fj_ctx *c, ColtGroup &G, fj_colt *const *colts, int n, u
     G.w_bsum = G.w_ex + align256(sizeof(u64) * (wcap + 2));
     G.w_total = G.w_bsum + align256(sizeof(u64) * (wcap / 1024 + 2));
     const size_t item_bytes = align256(sizeof(uint32_t) * (wp + 1));
-    G.w_ipart = G.w_total + 256;
-    G.w_irow = G.w_ipart + align256(sizeof(uint16_t) * (wp + 1));
-    G.w_ikey = G.w_irow + item_bytes;
-    G.w_ikv = G.w_ikey + item_bytes;
-    G.w_prow = G.w_ikv + item_bytes;
+    G.w_prow = G.w_total + 256;
     G.w_pkey = G.w_prow + item_bytes;
     G.w_pkv = G.w_pkey + item_bytes;
     G.w_scnt = G.w_pkv + item_bytes;
-    G.w_pcnt = G.w_scnt + align256(sizeof(uint32_t) * (nslots + 1));
-    G.w_pcur = G.w_pcnt + align256(sizeof(uint32_t) * (nparts + 1));
-    G.w_pstart = G.w_pcur + align256(sizeof(uint32_t) * (nparts + 1));
-    G.w_pdist = G.w_pstart + align256(sizeof(uint32_t) * (nparts + 1));
+    G.w_poff = G.w_scnt + align256(sizeof(uint32_t) * (nslots + 1));
+    G.w_pdist = G.w_poff + align256(sizeof(uint32_t) * (noff + 1));
     G.w_rstart = G.w_pdist + align256(sizeof(uint32_t) * (nparts + 1));
     G.w_pbsum = G.w_rstart + align256(sizeof(uint32_t) * (nparts + 1));
     const size_t work_bytes = G.w_pbsum + align256(sizeof(uint32_t) * (nparts / 1024 + 2)) + 256;
     FJ_TRY(G.work.ensure(work_bytes, c->stream));
     std::vector<fj::FillBlock> fb;
-    auto add_zero = [&](uint32_t *p, u64 nwords) {
-        for (u64 off = 0; off < nwords; off += kFillChunk) {
-            fj::FillBlock b;
-            memset(&b, 0, sizeof(b));
-            b.p = p;
-            b.start = off;
-            b.n = std::min<u64>(kFillChunk, nwords - off);
-            b.period = 1;
-            fb.push_back(b);
-        }
-    };
-    if (nparts) {
-        add_zero(G.work.as<uint32_t>(G.w_pcnt), nparts);
-        add_zero(G.work.as<uint32_t>(G.w_pcur), nparts);
-    }
     for (int k = 0; k < n; k++) {
         const fj::FillList &fl = colts[k]->fill_h;
         for (int r = 0; r < fl.n; r++)
@@ -827,7 +812,7 @@ fj_status group_launch(fj_ctx *c, ColtGroup &G) {
         FJ_HIP(fj::launch_group_force(3, descs, wpre, G.n, G.wtot, c->stream));   // scatter offsets
     }
     if (G.nparts > 0) {
-        // KM_K32 roots range by range: count, group by range, build, rank
+        // KM_K32 roots range by range: place by slice, build, rank
         fj::PartArgs pa;
         memset(&pa, 0, sizeof(pa));
         pa.descs = descs;
@@ -835,23 +820,18 @@ fj_status group_launch(fj_ctx *c, ColtGroup &G) {
         pa.n = G.npm;
         pa.nblocks = G.nblocks;
         pa.nparts = G.nparts;
-        pa.ipart = G.work.as<uint16_t>(G.w_ipart);
-        pa.irow = G.work.as<uint32_t>(G.w_irow);
-        pa.ikey = G.work.as<uint32_t>(G.w_ikey);
-        pa.ikv = G.work.as<uint32_t>(G.w_ikv);
+        pa.items = (uint32_t)G.wp;
+        pa.poff = G.work.as<uint32_t>(G.w_poff);
         pa.prow = G.work.as<uint32_t>(G.w_prow);
         pa.pkey = G.work.as<uint32_t>(G.w_pkey);
         pa.pkv = G.work.as<uint32_t>(G.w_pkv);
         pa.scnt = G.work.as<uint32_t>(G.w_scnt);
-        pa.pcnt = G.work.as<uint32_t>(G.w_pcnt);
-        pa.pcur = G.work.as<uint32_t>(G.w_pcur);
-        pa.pstart = G.work.as<uint32_t>(G.w_pstart);
         pa.pdist = G.work.as<uint32_t>(G.w_pdist);
         pa.rstart = G.work.as<uint32_t>(G.w_rstart);
         pa.status = c->status_d;
         uint32_t *pbsum = G.work.as<uint32_t>(G.w_pbsum);
-        // few ranges: the passes sum the counts they need (no scan
-        // launches); more: the scans run in one workgroup, or in three
+        // few ranges: the rank pass sums the distinct counts it needs (no
+        // scan launch); more: the scan runs in one workgroup, or in three
         // launches beyond 32,768 ranges
         pa.inline_scan = G.nparts <= 2048 ? 1 : 0;
         // roots that are only probed need no key list: no rank pass, the
@@ -863,12 +843,10 @@ fj_status group_launch(fj_ctx *c, ColtGroup &G) {
                                      : fj::launch_scan_u32(in, out, G.nparts, pbsum, out + G.nparts, c->stream);
         };
         FJ_HIP(fj::launch_part_phase(0, pa, c->stream));
-        FJ_HIP(scan(pa.pcnt, pa.pstart));
         FJ_HIP(fj::launch_part_phase(1, pa, c->stream));
-        FJ_HIP(fj::launch_part_phase(2, pa, c->stream));
         if (G.part_keys) {
             FJ_HIP(scan(pa.pdist, pa.rstart));
-            FJ_HIP(fj::launch_part_phase(3, pa, c->stream));
+            FJ_HIP(fj::launch_part_phase(2, pa, c->stream));
         }
     }
     return FJ_OK;
@@ -1161,7 +1139,7 @@ fj_status fj_filter_lt_batch(fj_ctx *c, int32_t n, const int32_t *const *cols, c
         off[i + 1] = off[i] + align256(((u64)nrows[i] / 1024 + 2) * sizeof(uint32_t));
     }
     FJ_TRY(c->scanb.ensure(off[n] + 256, c->stream));
-    FJ_TRY(zero_status_field(c, offsetof(StatusDev, ftotal), sizeof(c->status_h->ftotal)));
+    // (each non-empty selection's last block stores its total: no clearing)
     {
         // the non-empty selections in one grouped pass of two launches
         const int32_t *gc[FJ_MAX_ATOMS];
@@ -1183,7 +1161,7 @@ fj_status fj_filter_lt_batch(fj_ctx *c, int32_t n, const int32_t *const *cols, c
         FJ_HIP(fj::launch_filter_lt_group(m, gc, gr, gb, go, gs, gt, c->stream));
     }
     FJ_TRY(sync_status(c));
-    for (int i = 0; i < n; i++) counts[i] = (int64_t)c->status_h->ftotal[i];
+    for (int i = 0; i < n; i++) counts[i] = nrows[i] > 0 ? (int64_t)c->status_h->ftotal[i] : 0;
     return FJ_OK;
 }
 

@@ -260,36 +260,33 @@ struct GroupRoot {
 // of np ranges (kK32Part slots each, or the whole map when smaller) is
 // built range by range, each range by one workgroup in LDS.
 constexpr uint32_t kMaxParts = 4096;       // ranges per map on this path
-#ifndef FJ_PART_ITEMS
-#define FJ_PART_ITEMS 1024
-#endif
-constexpr uint32_t kPartItems = FJ_PART_ITEMS;   // items per block of the count and scatter passes
-static_assert(kPartItems % 256 == 0, "items per block: a multiple of the block's threads");
+constexpr uint32_t kPlaceChunk = 1024;     // items a block of the place pass holds at once (4 a thread)
+constexpr uint32_t kMaxPlaceBlocks = 1024; // place blocks per member (one per build thread)
 struct PartMember {
     int desc;                 // the member's ForceArgs in the group
     uint32_t np;              // ranges of its map
     uint32_t plog;            // log2 of the slots per range
     uint32_t part_base;       // its first range in the group's range space
-    uint32_t block_base;      // its first block of the count and scatter passes
+    uint32_t block_base;      // its first block of the place pass
+    uint32_t nb;              // its blocks of the place pass
+    uint32_t ipb;             // items per place block (a multiple of kPlaceChunk; the last takes the rest)
     uint32_t item_base;       // its first item in the group's item space
     uint32_t W;               // its root rows
     unsigned long long slot_base;  // its first slot in the group's slot space (scnt)
+    unsigned long long off_base;   // its (np + 1) x nb offset matrix in poff
 };
 struct PartArgs {
     const ForceArgs *descs;
     const PartMember *mem;
     int n;
-    uint32_t nblocks;         // blocks of the count and scatter passes
+    uint32_t nblocks;         // blocks of the place pass
     uint32_t nparts;          // ranges of every member
+    uint32_t items;           // items of every member (the length of prow, pkey, pkv)
     int set_st;               // no rank pass: the build pass marks each root forced (st = 1, no key list)
-    int inline_scan;          // few ranges: the passes sum the per-range counts they need themselves
-                              // (the scatter pass's block 0 writes pstart), no scan launches
-    uint16_t *ipart;          // per item: its range within its member
-    uint32_t *irow, *ikey, *ikv;   // per item: its row, root key and child-level key (ikv: if kept)
-    uint32_t *pcnt;           // per range: items (counted)
-    uint32_t *pcur;           // per range: scatter cursor
-    uint32_t *pstart;         // nparts + 1: exclusive scan of pcnt (items grouped by range)
-    uint32_t *prow, *pkey, *pkv;   // the items' row, key and child key, grouped by range
+    int inline_scan;          // few ranges: the rank pass sums the distinct counts it needs itself
+    uint32_t *poff;           // per member: poff[p * nb + b] = block b's items in ranges before p
+    uint32_t *prow, *pkey, *pkv;   // the items' row, key and child key: each place block's slice
+                                   // of ipb items, grouped by range within the slice
     uint32_t *scnt;           // per slot of every range (ranges at slot_base): its key's offset count
     uint32_t *pdist;          // per range: distinct keys
     uint32_t *rstart;         // nparts + 1: exclusive scan of pdist (ranks)

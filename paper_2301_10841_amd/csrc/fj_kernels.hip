@@ -876,13 +876,15 @@ __device__ __forceinline__ void group_root_words(const GroupRoot &g) {
 
 // ------------------------------------------- grouped root builds by range
 // A KM_K32 root map is probed within ranges of kK32Part slots (k32_next), so
-// the keys of one range can all be placed by one workgroup: the group's
-// items are counted per range and grouped by range (two passes with one
-// global atomic per block and range, not per item), then each range is
-// built in LDS and written out whole, table words, child segments and
-// offsets, with plain stores; a last pass numbers the keys across ranges.
-// The map needs no clearing beforehand and no per-key device atomics,
-// which on this GPU are performed past the L2 and are slow.
+// the keys of one range can all be placed by one workgroup.  A first pass
+// cuts each member's items into slices, one per block, and writes each slice
+// grouped by range, with the range offsets of every slice in a small matrix
+// (no global atomics, no scan); then one workgroup per range gathers its
+// items (one segment of each slice), builds the range in LDS and writes it
+// out whole: table words, child segments and offsets, with plain stores; a
+// last pass numbers the keys across ranges.  The map needs no clearing
+// beforehand and no per-key device atomics, which on this GPU are performed
+// past the L2 and are slow.
 
 __device__ __forceinline__ int part_member_of_block(const PartArgs &a, uint32_t b) {
     int lo = 0, hi = a.n;   // mem[lo].block_base <= b
@@ -909,52 +911,6 @@ __device__ __forceinline__ uint32_t key_part(const LevelDev &L, uint32_t key, ui
     return (uint32_t)(k32_bucket(mix32(key), L.mask) >> plog);
 }
 
-// Pass 1: items per range.  One block takes kPartItems items of one member.
-__global__ void __launch_bounds__(256) k_part_count(PartArgs a) {
-    __shared__ uint32_t hist[kMaxParts];
-    StatusDev *status = a.status;
-    const int k = part_member_of_block(a, blockIdx.x);
-    const PartMember &m = a.mem[k];
-    const ForceArgs &f = a.descs[m.desc];
-    for (uint32_t p = threadIdx.x; p < m.np; p += 256) hist[p] = 0;
-    __syncthreads();
-    const uint32_t w0 = (blockIdx.x - m.block_base) * kPartItems;
-    const int32_t *kc = f.cols[f.L.kcol[0]];
-    const int32_t *kvc = f.C.kv ? f.cols[f.C.kcol[0]] : nullptr;
-    constexpr int R = (int)(kPartItems / 256);
-    uint32_t row[R], key[R], kv[R];
-    bool ok[R];
-    // the gathers of all the thread's items in flight together
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        const uint32_t w = w0 + r * 256 + threadIdx.x;
-        ok[r] = w < m.W;
-        row[r] = ok[r] ? (f.L.offs ? f.L.offs[w] : w) : 0u;
-        ok[r] = ok[r] && CK(row[r] < f.L.nrows);
-    }
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        key[r] = ok[r] ? (uint32_t)kc[row[r]] : 0u;
-        kv[r] = (ok[r] && kvc) ? (uint32_t)kvc[row[r]] : 0u;
-    }
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        if (!ok[r]) continue;
-        const uint32_t w = w0 + r * 256 + threadIdx.x;
-        const uint32_t part = key_part(f.L, key[r], m.np, m.plog);
-        if (!CK(part < m.np)) continue;
-        const u64 it = (u64)m.item_base + w;
-        a.ipart[it] = (uint16_t)part;
-        a.irow[it] = row[r];
-        a.ikey[it] = key[r];
-        if (kvc) a.ikv[it] = kv[r];
-        atomicAdd(&hist[part], 1u);
-    }
-    __syncthreads();
-    for (uint32_t p = threadIdx.x; p < m.np; p += 256)
-        if (hist[p]) atomicAdd(&a.pcnt[m.part_base + p], hist[p]);
-}
-
 // Sum of in[lo, hi) by the whole block (every thread gets it).
 __device__ __forceinline__ uint32_t block_sum_u32(const uint32_t *in, uint32_t lo, uint32_t hi, uint32_t *red) {
     uint32_t v = 0;
@@ -964,65 +920,114 @@ __device__ __forceinline__ uint32_t block_sum_u32(const uint32_t *in, uint32_t l
     return tot;
 }
 
-// out[i] = add + in[0] + ... + in[i - 1] for i <= n, by the whole block.
-__device__ __forceinline__ void block_scan_u32(const uint32_t *in, uint32_t n, uint32_t add, uint32_t *out,
-                                               uint32_t *red) {
-    uint32_t carry = add;
-    for (uint32_t c = 0; c < n; c += blockDim.x) {
-        const uint32_t i = c + threadIdx.x;
-        const uint32_t v = i < n ? in[i] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan<uint32_t>(v, red, tot);
-        if (i < n) out[i] = carry + ex;
-        carry += tot;
+// A chunk of a place block's items (kPlaceChunk, four a thread): row, root
+// key, child key and range; part = 0xFFFFFFFF for an item past the slice or
+// failing a check.
+struct PlaceItems {
+    uint32_t row[kPlaceChunk / 256], key[kPlaceChunk / 256], kv[kPlaceChunk / 256], part[kPlaceChunk / 256];
+};
+
+__device__ __forceinline__ void place_gather(const ForceArgs &f, const PartMember &m, uint32_t c, uint32_t w1,
+                                             const int32_t *kc, const int32_t *kvc, PlaceItems &it,
+                                             StatusDev *status) {
+    constexpr int R = (int)(kPlaceChunk / 256);
+    bool ok[R];
+    // the gathers of all the thread's items in flight together
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const uint32_t w = c + r * 256 + threadIdx.x;
+        ok[r] = w < w1;
+        it.row[r] = ok[r] ? (f.L.offs ? f.L.offs[w] : w) : 0u;
+        ok[r] = ok[r] && CK(it.row[r] < f.L.nrows);
     }
-    if (threadIdx.x == 0) out[n] = carry;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        it.key[r] = ok[r] ? (uint32_t)kc[it.row[r]] : 0u;
+        it.kv[r] = (ok[r] && kvc) ? (uint32_t)kvc[it.row[r]] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const uint32_t part = ok[r] ? key_part(f.L, it.key[r], m.np, m.plog) : 0xFFFFFFFFu;
+        it.part[r] = (ok[r] && CK(part < m.np)) ? part : 0xFFFFFFFFu;
+    }
 }
 
-// Pass 2 (after the scan of the counts): items grouped by range, each
-// block reserving its share of every range with one atomic.  With few
-// ranges the block takes its member's range starts from the counts
-// itself, and block 0 writes every range's start for the build pass.
-__global__ void __launch_bounds__(256) k_part_scatter(PartArgs a) {
-    __shared__ uint32_t hist[kMaxParts];
-    __shared__ uint32_t pst[kMaxParts + 1];
+// Pass 1: block b of a member takes its items [b ipb, (b + 1) ipb), counts
+// them per range in LDS, writes the slice's range offsets to column b of
+// the member's offset matrix (row p: the slice's items in ranges before p,
+// row np: all of them) and the items themselves into the slice's own
+// positions, grouped by range.  A slice of one chunk keeps its items in
+// registers; a longer one reads them again for the writes.
+__global__ void __launch_bounds__(256) k_part_place(PartArgs a) {
+    __shared__ uint32_t hist[kMaxParts + 1];   // counts, then offsets (then write cursors)
     __shared__ uint32_t red[17];
     StatusDev *status = a.status;
     const int k = part_member_of_block(a, blockIdx.x);
     const PartMember &m = a.mem[k];
-    for (uint32_t p = threadIdx.x; p < m.np; p += 256) hist[p] = 0;
-    const uint32_t *pstart = a.pstart + m.part_base;
-    if (a.inline_scan) {
-        if (blockIdx.x == 0) block_scan_u32(a.pcnt, a.nparts, 0u, a.pstart, red);
-        const uint32_t before = block_sum_u32(a.pcnt, 0, m.part_base, red);
-        block_scan_u32(a.pcnt + m.part_base, m.np, before, pst, red);
-        pstart = pst;
+    const ForceArgs &f = a.descs[m.desc];
+    const uint32_t np = m.np;
+    const uint32_t b = blockIdx.x - m.block_base;
+    const uint32_t w0 = b * m.ipb;                                 // < W: b < nb = ceil(W / ipb)
+    const uint32_t w1 = (uint32_t)min((u64)w0 + m.ipb, (u64)m.W);
+    for (uint32_t p = threadIdx.x; p < np; p += 256) hist[p] = 0;
+    __syncthreads();
+    const int32_t *kc = f.cols[f.L.kcol[0]];
+    const int32_t *kvc = f.C.kv ? f.cols[f.C.kcol[0]] : nullptr;
+    constexpr int R = (int)(kPlaceChunk / 256);
+    const bool one = w1 - w0 <= kPlaceChunk;
+    PlaceItems it;
+    uint32_t loc[R];
+    for (uint32_t c = w0; c < w1; c += kPlaceChunk) {
+        place_gather(f, m, c, w1, kc, kvc, it, status);
+#pragma unroll
+        for (int r = 0; r < R; r++)
+            if (it.part[r] < np) loc[r] = atomicAdd(&hist[it.part[r]], 1u);
     }
     __syncthreads();
-    const uint32_t w0 = (blockIdx.x - m.block_base) * kPartItems;
-    constexpr int R = (int)(kPartItems / 256);
-    uint32_t part[R], loc[R];
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        const uint32_t w = w0 + r * 256 + threadIdx.x;
-        part[r] = w < m.W ? a.ipart[m.item_base + w] : 0xFFFFFFFFu;
-        if (part[r] < m.np) loc[r] = atomicAdd(&hist[part[r]], 1u);
+    // exclusive scan of the counts, in place: each thread its own run of ranges
+    {
+        const uint32_t per = (np + 255) / 256;
+        const uint32_t lo = min(threadIdx.x * per, np), hi = min(lo + per, np);
+        uint32_t v = 0;
+        for (uint32_t p = lo; p < hi; p++) v += hist[p];
+        uint32_t tot;
+        uint32_t ex = block_excl_scan<uint32_t>(v, red, tot);
+        for (uint32_t p = lo; p < hi; p++) {
+            const uint32_t c = hist[p];
+            hist[p] = ex;
+            ex += c;
+        }
+        if (threadIdx.x == 0) hist[np] = tot;
     }
     __syncthreads();
-    for (uint32_t p = threadIdx.x; p < m.np; p += 256)
-        if (hist[p]) hist[p] = atomicAdd(&a.pcur[m.part_base + p], hist[p]);
-    __syncthreads();
-    const bool has_kv = a.descs[m.desc].C.kv != nullptr;
+    uint32_t *O = a.poff + m.off_base;
+    for (uint32_t p = threadIdx.x; p <= np; p += 256) O[(u64)p * m.nb + b] = hist[p];
+    const uint32_t slice = m.item_base + w0;                       // its first position in the item arrays
+    const bool has_kv = kvc != nullptr;
+    if (one) {
 #pragma unroll
-    for (int r = 0; r < R; r++) {
-        if (part[r] >= m.np) continue;
-        const uint32_t w = w0 + r * 256 + threadIdx.x;
-        const u64 it = (u64)m.item_base + w;
-        const u64 pos = (u64)pstart[part[r]] + hist[part[r]] + loc[r];
-        if (!CK(pos < pstart[part[r] + 1])) continue;
-        a.prow[pos] = a.irow[it];
-        a.pkey[pos] = a.ikey[it];
-        if (has_kv) a.pkv[pos] = a.ikv[it];
+        for (int r = 0; r < R; r++) {
+            if (it.part[r] >= np) continue;
+            const uint32_t pos = slice + hist[it.part[r]] + loc[r];
+            if (!CK(pos < m.item_base + w1 && pos < a.items)) continue;
+            a.prow[pos] = it.row[r];
+            a.pkey[pos] = it.key[r];
+            if (has_kv) a.pkv[pos] = it.kv[r];
+        }
+        return;
+    }
+    __syncthreads();   // the offsets are read out; they become the write cursors
+    for (uint32_t c = w0; c < w1; c += kPlaceChunk) {
+        place_gather(f, m, c, w1, kc, kvc, it, status);
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            if (it.part[r] >= np) continue;
+            const uint32_t pos = slice + atomicAdd(&hist[it.part[r]], 1u);
+            if (!CK(pos < m.item_base + w1 && pos < a.items)) continue;
+            a.prow[pos] = it.row[r];
+            a.pkey[pos] = it.key[r];
+            if (has_kv) a.pkv[pos] = it.kv[r];
+        }
     }
 }
 
@@ -1072,12 +1077,27 @@ __device__ __forceinline__ bool wave_slot_add(bool &todo, uint32_t s, uint32_t *
     return false;
 }
 
-// Pass 3: one workgroup per range builds it in LDS: keys and their offset
+// The item arrays' position of item j of a range whose items are segments
+// of the place slices: segment t holds the range's items [sst[t], sst[t+1])
+// from position ssrc[t] on (the last t with sst[t] <= j; empty segments
+// share their start with the next one).
+__device__ __forceinline__ uint32_t range_item_pos(const uint32_t *sst, const uint32_t *ssrc, uint32_t nb,
+                                                   uint32_t j) {
+    uint32_t lo = 0, hi = nb;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (sst[mid] <= j) lo = mid; else hi = mid;
+    }
+    return ssrc[lo] + (j - sst[lo]);
+}
+
+// Pass 2: one workgroup per range builds it in LDS: keys and their offset
 // counts, child segments laid out in the range's own item positions (the
 // empty marker's first), then the range's table words, child lengths,
 // offsets (and the keys beside them) and per-slot counts are written.  The
-// items' rows and keys were gathered by the count pass and moved into range
-// order by the scatter pass, so they are read here contiguously.
+// range's items are one segment of each place slice, found from row lp and
+// lp + 1 of the member's offset matrix; the sum of row lp is the member's
+// items in the ranges before this one, where its child segments start.
 constexpr int kPartBuildThreads = 1024;
 __global__ void __launch_bounds__(kPartBuildThreads) k_part_build(PartArgs a) {
     __shared__ uint32_t keys[kK32Part];
@@ -1085,6 +1105,9 @@ __global__ void __launch_bounds__(kPartBuildThreads) k_part_build(PartArgs a) {
     __shared__ uint32_t fw[kK32Part / kK32Bucket];   // the range's filter words
     __shared__ uint32_t red[17];
     __shared__ uint32_t emp;
+    __shared__ uint32_t sst[kMaxPlaceBlocks + 1];   // the range's items: segment starts
+    __shared__ uint32_t ssrc[kMaxPlaceBlocks];      // and their first positions in the item arrays
+    static_assert(kMaxPlaceBlocks <= kPartBuildThreads, "a thread per place block");
     StatusDev *status = a.status;
     const uint32_t P = blockIdx.x;
     const int k = part_member_of_part(a, P);
@@ -1093,6 +1116,16 @@ __global__ void __launch_bounds__(kPartBuildThreads) k_part_build(PartArgs a) {
     const uint32_t lp = P - m.part_base;
     const uint32_t n = 1u << m.plog;                  // slots of the range
     const u64 s0 = (u64)lp << m.plog;                 // its first slot in the map
+    const uint32_t nb = m.nb;
+    uint32_t seg = 0, before = 0;
+    if (threadIdx.x < nb) {
+        const uint32_t *O = a.poff + m.off_base;
+        const uint32_t t = threadIdx.x;
+        before = O[(u64)lp * nb + t];
+        const uint32_t e = O[(u64)(lp + 1) * nb + t];
+        seg = CK(e >= before) ? e - before : 0u;
+        ssrc[t] = m.item_base + t * m.ipb + before;
+    }
     for (uint32_t s = threadIdx.x; s < n; s += kPartBuildThreads) { keys[s] = kEmpty32; cnt[s] = 0; }
     // the filter's words of this range (the host keeps at least one per range)
     const uint32_t fsh = 2 + f.L.bloom_shift;
@@ -1100,14 +1133,19 @@ __global__ void __launch_bounds__(kPartBuildThreads) k_part_build(PartArgs a) {
     const uint32_t fw0 = (uint32_t)(s0 >> fsh);
     for (uint32_t w = threadIdx.x; w < nfw; w += kPartBuildThreads) fw[w] = 0;
     if (threadIdx.x == 0) emp = 0;
+    uint32_t ni;
+    const uint32_t sx = block_excl_scan<uint32_t>(seg, red, ni);
+    if (threadIdx.x < nb) sst[threadIdx.x] = sx;
+    if (threadIdx.x == 0) sst[nb] = ni;
+    uint32_t base;                                    // the range's first position in the member
+    block_excl_scan<uint32_t>(before, red, base);
     __syncthreads();
-    const uint32_t i0 = a.pstart[P], i1 = a.pstart[P + 1];
-    const uint32_t base = i0 - a.pstart[m.part_base];  // the range's first position in the member
     const bool has_kv = f.C.kv != nullptr;
     // (the loops run whole waves, so that lanes can pool their atomics)
-    const uint32_t i1w = i0 + ((i1 - i0 + kPartBuildThreads - 1) / kPartBuildThreads) * kPartBuildThreads;
-    for (uint32_t i = i0 + threadIdx.x; i < i1w; i += kPartBuildThreads) {
-        const bool live = i < i1;
+    const uint32_t niw = ((ni + kPartBuildThreads - 1) / kPartBuildThreads) * kPartBuildThreads;
+    for (uint32_t j = threadIdx.x; j < niw; j += kPartBuildThreads) {
+        const uint32_t i = j < ni ? range_item_pos(sst, ssrc, nb, j) : 0u;
+        const bool live = j < ni && CK(i < a.items);
         const uint32_t key = live ? a.pkey[i] : kEmpty32;
         if (live && key == kEmpty32) atomicAdd(&emp, 1u);
         uint32_t s = 0xFFFFFFFFu;
@@ -1168,8 +1206,9 @@ __global__ void __launch_bounds__(kPartBuildThreads) k_part_build(PartArgs a) {
     }
     __syncthreads();
     for (uint32_t w = threadIdx.x; w < nfw; w += kPartBuildThreads) f.L.bloom[fw0 + w] = fw[w];
-    for (uint32_t i = i0 + threadIdx.x; i < i1w; i += kPartBuildThreads) {
-        const bool live = i < i1;
+    for (uint32_t j = threadIdx.x; j < niw; j += kPartBuildThreads) {
+        const uint32_t i = j < ni ? range_item_pos(sst, ssrc, nb, j) : 0u;
+        const bool live = j < ni && i < a.items;       // (a failed check was reported above)
         const uint32_t key = live ? a.pkey[i] : kEmpty32;
         uint32_t pos = 0xFFFFFFFFu;
         if (live && key == kEmpty32) pos = atomicAdd(&emp, 1u);
@@ -1188,7 +1227,7 @@ __global__ void __launch_bounds__(kPartBuildThreads) k_part_build(PartArgs a) {
     }
 }
 
-// Pass 4 (after the scan of the distinct counts): the keys of each range
+// Pass 3 (after the scan of the distinct counts): the keys of each range
 // take their ranks in slot order (the empty marker's first) and are listed
 // in the root's key list; a member's first range records its key count.
 __global__ void __launch_bounds__(256) k_part_ranks(PartArgs a) {
@@ -2986,10 +3025,9 @@ hipError_t launch_scan_small_u32(const uint32_t *in, uint32_t *out, uint32_t n, 
 hipError_t launch_part_phase(int phase, const PartArgs &a, hipStream_t s) {
     if (a.n <= 0 || a.nparts == 0) return hipSuccess;
     switch (phase) {
-        case 0: if (a.nblocks) hipLaunchKernelGGL(k_part_count, dim3(a.nblocks), dim3(256), 0, s, a); break;
-        case 1: if (a.nblocks) hipLaunchKernelGGL(k_part_scatter, dim3(a.nblocks), dim3(256), 0, s, a); break;
-        case 2: hipLaunchKernelGGL(k_part_build, dim3(a.nparts), dim3(kPartBuildThreads), 0, s, a); break;
-        case 3: hipLaunchKernelGGL(k_part_ranks, dim3(a.nparts), dim3(256), 0, s, a); break;
+        case 0: if (a.nblocks) hipLaunchKernelGGL(k_part_place, dim3(a.nblocks), dim3(256), 0, s, a); break;
+        case 1: hipLaunchKernelGGL(k_part_build, dim3(a.nparts), dim3(kPartBuildThreads), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(k_part_ranks, dim3(a.nparts), dim3(256), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -118,9 +118,9 @@ hipError_t launch_filter_lt_group(int n, const int32_t *const *cols, const unsig
 hipError_t launch_fq_lens(const LevelDev &L, const uint32_t *fq, uint32_t nh, uint32_t *lens, StatusDev *st,
                           hipStream_t s);
 hipError_t launch_force_phase(int phase, const ForceLaunch &f, hipStream_t s);
-// Grouped builds of KM_K32 roots by key range, phase 0: count items per
-// range; 1: group items by range (after a scan of the counts); 2: build
-// each range; 3: rank the keys (after a scan of the distinct counts).
+// Grouped builds of KM_K32 roots by key range, phase 0: place each slice of
+// items grouped by range; 1: build each range; 2: rank the keys (after a
+// scan of the distinct counts).
 hipError_t launch_part_phase(int phase, const PartArgs &a, hipStream_t s);
 // Exclusive scan of n u32 values in one workgroup (small n), out[n] = total.
 hipError_t launch_scan_small_u32(const uint32_t *in, uint32_t *out, uint32_t n, hipStream_t s);
