@@ -418,8 +418,9 @@ static fj_status colt_fill_list(fj_colt *t, u64 rows) {
     t->fill_words = 0;
     for (int l = 0; l < t->nlev; l++) {
         LevelDev &L = t->lev[l];
-        // (the root's state word is set with the root handle, not filled)
-        if (l > 0) add(t->fill_h, t->fill_words, L.st, n, {0u});
+        // (the root's state word is set with the root handle, not filled; a
+        // root built range by range clears level 1's state words itself)
+        if (l > 0 && !(l == 1 && t->root_part)) add(t->fill_h, t->fill_words, L.st, n, {0u});
         fj::FillList &fl = l == 0 ? t->fill_h : t->fill_lev_h[l];
         u64 &words = l == 0 ? t->fill_words : t->fill_lev_words[l];
         if (l > 0) {
@@ -427,7 +428,9 @@ static fj_status colt_fill_list(fj_colt *t, u64 rows) {
             words = 0;
         }
         if (!L.cnt) continue;  // directly iterated base table
-        add(fl, words, L.cnt, n, {0u});
+        // (the counters serve the force passes, which a root built range
+        // by range does not use)
+        if (!(l == 0 && t->root_part)) add(fl, words, L.cnt, n, {0u});
         if (!L.table || (l == 0 && t->root_part)) continue;
         const u64 ns = t->table_slots[l];
         uint32_t *T = (uint32_t *)L.table;
@@ -691,6 +694,7 @@ fj_status group_prepare(fj_ctx *c, ColtGroup &G, fj_colt *const *colts, int n, u
         m.nb = (uint32_t)((W + m.ipb - 1) / m.ipb);
         m.off_base = noff;
         noff += (u64)(m.np + 1) * m.nb;
+        m.clear_cst = (t->nlev >= 2 && t->lev[1].st) ? 1 : 0;   // left out of its fill list
         nparts += m.np;
         nblocks += m.nb;
         wp += t->nroot;
@@ -801,8 +805,12 @@ fj_status group_launch(fj_ctx *c, ColtGroup &G) {
     const fj::ForceArgs *descs = (const fj::ForceArgs *)meta;
     const u64 *wpre = (const u64 *)(meta + G.o_wpre);
     Timer tm(c, FJ_T_BUILD);
-    FJ_HIP(fj::launch_group_fill((const fj::FillBlock *)(meta + G.o_fill), G.nfill,
-                                 (const fj::GroupRoot *)(meta + G.o_roots), G.n, c->stream));
+    // with nothing to fill and no general-path member, the place pass of
+    // the range builds writes the root words (one launch less)
+    const bool roots_in_place = G.nfill == 0 && G.wtot == 0 && G.nparts > 0 && G.nblocks > 0;
+    if (!roots_in_place)
+        FJ_HIP(fj::launch_group_fill((const fj::FillBlock *)(meta + G.o_fill), G.nfill,
+                                     (const fj::GroupRoot *)(meta + G.o_roots), G.n, c->stream));
     if (G.wtot > 0) {
         FJ_HIP(fj::launch_group_force(0, descs, wpre, G.n, G.wtot, c->stream));   // insert and count
         FJ_HIP(fj::launch_group_force(1, descs, wpre, G.n, G.wtot, c->stream));   // (1, count) per new key
@@ -827,6 +835,10 @@ fj_status group_launch(fj_ctx *c, ColtGroup &G) {
         pa.pkv = G.work.as<uint32_t>(G.w_pkv);
         pa.scnt = G.work.as<uint32_t>(G.w_scnt);
         pa.pdist = G.work.as<uint32_t>(G.w_pdist);
+        if (roots_in_place) {
+            pa.roots = (const fj::GroupRoot *)(meta + G.o_roots);
+            pa.nroots = G.n;
+        }
         pa.rstart = G.work.as<uint32_t>(G.w_rstart);
         pa.status = c->status_d;
         uint32_t *pbsum = G.work.as<uint32_t>(G.w_pbsum);
@@ -1968,11 +1980,12 @@ static fj_status execute_impl(fj_ctx *c, const fj_query *q, const fj_plan *p, fj
         if (!(c->desc_last_dev == c->desc.p && c->desc_last.size() == bytes &&
               memcmp(c->desc_last.data(), c->desc_h, bytes) == 0)) {
             FJ_HIP(hipMemcpyAsync(c->desc.p, c->desc_h, bytes, hipMemcpyHostToDevice, c->stream));
+            // (the staging buffer is rewritten only once this copy is done)
+            FJ_HIP(hipEventRecord(c->desc_done, c->stream));
             c->desc_last.assign((const char *)c->desc_h, (const char *)c->desc_h + bytes);
             c->desc_last_dev = c->desc.p;
         }
     }
-    FJ_HIP(hipEventRecord(c->desc_done, c->stream));
 
     // clear the counters but keep any error a build left for the next check;
     // the host copy mirrors the cleared counters (they are read as bases)

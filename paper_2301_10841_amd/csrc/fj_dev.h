@@ -272,6 +272,7 @@ struct PartMember {
     uint32_t ipb;             // items per place block (a multiple of kPlaceChunk; the last takes the rest)
     uint32_t item_base;       // its first item in the group's item space
     uint32_t W;               // its root rows
+    int clear_cst;            // the build clears level 1's state words of the member's positions
     unsigned long long slot_base;  // its first slot in the group's slot space (scnt)
     unsigned long long off_base;   // its (np + 1) x nb offset matrix in poff
 };
@@ -290,6 +291,8 @@ struct PartArgs {
     uint32_t *scnt;           // per slot of every range (ranges at slot_base): its key's offset count
     uint32_t *pdist;          // per range: distinct keys
     uint32_t *rstart;         // nparts + 1: exclusive scan of pdist (ranks)
+    const GroupRoot *roots;   // nroots > 0: the group's root words, written by blocks after the place blocks
+    int nroots;
     struct StatusDev *status;
 };
 

@@ -483,17 +483,28 @@ __global__ void k_scan_total(T *out, u64 n, const T *total) {
 constexpr int kFilterRows = 4;
 constexpr int kFilterBlock = 256 * kFilterRows;
 
-__device__ __forceinline__ uint32_t filter_bits(const int32_t *col, u64 n, int32_t bound, u64 first, bool vec) {
+// Bit r: row first + r passes (ROWS consecutive rows, a multiple of four,
+// read with 16-byte loads when the column is 16-byte aligned).
+template <int ROWS>
+__device__ __forceinline__ uint32_t filter_bits_n(const int32_t *col, u64 n, int32_t bound, u64 first, bool vec) {
+    static_assert(ROWS % 4 == 0 && ROWS <= 32, "whole 16-byte loads, one bit a row");
     uint32_t bits = 0;
-    if (vec && first + kFilterRows <= n) {
-        const int4 x = *(const int4 *)(col + first);
-        bits = (uint32_t)(x.x < bound) | ((uint32_t)(x.y < bound) << 1) | ((uint32_t)(x.z < bound) << 2) |
-               ((uint32_t)(x.w < bound) << 3);
+    if (vec && first + ROWS <= n) {
+        int4 x[ROWS / 4];
+#pragma unroll
+        for (int q = 0; q < ROWS / 4; q++) x[q] = *(const int4 *)(col + first + 4 * q);
+#pragma unroll
+        for (int q = 0; q < ROWS / 4; q++)
+            bits |= ((uint32_t)(x[q].x < bound) | ((uint32_t)(x[q].y < bound) << 1) |
+                     ((uint32_t)(x[q].z < bound) << 2) | ((uint32_t)(x[q].w < bound) << 3)) << (4 * q);
     } else {
-        for (int r = 0; r < kFilterRows; r++)
+        for (int r = 0; r < ROWS; r++)
             if (first + r < n && col[first + r] < bound) bits |= 1u << r;
     }
     return bits;
+}
+__device__ __forceinline__ uint32_t filter_bits(const int32_t *col, u64 n, int32_t bound, u64 first, bool vec) {
+    return filter_bits_n<kFilterRows>(col, n, bound, first, vec);
 }
 
 __global__ void __launch_bounds__(256) k_filter_count(const int32_t *__restrict__ col, u64 n, int32_t bound, int vec,
@@ -521,7 +532,11 @@ __global__ void __launch_bounds__(256) k_filter_write(const int32_t *__restrict_
 // selection i with bpre[i] <= b < bpre[i + 1] and is its block b - bpre[i].
 // The first launch counts each block's kept rows; in the second, each block
 // sums the counts of its selection's earlier blocks (a few hundred
-// contiguous words) for its place, and writes its rows in order.
+// contiguous words) for its place, and writes its rows in order.  A thread
+// takes sixteen consecutive rows, so that a million-row selection is a
+// few hundred blocks, all resident at once.
+constexpr int kFilterGroupRows = 16;
+constexpr int kFilterGroupBlock = 256 * kFilterGroupRows;
 struct FilterGroup {
     int n;
     const int32_t *col[FJ_MAX_ATOMS];
@@ -544,8 +559,8 @@ __global__ void __launch_bounds__(256) k_filter_count_group(FilterGroup g) {
     __shared__ uint32_t lds[17];
     const int i = filter_member(g, blockIdx.x);
     const uint32_t b = blockIdx.x - g.bpre[i];
-    const u64 first = ((u64)b * 256 + threadIdx.x) * kFilterRows;
-    const uint32_t bits = filter_bits(g.col[i], g.rows[i], g.bound[i], first, g.vec[i]);
+    const u64 first = ((u64)b * 256 + threadIdx.x) * kFilterGroupRows;
+    const uint32_t bits = filter_bits_n<kFilterGroupRows>(g.col[i], g.rows[i], g.bound[i], first, g.vec[i]);
     uint32_t tot;
     block_excl_scan<uint32_t>((uint32_t)__popc(bits), lds, tot);
     if (threadIdx.x == 0) g.bsum[i][b] = tot;
@@ -560,14 +575,13 @@ __global__ void __launch_bounds__(256) k_filter_write_group(FilterGroup g) {
     for (uint32_t k = threadIdx.x; k < b; k += 256) part += bsum[k];
     uint32_t base;
     block_excl_scan<uint32_t>(part, lds, base);
-    const u64 first = ((u64)b * 256 + threadIdx.x) * kFilterRows;
-    const uint32_t bits = filter_bits(g.col[i], g.rows[i], g.bound[i], first, g.vec[i]);
+    const u64 first = ((u64)b * 256 + threadIdx.x) * kFilterGroupRows;
+    const uint32_t bits = filter_bits_n<kFilterGroupRows>(g.col[i], g.rows[i], g.bound[i], first, g.vec[i]);
     uint32_t tot;
     uint32_t pos = base + block_excl_scan<uint32_t>((uint32_t)__popc(bits), lds, tot);
     if (threadIdx.x == 0 && b + 1 == g.bpre[i + 1] - g.bpre[i]) *g.total[i] = base + tot;
     uint32_t *out = g.out[i];
-    for (int r = 0; r < kFilterRows; r++)
-        if (bits & (1u << r)) out[pos++] = (uint32_t)(first + r);
+    for (uint32_t m = bits; m; m &= m - 1) out[pos++] = (uint32_t)(first + __builtin_ctz(m));
 }
 
 // ------------------------------------------------------------------ checks
@@ -958,9 +972,16 @@ __device__ __forceinline__ void place_gather(const ForceArgs &f, const PartMembe
 // row np: all of them) and the items themselves into the slice's own
 // positions, grouped by range.  A slice of one chunk keeps its items in
 // registers; a longer one reads them again for the writes.
+// Blocks after the place blocks: the group's root words, 256 COLTs a block
+// (when no fill launch precedes the pass).
 __global__ void __launch_bounds__(256) k_part_place(PartArgs a) {
     __shared__ uint32_t hist[kMaxParts + 1];   // counts, then offsets (then write cursors)
     __shared__ uint32_t red[17];
+    if (blockIdx.x >= a.nblocks) {
+        const int k = (int)(blockIdx.x - a.nblocks) * 256 + threadIdx.x;
+        if (k < a.nroots) group_root_words(a.roots[k]);
+        return;
+    }
     StatusDev *status = a.status;
     const int k = part_member_of_block(a, blockIdx.x);
     const PartMember &m = a.mem[k];
@@ -1140,6 +1161,9 @@ __global__ void __launch_bounds__(kPartBuildThreads) k_part_build(PartArgs a) {
     uint32_t base;                                    // the range's first position in the member
     block_excl_scan<uint32_t>(before, red, base);
     __syncthreads();
+    if (m.clear_cst)                                  // level 1's tries start unforced
+        for (uint32_t j = threadIdx.x; j < ni; j += kPartBuildThreads)
+            if (CK((u64)base + j < f.C.npos)) f.C.st[base + j] = 0u;
     const bool has_kv = f.C.kv != nullptr;
     // (the loops run whole waves, so that lanes can pool their atomics)
     const uint32_t niw = ((ni + kPartBuildThreads - 1) / kPartBuildThreads) * kPartBuildThreads;
@@ -2921,7 +2945,7 @@ hipError_t launch_filter_lt_group(int n, const int32_t *const *cols, const u64 *
         g.bsum[i] = bsums[i];
         g.total[i] = totals[i];
         g.bpre[i] = (uint32_t)nb;
-        nb += std::max<u64>((rows[i] + kFilterBlock - 1) / kFilterBlock, 1);
+        nb += std::max<u64>((rows[i] + kFilterGroupBlock - 1) / kFilterGroupBlock, 1);
     }
     if (nb > 0x7fffffffu) return hipErrorInvalidValue;
     g.bpre[n] = (uint32_t)nb;
@@ -3025,7 +3049,11 @@ hipError_t launch_scan_small_u32(const uint32_t *in, uint32_t *out, uint32_t n, 
 hipError_t launch_part_phase(int phase, const PartArgs &a, hipStream_t s) {
     if (a.n <= 0 || a.nparts == 0) return hipSuccess;
     switch (phase) {
-        case 0: if (a.nblocks) hipLaunchKernelGGL(k_part_place, dim3(a.nblocks), dim3(256), 0, s, a); break;
+        case 0:
+            if (a.nblocks || a.nroots > 0)
+                hipLaunchKernelGGL(k_part_place, dim3(a.nblocks + (unsigned)(std::max(a.nroots, 0) + 255) / 256),
+                                   dim3(256), 0, s, a);
+            break;
         case 1: hipLaunchKernelGGL(k_part_build, dim3(a.nparts), dim3(kPartBuildThreads), 0, s, a); break;
         case 2: hipLaunchKernelGGL(k_part_ranks, dim3(a.nparts), dim3(256), 0, s, a); break;
         default: return hipErrorInvalidValue;
