@@ -413,3 +413,48 @@ def test_star_rows_written_by_the_probe_kernel(fjm, ctx):
     w = Counter(map(tuple, want["rows"].tolist()))
     g = Counter(map(tuple, cut["rows"].tolist()))
     assert all(g[k] <= w[k] for k in g)
+
+
+@pytest.mark.parametrize("bound", [1 << 30, 500])
+def test_range_build_long_slices(fjm, ctx, bound):
+    # S(y, z) of 1.6M rows is the probed root, built range by range: with all
+    # rows selected its place slices span two 1,024-item chunks each (the
+    # pass reads its items twice), with about half of them one chunk; keys
+    # are skewed (a few keys own many rows) and include the maps' empty
+    # marker (-1).  Rows equal a plain merge of the two relations.
+    _, runner = fjm
+    rng = np.random.default_rng(17)
+    ns, nk = 1_600_000, 100_000
+    ys = np.minimum(rng.zipf(1.5, ns) - 1, nk - 1).astype(np.int32)   # 0 .. nk - 1, skewed
+    ys[rng.choice(ns, 1000, replace=False)] = -1
+    zs = rng.integers(0, 1000, ns).astype(np.int32)
+    nr = 2_000
+    xr = np.arange(nr, dtype=np.int32)
+    yr = rng.integers(1, 5000, nr).astype(np.int32)   # not the hottest key: a bounded result
+    yr[:3] = -1
+    r = datagen.Relation("R", [xr, yr])
+    s = datagen.Relation("S", [ys, zs])
+    dq = datagen.synth.make_query(["x", "y", "z"], [r, s], [(0, (0, 1)), (1, (1, 2))],
+                                  filters=[None, (1, bound)])
+    keep = zs < bound
+    # the expected rows: every R row with every selected S row of its key
+    order = np.argsort(ys[keep], kind="stable")
+    sy, sz = ys[keep][order], zs[keep][order]
+    lo = np.searchsorted(sy, yr, "left")
+    hi = np.searchsorted(sy, yr, "right")
+    cnt = hi - lo
+    want = np.empty((int(cnt.sum()), 3), dtype=np.int32)
+    want[:, 0] = np.repeat(xr, cnt)
+    want[:, 1] = np.repeat(yr, cnt)
+    idx = np.concatenate([np.arange(a, b) for a, b in zip(lo, hi)]) if cnt.sum() else np.zeros(0, np.int64)
+    want[:, 2] = sz[idx]
+    want = runner.sort_rows(want)
+    assert (ys[keep] == -1).any() and 0 < want.shape[0] < 3_000_000
+    _say("long slices", bound, int(keep.sum()), "S rows,", want.shape[0], "result rows")
+    d = runner.DeviceQuery(ctx, dq)
+    plan = d.plan_binary([0, 1], True)
+    got = d.run(plan, materialize=True)
+    assert got["count"] == want.shape[0]
+    assert_same_rows(got["rows"], want)
+    for c in got["colts"]:
+        c.free()
