@@ -130,19 +130,23 @@ struct fj_ctx {
 
 namespace {
 
+// Events around the launches of one kernel class (by_launch: the launches
+// record them themselves, through hipExtLaunchKernel, with no packets of
+// their own in the stream).
 struct Timer {
     fj_ctx *c;
     int cls;
+    bool by_launch;
     hipEvent_t a = nullptr, b = nullptr;
-    Timer(fj_ctx *ctx, int k) : c(ctx), cls(k) {
+    Timer(fj_ctx *ctx, int k, bool by_launch_ = false) : c(ctx), cls(k), by_launch(by_launch_) {
         if (!on()) return;
         a = get();
         b = get();
-        hipEventRecord(a, c->stream);
+        if (!by_launch) hipEventRecord(a, c->stream);
     }
     ~Timer() {
         if (!on()) return;
-        hipEventRecord(b, c->stream);
+        if (!by_launch) hipEventRecord(b, c->stream);
         c->pending.push_back({cls, a, b});
     }
     bool on() const { return c->opt.timing == 2 ? cls == FJ_T_PROBE0 : c->opt.timing != 0; }
@@ -1008,9 +1012,13 @@ fj_status fj_timings(fj_ctx *c, double *ms, uint64_t *launches) {
     FJ_HIP(hipStreamSynchronize(c->stream));
     for (auto &p : c->pending) {
         float m = 0;
-        FJ_HIP(hipEventElapsedTime(&m, p.a, p.b));
-        c->ms[p.cls] += m;
-        c->launches[p.cls] += 1;
+        // (a pair a launch did not record, one that launched nothing, is skipped)
+        if (hipEventElapsedTime(&m, p.a, p.b) == hipSuccess) {
+            c->ms[p.cls] += m;
+            c->launches[p.cls] += 1;
+        } else {
+            (void)hipGetLastError();
+        }
         c->pool.push_back(p.a);
         c->pool.push_back(p.b);
     }
@@ -1750,7 +1758,9 @@ fj_status exec_scan_node(Exec &x, int cover_sub, u64 T, uint32_t) {
         sl.n = n;
         sl.surv_base = surv_base;
         {
-            Timer t(c, FJ_T_PROBE0);
+            Timer t(c, FJ_T_PROBE0, true);
+            sl.t_start = t.a;
+            sl.t_stop = t.b;
             FJ_HIP(fj::launch_scan_probe(sl, c->stream));
         }
         if (x.stats) x.stats->tiles++;

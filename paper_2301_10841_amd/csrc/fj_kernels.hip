@@ -13,6 +13,7 @@
 // No kernel here is a dense contraction, so nothing uses MFMA; every kernel is
 // bound by HBM or L2/MALL traffic and written for coalesced streams, wave64
 // ballots and one atomic per wave.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -3223,24 +3224,24 @@ hipError_t launch_scan_probe(const ScanLaunch &l, hipStream_t s) {
             const u64 items = (u64)G * kFiltWaves;
             a.l0_per = (uint32_t)std::min<u64>((items + res - 1) / res, kListPerMax);
             if (l.count_stats)
-                hipLaunchKernelGGL(k_scan_filter<true>, dim3(G), dim3(kFiltThreads), 0, s, a);
+                hipExtLaunchKernelGGL(k_scan_filter<true>, dim3(G), dim3(kFiltThreads), 0, s, l.t_start, nullptr, 0, a);
             else
-                hipLaunchKernelGGL(k_scan_filter<false>, dim3(G), dim3(kFiltThreads), 0, s, a);
+                hipExtLaunchKernelGGL(k_scan_filter<false>, dim3(G), dim3(kFiltThreads), 0, s, l.t_start, nullptr, 0, a);
             e = hipGetLastError();
             if (e != hipSuccess) return e;
             const unsigned grid = (unsigned)((items + a.l0_per - 1) / a.l0_per);
             if (l.count_stats)
-                hipLaunchKernelGGL(k_scan_rounds<true>, dim3(grid), dim3(256), lds, s, a);
+                hipExtLaunchKernelGGL(k_scan_rounds<true>, dim3(grid), dim3(256), (uint32_t)lds, s, nullptr, l.t_stop, 0, a);
             else
-                hipLaunchKernelGGL(k_scan_rounds<false>, dim3(grid), dim3(256), lds, s, a);
+                hipExtLaunchKernelGGL(k_scan_rounds<false>, dim3(grid), dim3(256), (uint32_t)lds, s, nullptr, l.t_stop, 0, a);
             return hipGetLastError();
         }
     }
     const unsigned grid = (unsigned)std::min<u64>(blocks_for(l.n, kTile), (u64)res);
     if (l.count_stats)
-        hipLaunchKernelGGL(k_scan_probe<true>, dim3(grid), dim3(256), lds, s, a);
+        hipExtLaunchKernelGGL(k_scan_probe<true>, dim3(grid), dim3(256), (uint32_t)lds, s, l.t_start, l.t_stop, 0, a);
     else
-        hipLaunchKernelGGL(k_scan_probe<false>, dim3(grid), dim3(256), lds, s, a);
+        hipExtLaunchKernelGGL(k_scan_probe<false>, dim3(grid), dim3(256), (uint32_t)lds, s, l.t_start, l.t_stop, 0, a);
     return hipGetLastError();
 }
 

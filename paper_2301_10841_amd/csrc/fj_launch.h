@@ -76,6 +76,9 @@ struct ScanLaunch {
     // counters; null: one launch without the filter
     uint32_t *l0_row, *l0_key, *l0_cnt;
     unsigned long long l0_cap;
+    // the node's timing, or null: events the launches record themselves,
+    // at the start of its first kernel and the end of its last
+    hipEvent_t t_start, t_stop;
 };
 
 // The most filter-pass workgroups of a two-launch first node, the list's
