@@ -41,8 +41,9 @@ def log(*a):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 200 for the star, whose step is a fraction of a ms; 20 otherwise)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (default: 20 for the star; 3)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-reps", type=int, default=5)
     ap.add_argument("--seed-rep", type=int, default=0)
@@ -64,6 +65,11 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
+    star = args.workload == "star"
+    if args.steps is None:
+        args.steps = 200 if star else 20
+    if args.warmup is None:
+        args.warmup = 20 if star else 3
     # Python's cyclic garbage collector stays off: one collection of this
     # process's heap (torch's objects) takes tens of milliseconds and lands
     # inside whichever timed step triggers it (reference counting still
