@@ -688,6 +688,7 @@ fj_status group_prepare(fj_ctx *c, ColtGroup &G, fj_colt *const *colts, int n, u
         m.block_base = nblocks;
         m.item_base = (uint32_t)wp;
         m.W = t->nroot;
+        m.keys = t->root_keys ? 1 : 0;
         m.slot_base = nslots;
         nslots += (u64)m.np << m.plog;
         if (wp + t->nroot > 0xFFFFFFFFull) return fail(FJ_ERR_UNSUPPORTED, "grouped roots of 2^32 rows or more");
@@ -850,9 +851,9 @@ fj_status group_launch(fj_ctx *c, ColtGroup &G) {
         // scan launch); more: the scan runs in one workgroup, or in three
         // launches beyond 32,768 ranges
         pa.inline_scan = G.nparts <= 2048 ? 1 : 0;
-        // roots that are only probed need no key list: no rank pass, the
-        // build pass marks each root forced
-        pa.set_st = G.part_keys ? 0 : 1;
+        // roots that are only probed need no key list: the build pass marks
+        // each forced, and the rank pass (run when some root lists its keys)
+        // skips them
         auto scan = [&](const uint32_t *in, uint32_t *out) -> hipError_t {
             if (pa.inline_scan) return hipSuccess;
             return G.nparts <= 32768 ? fj::launch_scan_small_u32(in, out, G.nparts, c->stream)

@@ -273,6 +273,7 @@ struct PartMember {
     uint32_t item_base;       // its first item in the group's item space
     uint32_t W;               // its root rows
     int clear_cst;            // the build clears level 1's state words of the member's positions
+    int keys;                 // its root's keys are listed (the rank pass); else only probed
     unsigned long long slot_base;  // its first slot in the group's slot space (scnt)
     unsigned long long off_base;   // its (np + 1) x nb offset matrix in poff
 };
@@ -283,7 +284,6 @@ struct PartArgs {
     uint32_t nblocks;         // blocks of the place pass
     uint32_t nparts;          // ranges of every member
     uint32_t items;           // items of every member (the length of prow, pkey, pkv)
-    int set_st;               // no rank pass: the build pass marks each root forced (st = 1, no key list)
     int inline_scan;          // few ranges: the rank pass sums the distinct counts it needs itself
     uint32_t *poff;           // per member: poff[p * nb + b] = block b's items in ranges before p
     uint32_t *prow, *pkey, *pkv;   // the items' row, key and child key: each place block's slice

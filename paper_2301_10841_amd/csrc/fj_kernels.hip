@@ -1226,7 +1226,7 @@ __global__ void __launch_bounds__(kPartBuildThreads) k_part_build(PartArgs a) {
             if (emp && CK(base < f.C.npos)) f.C.len[base] = emp;
         }
         a.pdist[P] = ktot + (emp ? 1u : 0u);
-        if (a.set_st && lp == 0) f.L.st[0] = 1u;      // a root only probed: forced, its keys not listed
+        if (!m.keys && lp == 0) f.L.st[0] = 1u;       // a root only probed: forced, its keys not listed
         emp = base;                                   // the empty marker's scatter cursor
     }
     __syncthreads();
@@ -1252,15 +1252,17 @@ __global__ void __launch_bounds__(kPartBuildThreads) k_part_build(PartArgs a) {
     }
 }
 
-// Pass 3 (after the scan of the distinct counts): the keys of each range
-// take their ranks in slot order (the empty marker's first) and are listed
-// in the root's key list; a member's first range records its key count.
+// Pass 3 (after the scan of the distinct counts; roots whose keys are
+// listed): the keys of each range take their ranks in slot order (the empty
+// marker's first) and are listed in the root's key list; a member's first
+// range records its key count.
 __global__ void __launch_bounds__(256) k_part_ranks(PartArgs a) {
     __shared__ uint32_t red[17];
     StatusDev *status = a.status;
     const uint32_t P = blockIdx.x;
     const int k = part_member_of_part(a, P);
     const PartMember &m = a.mem[k];
+    if (!m.keys) return;   // a root only probed (the build marked it forced)
     const ForceArgs &f = a.descs[m.desc];
     const uint32_t lp = P - m.part_base;
     const uint32_t n = 1u << m.plog;
