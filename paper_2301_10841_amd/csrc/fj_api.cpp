@@ -601,7 +601,7 @@ struct ColtGroup {
     u64 wp = 0;
     DevBuf meta;   // descs | wpre | roots | pre | part members | fill blocks
     DevBuf work;   // wslot | cntv | ex | block sums | total | range arrays
-    size_t o_wpre = 0, o_roots = 0, o_pre = 0, o_pmem = 0, o_fill = 0, meta_bytes = 0;
+    size_t o_wpre = 0, o_roots = 0, o_pre = 0, o_pmem = 0, o_fill = 0, o_mop = 0, o_mob = 0, meta_bytes = 0;
     size_t w_cntv = 0, w_ex = 0, w_bsum = 0, w_total = 0;
     size_t w_prow = 0, w_pkey = 0, w_pkv = 0, w_scnt = 0, w_poff = 0, w_pdist = 0, w_rstart = 0, w_pbsum = 0;
     std::vector<char> stage, last;   // host image of meta, and the last one uploaded
@@ -750,7 +750,11 @@ fj_status group_prepare(fj_ctx *c, ColtGroup &G, fj_colt *const *colts, int n, u
     G.o_pre = G.o_roots + align256(sizeof(fj::GroupRoot) * n);
     G.o_pmem = G.o_pre + align256(sizeof(uint32_t) * 2 * n);
     G.o_fill = G.o_pmem + align256(sizeof(fj::PartMember) * std::max<size_t>(pm.size(), 1));
-    G.meta_bytes = G.o_fill + align256(sizeof(fj::FillBlock) * std::max<size_t>(fb.size(), 1));
+    // each range's and each place block's member, so that a workgroup finds
+    // its member with one load
+    G.o_mop = G.o_fill + align256(sizeof(fj::FillBlock) * std::max<size_t>(fb.size(), 1));
+    G.o_mob = G.o_mop + align256(sizeof(uint32_t) * std::max<u64>(nparts, 1));
+    G.meta_bytes = G.o_mob + align256(sizeof(uint32_t) * std::max<u64>(nblocks, 1));
     FJ_TRY(G.meta.ensure(G.meta_bytes, c->stream));
     char *meta = G.meta.as<char>();
     uint32_t *wslot = G.work.as<uint32_t>();
@@ -786,6 +790,13 @@ fj_status group_prepare(fj_ctx *c, ColtGroup &G, fj_colt *const *colts, int n, u
         g.built = t->root_built ? 1 : 0;
     }
     if (!pm.empty()) memcpy(h + G.o_pmem, pm.data(), sizeof(fj::PartMember) * pm.size());
+    {
+        uint32_t *mop = (uint32_t *)(h + G.o_mop), *mob = (uint32_t *)(h + G.o_mob);
+        for (size_t k = 0; k < pm.size(); k++) {
+            for (uint32_t q = 0; q < pm[k].np; q++) mop[pm[k].part_base + q] = (uint32_t)k;
+            for (uint32_t q = 0; q < pm[k].nb; q++) mob[pm[k].block_base + q] = (uint32_t)k;
+        }
+    }
     if (!fb.empty()) memcpy(h + G.o_fill, fb.data(), sizeof(fj::FillBlock) * fb.size());
     if (G.stage != G.last) {
         FJ_HIP(hipStreamSynchronize(c->stream));   // the pinned source may still be in use
@@ -830,6 +841,8 @@ fj_status group_launch(fj_ctx *c, ColtGroup &G) {
         memset(&pa, 0, sizeof(pa));
         pa.descs = descs;
         pa.mem = (const fj::PartMember *)(meta + G.o_pmem);
+        pa.mop = (const uint32_t *)(meta + G.o_mop);
+        pa.mob = (const uint32_t *)(meta + G.o_mob);
         pa.n = G.npm;
         pa.nblocks = G.nblocks;
         pa.nparts = G.nparts;

@@ -280,6 +280,8 @@ struct PartMember {
 struct PartArgs {
     const ForceArgs *descs;
     const PartMember *mem;
+    const uint32_t *mop;      // nparts: each range's member
+    const uint32_t *mob;      // nblocks: each place block's member
     int n;
     uint32_t nblocks;         // blocks of the place pass
     uint32_t nparts;          // ranges of every member

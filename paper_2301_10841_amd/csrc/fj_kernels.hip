@@ -901,23 +901,9 @@ __device__ __forceinline__ void group_root_words(const GroupRoot &g) {
 // beforehand and no per-key device atomics, which on this GPU are performed
 // past the L2 and are slow.
 
-__device__ __forceinline__ int part_member_of_block(const PartArgs &a, uint32_t b) {
-    int lo = 0, hi = a.n;   // mem[lo].block_base <= b
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (a.mem[mid].block_base <= b) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ int part_member_of_part(const PartArgs &a, uint32_t P) {
-    int lo = 0, hi = a.n;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (a.mem[mid].part_base <= P) lo = mid; else hi = mid;
-    }
-    return lo;
-}
+// The member of place block b, and of range P (host-written tables).
+__device__ __forceinline__ int part_member_of_block(const PartArgs &a, uint32_t b) { return (int)a.mob[b]; }
+__device__ __forceinline__ int part_member_of_part(const PartArgs &a, uint32_t P) { return (int)a.mop[P]; }
 
 // The range of a root key: its bucket's range, or the last range for the
 // key equal to the empty marker (kept in the reserved slot).
