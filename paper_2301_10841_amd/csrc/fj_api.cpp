@@ -100,6 +100,7 @@ struct fj_ctx {
     fj_options opt{};
     StatusDev *status_d = nullptr;
     StatusDev *status_h = nullptr;  // pinned
+    uint32_t *ftotal_h = nullptr;   // pinned, mapped: a batch of selections' counts, stored by the GPU
     uint32_t *noalloc = nullptr;    // this device's fixed scratch array (fj_filter_lt_noalloc)
     // per-node execution buffers
     DevBuf front[FJ_MAX_NODES + 1];
@@ -983,6 +984,9 @@ fj_status fj_ctx_create(int device, void *stream, const fj_options *opt, fj_ctx 
     e = hipHostMalloc((void **)&c->status_h, sizeof(StatusDev), hipHostMallocDefault);
     if (e != hipSuccess) { hipFree(c->status_d); delete c; return fail(FJ_ERR_OOM, "pinned status block"); }
     memset(c->status_h, 0, sizeof(StatusDev));
+    e = hipHostMalloc((void **)&c->ftotal_h, sizeof(uint32_t) * FJ_MAX_ATOMS,
+                      hipHostMallocMapped | hipHostMallocCoherent);
+    if (e != hipSuccess) { c->ftotal_h = nullptr; fj_ctx_destroy(c); return fail(FJ_ERR_OOM, "pinned selection counts"); }
     e = hipMemset(c->status_d, 0, sizeof(StatusDev));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) { fj_ctx_destroy(c); return fail(FJ_ERR_HIP, "status block initialisation failed"); }
@@ -1018,6 +1022,7 @@ void fj_ctx_destroy(fj_ctx *c) {
     for (auto e : c->pool) hipEventDestroy(e);
     if (c->status_d) hipFree(c->status_d);
     if (c->status_h) hipHostFree(c->status_h);
+    if (c->ftotal_h) hipHostFree(c->ftotal_h);
     delete c;
 }
 
@@ -1188,14 +1193,16 @@ fj_status fj_filter_lt_batch(fj_ctx *c, int32_t n, const int32_t *const *cols, c
             gb[m] = bounds[i];
             go[m] = outs[i];
             gs[m] = c->scanb.as<uint32_t>(off[i]);
-            gt[m] = &c->status_d->ftotal[i];
+            gt[m] = &c->ftotal_h[i];
             m++;
         }
         Timer t(c, FJ_T_FILTER);
         FJ_HIP(fj::launch_filter_lt_group(m, gc, gr, gb, go, gs, gt, c->stream));
     }
-    FJ_TRY(sync_status(c));
-    for (int i = 0; i < n; i++) counts[i] = nrows[i] > 0 ? (int64_t)c->status_h->ftotal[i] : 0;
+    // the totals land in mapped host memory: no copy, only the wait
+    FJ_HIP(hipStreamSynchronize(c->stream));
+    const volatile uint32_t *ft = c->ftotal_h;
+    for (int i = 0; i < n; i++) counts[i] = nrows[i] > 0 ? (int64_t)ft[i] : 0;
     return FJ_OK;
 }
 

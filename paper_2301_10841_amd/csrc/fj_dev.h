@@ -319,7 +319,6 @@ struct StatusDev {
     uint32_t fq_n[FJ_MAX_ATOMS * kMaxLevels];  // force-queue lengths per (atom, level)
     uint32_t pending;              // entries whose cover had to be forced first
     uint32_t total32;              // 32-bit scan totals
-    uint32_t ftotal[FJ_MAX_ATOMS];  // counts of a batch of selections
     alignas(128) unsigned long long count_part[kCountParts * kPartStride];  // more result tuples
     uint32_t err_line;             // first failed device bounds check (source line)
     uint32_t err_count;            // failed device bounds checks
