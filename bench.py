@@ -112,15 +112,14 @@ def main():
     out = torch.empty((OUT_CAP, dq.nvars), dtype=torch.int32, device="cuda:0")
 
     def step():
-        d.apply_filters()
-        d.rebuild(colts)
+        # the selections and the root builds in one library call, then the join
+        d.select_rebuild(colts)
         return ctx.execute(d.q, plan, colts, out=out)
 
     for _ in range(args.warmup):
         step()
     # which node-0 kernel runs: the key filter's count says
-    d.apply_filters()
-    d.rebuild(colts)
+    d.select_rebuild(colts)
     _, _, st0 = ctx.execute(d.q, plan, colts, out=out, stats=True)
     filtered = int(st0.filtered)
     probe0_lookups = int(st0.per_node()[0]["probe"])

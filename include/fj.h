@@ -231,6 +231,18 @@ fj_status fj_colt_rebuild(fj_ctx *ctx, fj_colt *colt, const fj_relation *rel);
    No COLT may appear twice.  Device scratch for the combined root rows is
    owned by the context and grows when needed. */
 fj_status fj_colt_rebuild_many(fj_ctx *ctx, int32_t n, fj_colt *const *colts, const fj_relation *rels);
+/* Pushed-down selections (Section 2.1) and then the build phase (Section 3.3)
+   over the selected rows, in one call with one host wait between: the
+   selections' counts size the maps.  Selection i keeps the rows
+   r < rels[atoms[i]].nrows of column rels[atoms[i]].cols[cols[i]] whose value
+   is below bounds[i], writing their offsets in row order to
+   rels[atoms[i]].sel (a device buffer of nrows entries, which must be
+   non-null; it is written although the field is const) and their number to
+   rels[atoms[i]].nsel; then as fj_colt_rebuild_many(ctx, n, colts, rels).
+   nsel <= FJ_MAX_ATOMS, each atoms[i] in [0, n) and listed once.  On an error
+   after the selections ran, their counts are already in rels. */
+fj_status fj_select_rebuild(fj_ctx *ctx, int32_t nsel, const int32_t *atoms, const int32_t *cols,
+                            const int32_t *bounds, int32_t n, fj_colt *const *colts, fj_relation *rels);
 void fj_colt_free(fj_colt *colt);
 
 /* --------------------------------------------------------------------- join */

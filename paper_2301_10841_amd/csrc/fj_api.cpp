@@ -1360,6 +1360,32 @@ fj_status fj_colt_rebuild_many(fj_ctx *c, int32_t n, fj_colt *const *colts, cons
     return FJ_OK;
 }
 
+fj_status fj_select_rebuild(fj_ctx *c, int32_t nsel, const int32_t *atoms, const int32_t *cols,
+                            const int32_t *bounds, int32_t n, fj_colt *const *colts, fj_relation *rels) {
+    if (!c || nsel < 0 || nsel > FJ_MAX_ATOMS || n < 0 || (nsel && (!atoms || !cols || !bounds)) ||
+        (n && (!colts || !rels)))
+        return fail(FJ_ERR_ARG, "bad argument");
+    const int32_t *cp[FJ_MAX_ATOMS];
+    int64_t nr[FJ_MAX_ATOMS], cnt[FJ_MAX_ATOMS];
+    uint32_t *outs[FJ_MAX_ATOMS];
+    for (int i = 0; i < nsel; i++) {
+        const int a = atoms[i];
+        if (a < 0 || a >= n) return fail(FJ_ERR_ARG, "selection atom out of range");
+        for (int j = 0; j < i; j++)
+            if (atoms[j] == a) return fail(FJ_ERR_ARG, "an atom is selected twice");
+        const fj_relation &r = rels[a];
+        if (cols[i] < 0 || cols[i] >= r.ncols || r.ncols > FJ_MAX_COLS)
+            return fail(FJ_ERR_ARG, "selection column out of range");
+        if (r.nrows > 0 && !r.sel) return fail(FJ_ERR_ARG, "a selected relation needs its selection buffer");
+        cp[i] = r.cols[cols[i]];
+        nr[i] = r.nrows;
+        outs[i] = const_cast<uint32_t *>(r.sel);
+    }
+    if (nsel) FJ_TRY(fj_filter_lt_batch(c, nsel, cp, nr, bounds, outs, cnt));
+    for (int i = 0; i < nsel; i++) rels[atoms[i]].nsel = cnt[i];
+    return fj_colt_rebuild_many(c, n, colts, rels);
+}
+
 void fj_colt_free(fj_colt *t) {
     if (!t) return;
     hipSetDevice(t->device);

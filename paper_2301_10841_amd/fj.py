@@ -164,6 +164,7 @@ def lib():
         L.fj_build_colt.argtypes = [vp, P(QueryS), vp, C.c_int32, P(Relation), P(vp)]
         L.fj_colt_rebuild.argtypes = [vp, vp, P(Relation)]
         L.fj_colt_rebuild_many.argtypes = [vp, C.c_int32, vp, vp]
+        L.fj_select_rebuild.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_int32, vp, vp]
         L.fj_colt_free.argtypes = [vp]
         L.fj_colt_free.restype = None
         L.fj_execute.argtypes = [vp, P(QueryS), vp, vp, P(C.c_uint64), vp, C.c_uint64,
@@ -196,7 +197,8 @@ def lib():
         L.fj_choose_plan.argtypes = [vp, vp, P(QueryS), vp, C.c_float, C.c_uint64, P(vp), P(C.c_int32), vp]
         for name in ("fj_ctx_create", "fj_timings", "fj_timings_reset", "fj_plan_from_binary",
                      "fj_plan_from_nodes", "fj_plan_get", "fj_filter_lt", "fj_filter_lt_batch", "fj_build_colt",
-                     "fj_colt_rebuild", "fj_colt_rebuild_many", "fj_execute", "fj_execute_factorized",
+                     "fj_colt_rebuild", "fj_colt_rebuild_many", "fj_select_rebuild", "fj_execute",
+                     "fj_execute_factorized",
                      "fj_result_expand", "fj_execute_bushy", "fj_bushy_decompose", "fj_batch_create", "fj_batch_run", "fj_sketch_relation",
                      "fj_greedy_order", "fj_plan_candidates", "fj_candidate_plan", "fj_mlp_create",
                      "fj_mlp_set_params", "fj_mlp_get_params", "fj_mlp_forward", "fj_mlp_gradient",
@@ -374,6 +376,11 @@ class Context:
         self.rebuild_colts_prepared(n, arr, rels)
         for c, sp in zip(colts, specs):
             c.keep = (sp[0], sp[1])
+
+    def select_rebuild_prepared(self, nsel: int, atoms, cols, bounds, n: int, arr, rels):
+        """fj_select_rebuild with every array already marshalled: the
+        selections' counts land in rels[atoms[i]].nsel."""
+        _check(lib().fj_select_rebuild(self.h, nsel, atoms, cols, bounds, n, arr, rels))
 
     def rebuild_colts_prepared(self, n: int, arr, rels):
         """As rebuild_colts, with the handle and relation arrays already

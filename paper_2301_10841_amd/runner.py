@@ -29,6 +29,7 @@ class DeviceQuery:
         self.nsel: List[int] = [0] * len(dq.atoms)
         self._flt = None      # selections' marshalled arguments (the buffers are fixed)
         self._rb = None       # (COLT handles, handle array, relation array) of the last rebuild
+        self._sr = None       # the same for select_rebuild, with the selections' arrays
         self.apply_filters()
 
     def apply_filters(self):
@@ -100,6 +101,29 @@ class DeviceQuery:
                 if self.sel[a] is not None:
                     rels[a].nsel = int(self.nsel[a])
         self.ctx.rebuild_colts_prepared(n, self._rb[1], self._rb[2])
+
+    def select_rebuild(self, colts):
+        """The query's selections and then one grouped rebuild of its COLTs,
+        in one library call with one host wait (apply_filters() followed by
+        rebuild(colts)).  The arrays are marshalled once per set of COLTs."""
+        import ctypes as C
+        n = len(colts)
+        key = tuple(c.h for c in colts)
+        if self._sr is None or self._sr[0] != key:
+            specs = [(self.atom_cols(a), self.sel[a], self.nsel[a]) for a in range(n)]
+            rels = (fj.Relation * n)(*[fj._relation(*sp) for sp in specs])
+            for c, sp in zip(colts, specs):
+                c.keep = (sp[0], sp[1])
+            fa = [a for a in range(n) if self.dq.filters[a] is not None]
+            m = max(len(fa), 1)
+            atoms = (C.c_int32 * m)(*fa)
+            cols = (C.c_int32 * m)(*[int(self.dq.filters[a][0]) for a in fa])
+            bounds = (C.c_int32 * m)(*[int(self.dq.filters[a][1]) for a in fa])
+            self._sr = (key, (C.c_void_p * n)(*key), rels, atoms, cols, bounds, fa)
+        _, arr, rels, atoms, cols, bounds, fa = self._sr
+        self.ctx.select_rebuild_prepared(len(fa), atoms, cols, bounds, n, arr, rels)
+        for a in fa:
+            self.nsel[a] = int(rels[a].nsel)
 
     def run(self, plan: fj.Plan, materialize: bool = True, cap: Optional[int] = None,
             stats: bool = False, colts=None):

@@ -139,3 +139,46 @@ def test_empty_marker_keys(fjm, ctxs):
     want = oracle_run(dq, oracle_plan_binary(dq, [0, 1, 2], True), counters=False)
     assert (want["rows"][:, 0] == -1).any()
     _all_three(fjm, ctxs, dq, want["rows"])
+
+
+def test_select_rebuild_matches_two_calls(fjm, ctxs):
+    # fj_select_rebuild (the selections and the grouped rebuild in one call)
+    # gives the same selection counts, rows and lookup counts as
+    # fj_filter_lt_batch followed by fj_colt_rebuild_many, step after step
+    fj, runner = fjm
+    ctx = ctxs["filter"]
+    dq = datagen.star_schema(datagen.seed_for(2, 14), n_fact=300_007, n_dim=30_000)
+    dims = [tuple(dq.relations[i + 1].cols) for i in range(4)]
+    want = closed.star_rows(dq.relations[0].cols, dims, [10] * 4)
+    d = runner.DeviceQuery(ctx, dq)
+    plan = d.plan_binary([0, 1, 2, 3, 4], True)
+    colts = d.build(plan)
+    import torch
+    out = torch.empty((want.shape[0] + 5, dq.nvars), dtype=torch.int32, device="cuda:0")
+    two = list(d.nsel)
+    for rep in range(3):
+        d.nsel = [0] * len(d.nsel)
+        d.select_rebuild(colts)
+        assert d.nsel == two, rep
+        cnt, written, st = ctx.execute(d.q, plan, colts, out=out, stats=True)
+        assert cnt == written == want.shape[0]
+        assert_same_rows(runner.sort_rows(out[:written].cpu().numpy()), want)
+        d.apply_filters()
+        d.rebuild(colts)
+        _, _, st2 = ctx.execute(d.q, plan, colts, stats=True)
+        assert st.per_node() == st2.per_node()
+    # argument errors are refused before any device work
+    import ctypes as C
+    key = tuple(c.h for c in colts)
+    arr = (C.c_void_p * len(key))(*key)
+    rels = (fj.Relation * len(colts))(*[fj._relation(d.atom_cols(a), d.sel[a], d.nsel[a])
+                                         for a in range(len(colts))])
+    for atoms, cols in [([1, 1], [1, 1]), ([7], [1]), ([1], [5])]:
+        at = (C.c_int32 * len(atoms))(*atoms)
+        co = (C.c_int32 * len(cols))(*cols)
+        bo = (C.c_int32 * len(atoms))(*([10] * len(atoms)))
+        with pytest.raises(fj.FJError) as ex:
+            ctx.select_rebuild_prepared(len(atoms), at, co, bo, len(colts), arr, rels)
+        assert ex.value.status == -1, (atoms, cols)
+    for c in colts:
+        c.free()
