@@ -2488,8 +2488,9 @@ __global__ void __launch_bounds__(256, FJ_SCAN_WAVES) k_scan_rounds(ScanArgs a) 
 // probes them, many per thread at once, and runs the later lookups.  What
 // bounds such a node is the chain of dependent memory round trips each
 // wave makes; this pass makes none beyond its stream, which it keeps one
-// tile ahead.  The filter (64 KB) leaves LDS for one 1,024-thread workgroup
-// per CU; tiles are 8 rows per thread.
+// tile ahead.  The filter takes 64 KB of LDS and the pass 64 registers a
+// thread, so that two 1,024-thread workgroups share a CU; tiles are 8 rows
+// per thread.
 
 __device__ __forceinline__ bool bloom_pass(const uint32_t *filt, const ScanLookup &L, uint32_t key) {
     if (key == kEmpty32) return true;   // kept in the reserved slot, not in the filter
@@ -2516,7 +2517,7 @@ __device__ __forceinline__ uint32_t filt_row(const ScanArgs &a, uint32_t tile0, 
 }
 
 template <bool STATS>
-__global__ void __launch_bounds__(kFiltThreads, 1) k_scan_filter(ScanArgs a) {
+__global__ void __launch_bounds__(kFiltThreads, 8) k_scan_filter(ScanArgs a) {
     StatusDev *status = a.status;
     __shared__ uint4 filt4[kBloomWords / 4];
     const uint32_t *filt = (const uint32_t *)filt4;
